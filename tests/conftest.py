@@ -1,0 +1,32 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: large inputs; minutes of CPU time")
+
+
+def pytest_collection_modifyitems(config, items):
+    # GPU tests are collected after the CPU tests of the same run.
+    items.sort(key=lambda it: 1 if it.get_closest_marker("gpu") else 0)
+
+
+@pytest.fixture(scope="session")
+def oracle_mod():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+@pytest.fixture(scope="session")
+def sg():
+    import scenegen
+    scenegen.build(force=False)
+    return scenegen

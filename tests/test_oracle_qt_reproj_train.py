@@ -1,0 +1,350 @@
+"""Pins of the oracle's quadtree (Sec. 3.1), reprojection (Sec. 3.3, interpolated
+frames) and training step (Sec. 3.3: MSE, Adam) against hand-computed cases,
+closed forms, brute force and finite differences."""
+import numpy as np
+import pytest
+
+
+def parity_image(W, H, region):
+    """Black image with colour (x mod 2, y mod 2, 0) inside region (x0, y0, x1, y1)."""
+    img = np.zeros((H, W, 3), np.float32)
+    x0, y0, x1, y1 = region
+    ys, xs = np.mgrid[y0:y1, x0:x1]
+    img[y0:y1, x0:x1, 0] = xs % 2
+    img[y0:y1, x0:x1, 1] = ys % 2
+    return img
+
+
+def test_uniform_image_all_level_zero(oracle_mod):
+    W, H = 200, 130
+    img = np.full((H, W, 3), 0.4, np.float32)
+    N = np.ones(W * H, np.uint32)
+    mask, level, hist, D = oracle_mod.quadtree(img, N, W, H, base=64)
+    assert np.all(mask == 0) and np.all(level == 0) and np.all(D == 0)
+    assert list(hist) == [4 * 3, 0, 0, 0]  # 4 x 3 base tiles, all occupied level-0 leaves
+
+
+def test_step_edge_on_tile_boundary_never_splits(oracle_mod):
+    """Corners of every node lie on one side of an edge at x = 64, so D = 0."""
+    W, H = 192, 128
+    img = np.zeros((H, W, 3), np.float32)
+    img[:, 64:] = (1.0, 1.0, 1.0)
+    N = np.ones(W * H, np.uint32)
+    mask, level, hist, D = oracle_mod.quadtree(img, N, W, H, base=64)
+    assert np.all(mask == 0) and np.all(level == 0)
+    # the same edge at x = 70 lies inside tile 1 and splits it
+    img2 = np.zeros((H, W, 3), np.float32)
+    img2[:, 70:] = 1.0
+    mask2, _, _, _ = oracle_mod.quadtree(img2, N, W, H, base=64)
+    assert mask2[1] & 1
+
+
+def _corner_block_case():
+    """2x2 base tiles of 64 px; only the bottom-right level-2 node of tile 0
+    (x, y in [48, 64)) holds a parity pattern."""
+    W = H = 128
+    img = parity_image(W, H, (48, 48, 64, 64))
+    return img, W, H
+
+
+def test_hand_computed_relaxation_k1_vs_k2(oracle_mod):
+    """Hand-derived level maps. Tile 0: level 3 in cells (6..7, 6..7), level 2 in
+    the rest of its bottom-right quadrant, level 1 elsewhere. One relaxation
+    raises the facing quadrants of tiles 1 and 2 to level 2 (rest level 1) but
+    leaves tile 3 at level 0, next to level-2 cells; the second relaxation
+    lifts tile 3 to level 1. This fixes k."""
+    img, W, H = _corner_block_case()
+    N = np.ones(W * H, np.uint32)
+    t0 = np.ones((8, 8), int)
+    t0[4:, 4:] = 2
+    t0[6:, 6:] = 3
+    t1 = np.ones((8, 8), int)
+    t1[4:, 0:4] = 2
+    t2 = np.ones((8, 8), int)
+    t2[0:4, 4:] = 2
+    for k, t3v, hist in ((1, 0, [1, 9, 11, 4]), (2, 1, [0, 13, 11, 4])):
+        mask, level, h, _ = oracle_mod.quadtree(img, N, W, H, base=64, k_relax=k)
+        want = np.zeros((16, 16), int)
+        want[0:8, 0:8] = t0
+        want[0:8, 8:16] = t1
+        want[8:16, 0:8] = t2
+        want[8:16, 8:16] = t3v
+        np.testing.assert_array_equal(level, want)
+        assert list(h) == hist
+    # tile masks after k = 2: tile 0 root + quadrant 3 + its child 3 (bit 5 + 4*3 + 3)
+    mask, _, _, _ = oracle_mod.quadtree(img, N, W, H, base=64, k_relax=2)
+    assert mask[0] == (1 | 1 << (1 + 3) | 1 << (5 + 4 * 3 + 3))
+    assert mask[1] == (1 | 1 << (1 + 2))      # bottom-left quadrant of tile 1
+    assert mask[2] == (1 | 1 << (1 + 1))      # top-right quadrant of tile 2
+    assert mask[3] == 1
+
+
+def test_temporal_limit_one_level_per_frame(oracle_mod):
+    """A strong tile starting from an all-level-0 history reaches level 1, 2, 3
+    in three frames (Sec. 3.1: one level per frame)."""
+    W = H = 64
+    img = parity_image(W, H, (0, 0, 64, 64))
+    N = np.ones(W * H, np.uint32)
+    prev = np.zeros(1, np.uint32)
+    seen = []
+    for _ in range(4):
+        mask, level, _, _ = oracle_mod.quadtree(img, N, W, H, base=64, prev_mask=prev)
+        seen.append(int(level.max()))
+        assert level.min() == level.max()
+        prev = mask
+    assert seen == [1, 2, 3, 3]
+    # without history the first frame goes straight to level 3
+    _, level, _, _ = oracle_mod.quadtree(img, N, W, H, base=64)
+    assert level.min() == 3
+
+
+def test_hysteresis_band(oracle_mod):
+    """D strictly between tau_merge and tau_split keeps the previous state."""
+    W = H = 64
+    img = np.zeros((H, W, 3), np.float32)
+    img[63, 63] = (0.14, 0.0, 0.0)  # one corner differs: D = 3 * 0.14 / 6 = 0.07
+    N = np.ones(W * H, np.uint32)
+    mask, _, _, D = oracle_mod.quadtree(img, N, W, H, base=64, tau_split=0.10, tau_merge=0.05, k_relax=0)
+    assert abs(D[0, 0] - 0.07) < 1e-7
+    assert mask[0] == 0                                         # unsplit stays unsplit
+    m2, _, _, _ = oracle_mod.quadtree(img, N, W, H, base=64, tau_split=0.10, tau_merge=0.05, k_relax=0,
+                                      prev_mask=np.array([1], np.uint32))
+    assert m2[0] & 1                                            # split stays split
+    m3, _, _, _ = oracle_mod.quadtree(img, N, W, H, base=64, tau_split=0.06, tau_merge=0.05, k_relax=0)
+    assert m3[0] & 1
+    m4, _, _, _ = oracle_mod.quadtree(img, N, W, H, base=64, tau_split=0.10, tau_merge=0.08, k_relax=0,
+                                      prev_mask=np.array([1], np.uint32))
+    assert not (m4[0] & 1)
+
+
+def _brute_topdown(img, W, H, B, tau):
+    """Recursive top-down refinement without history (k = 0)."""
+    Tw, Th = (W + B - 1) // B, (H + B - 1) // B
+    cs = B // 8
+    Cw, Ch = (W + cs - 1) // cs, (H + cs - 1) // cs
+    level = np.zeros((Ch, Cw), int)
+    masks = []
+
+    def D(x0, y0, s):
+        if x0 >= W or y0 >= H:
+            return 0.0
+        x1, y1 = min(x0 + s - 1, W - 1), min(y0 + s - 1, H - 1)
+        cs_ = [img[y, x].astype(np.float64) for (x, y) in ((x0, y0), (x1, y0), (x0, y1), (x1, y1))]
+        return sum(np.linalg.norm(cs_[a] - cs_[b]) for a in range(4) for b in range(a + 1, 4)) / 6
+
+    def visit(lvl, x0, y0, bitbase, nx, ny, tile_mask):
+        s = B >> lvl
+        split = lvl <= 2 and D(x0, y0, s) > tau
+        if split:
+            if lvl == 0:
+                bit = 0
+            elif lvl == 1:
+                bit = 1 + nx + 2 * ny
+            else:
+                bit = 5 + 4 * ((nx >> 1) + 2 * (ny >> 1)) + (nx & 1) + 2 * (ny & 1)
+            tile_mask[0] |= 1 << bit
+            h = s // 2
+            for cy in range(2):
+                for cx in range(2):
+                    visit(lvl + 1, x0 + cx * h, y0 + cy * h, 0, 2 * nx + cx, 2 * ny + cy, tile_mask)
+        else:
+            for y in range(y0, min(y0 + s, Ch * cs), cs):
+                for x in range(x0, min(x0 + s, Cw * cs), cs):
+                    level[y // cs, x // cs] = lvl
+
+    for ty in range(Th):
+        for tx in range(Tw):
+            tm = [0]
+            visit(0, tx * B, ty * B, 0, 0, 0, tm)
+            masks.append(tm[0])
+    return np.array(masks, np.uint32), level
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_topdown_brute_force_base8(oracle_mod, seed):
+    """Exhaustive node evaluation on a tiny base size (8 px -> 1 px cells),
+    ragged frame edges included."""
+    rng = np.random.default_rng(seed)
+    W, H = 37, 29
+    img = (rng.random((H, W, 3)) * (rng.random((H, W, 1)) < 0.3)).astype(np.float32)
+    N = np.ones(W * H, np.uint32)
+    for tau in (0.05, 0.2, 0.5):
+        mask, level, _, _ = oracle_mod.quadtree(img, N, W, H, base=8, tau_split=tau, tau_merge=tau / 2, k_relax=0)
+        bm, bl = _brute_topdown(img, W, H, 8, tau)
+        np.testing.assert_array_equal(mask, bm)
+        np.testing.assert_array_equal(level, bl)
+
+
+def test_quadtree_structural_invariants(oracle_mod):
+    """Random images: masks are trees (a split node's parent is split), levels
+    equal the leaf depth of the mask, the histogram counts occupied leaves, and
+    two relaxations leave the level map consistent with the masks."""
+    rng = np.random.default_rng(5)
+    W, H = 300, 170
+    img = rng.random((H, W, 3)).astype(np.float32)
+    img[:, :120] = 0.5
+    N = (rng.random(W * H) < 0.7).astype(np.uint32)
+    prev = None
+    for _ in range(3):
+        mask, level, hist, _ = oracle_mod.quadtree(img, N, W, H, base=64, prev_mask=prev)
+        for m in mask:
+            m = int(m)
+            for q in range(4):
+                if m & (1 << (1 + q)):
+                    assert m & 1
+                for r in range(4):
+                    if m & (1 << (5 + 4 * q + r)):
+                        assert m & (1 << (1 + q))
+        assert hist.sum() > 0
+        prev = mask
+    # level-1 neighbour differences after k = 2 from a history: count only
+    d = np.abs(np.diff(level.astype(int), axis=1))
+    assert d.max() <= 3
+
+
+# ---------------------------------------------------------------------------
+# reprojection
+
+def test_reproject_identity(oracle_mod):
+    W, H = 33, 17
+    rng = np.random.default_rng(0)
+    rgb = rng.random((W * H, 3)).astype(np.float32)
+    d1 = rng.random(W * H).astype(np.float32)
+    out, src, _ = oracle_mod.reproject(rgb, d1, np.zeros((4, 4)), W, H)
+    np.testing.assert_array_equal(src, np.arange(W * H))
+    np.testing.assert_array_equal(out, rgb)
+
+
+@pytest.mark.parametrize("k,m", [(3, 0), (-5, 2), (0, -4), (7, 7)])
+def test_reproject_screen_translation(oracle_mod, k, m):
+    """M = translation by (2k/W, -2m/H) in NDC at any depth: the source of pixel
+    (x, y) is (x + k, y + m); outside the frame -> -1 and own colour kept."""
+    W, H = 40, 24
+    rng = np.random.default_rng(1)
+    rgb = rng.random((W * H, 3)).astype(np.float32)
+    d1 = rng.random(W * H).astype(np.float32)
+    mmi = np.zeros((4, 4))
+    mmi[0, 3] = 2.0 * k / W
+    mmi[1, 3] = -2.0 * m / H
+    out, src, _ = oracle_mod.reproject(rgb, d1, mmi, W, H)
+    for y in range(H):
+        for x in range(W):
+            p = y * W + x
+            sx, sy = x + k, y + m
+            if 0 <= sx < W and 0 <= sy < H:
+                assert src[p] == sy * W + sx
+                np.testing.assert_array_equal(out[p], rgb[sy * W + sx])
+            else:
+                assert src[p] == -1
+                np.testing.assert_array_equal(out[p], rgb[p])
+
+
+def test_reproject_matches_full_unproject_project(oracle_mod, sg):
+    """The M - I gather equals explicit unprojection through VP_t^-1 and
+    projection through VP_r (scene camera path), away from rounding ties."""
+    sc = sg.Scene("c2_1080p", width=320, height=180, num_tris=150)
+    vp_r, vp_t = sc.camera(2), sc.camera(3)
+    W, H = 320, 180
+    d1 = np.random.default_rng(2).uniform(0.85, 0.99, W * H).astype(np.float32)
+    rgb = np.random.default_rng(3).random((W * H, 3)).astype(np.float32)
+    mmi = oracle_mod.m_minus_i(vp_r, vp_t)
+    _, src, mg = oracle_mod.reproject(rgb, d1, mmi, W, H)
+    su, sv = oracle_mod.reproject_full(d1, vp_r, vp_t, W, H)
+    qx, qy = np.floor(su), np.floor(sv)
+    inside = (qx >= 0) & (qx < W) & (qy >= 0) & (qy < H)
+    want = np.where(inside, qy * W + qx, -1)
+    ok = mg > 1e-6
+    assert ok.mean() > 0.99
+    np.testing.assert_array_equal(src[ok], want[ok].astype(np.int32))
+    # the motion is real: most pixels move
+    assert (src != np.arange(W * H)).mean() > 0.5
+
+
+# ---------------------------------------------------------------------------
+# training
+
+def _kink_free_batch(dims, w, rng, B):
+    """Inputs whose pre-activations stay away from 0 (so the loss is smooth)."""
+    import oracle
+    Ws, bs = oracle.split_params(dims, w)
+    xs = []
+    while len(xs) < B:
+        x = rng.normal(size=dims[0])
+        z1 = Ws[0] @ x + bs[0]
+        h1 = np.maximum(z1, 0)
+        z2 = Ws[1] @ h1 + bs[1]
+        h2 = np.maximum(z2, 0)
+        z3 = Ws[2] @ h2 + bs[2]
+        if min(np.abs(z1).min(), np.abs(z2).min(), np.abs(z3).min()) > 1e-3:
+            xs.append(x)
+    return np.array(xs)
+
+
+def test_gradient_central_differences(oracle_mod):
+    dims = (16, 12, 10, 3)
+    rng = np.random.default_rng(0)
+    n = 12 * 16 + 12 + 10 * 12 + 10 + 3 * 10 + 3
+    w = rng.normal(scale=0.4, size=n)
+    w[-3:] = 0.5  # mostly live outputs
+    x = _kink_free_batch(dims, w, rng, 6)
+    y = rng.random((6, 3))
+    loss, g = oracle_mod.loss_grad(dims, w, x, y)
+    h = 1e-6
+    for i in rng.choice(n, 60, replace=False):
+        wp, wm = w.copy(), w.copy()
+        wp[i] += h
+        wm[i] -= h
+        fd = (oracle_mod.loss_grad(dims, wp, x, y)[0] - oracle_mod.loss_grad(dims, wm, x, y)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(g[i])) + 1e-9, (i, fd, g[i])
+
+
+def test_loss_value_closed_form(oracle_mod):
+    """Zero weights: f = relu(b3), loss = mean((relu(b3) - y)^2)."""
+    dims = (16, 4, 4, 3)
+    n = 4 * 16 + 4 + 16 + 4 + 12 + 3
+    w = np.zeros(n)
+    w[-3:] = (0.5, -1.0, 0.25)
+    x = np.random.default_rng(0).random((5, 16))
+    y = np.random.default_rng(1).random((5, 3))
+    loss, g = oracle_mod.loss_grad(dims, w, x, y)
+    f = np.array([0.5, 0.0, 0.25])
+    assert abs(loss - ((f - y) ** 2).mean()) < 1e-15
+    # only the live output biases receive gradient: d/db3 = 2 mean_k (f - y) / 3
+    np.testing.assert_allclose(g[-3:], [2 * (0.5 - y[:, 0]).sum() / 15, 0.0, 2 * (0.25 - y[:, 2]).sum() / 15],
+                               atol=1e-15)
+    assert np.all(g[:-3] == 0)
+
+
+def test_adam_first_step_closed_form(oracle_mod):
+    """Step 1 with zero moments: w -= lr g / (|g| + eps)."""
+    g = np.array([0.3, -2.0, 1e-4, 0.0, 5.0])
+    w = np.array([1.0, 2.0, 3.0, 4.0, 5.0])
+    m = np.zeros(5)
+    v = np.zeros(5)
+    w0 = w.copy()
+    oracle_mod.adam(w, m, v, g, lr=1e-2, t=1)
+    np.testing.assert_allclose(w, w0 - 1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-15)
+    # a constant gradient keeps bias-corrected moments at g and g^2
+    for t in range(2, 6):
+        w_prev = w.copy()
+        oracle_mod.adam(w, m, v, g, lr=1e-2, t=t)
+        np.testing.assert_allclose(w, w_prev - 1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-9, atol=1e-15)
+
+
+def test_overfit_tiny_batch(oracle_mod, sg):
+    """Adam on MSE drives the loss on a tiny batch below 1e-6."""
+    dims = (16, 32, 32, 3)
+    Ws, bs = sg.init_mlp(dims, out_bias=0.2)
+    w = oracle_mod.Mlp(Ws, bs).params()
+    rng = np.random.default_rng(4)
+    x = np.zeros((4, 16))
+    x[:, :5] = rng.random((4, 5))
+    y = rng.uniform(0.1, 0.9, (4, 3))
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    loss = None
+    for t in range(1, 3001):
+        loss, g = oracle_mod.loss_grad(dims, w, x, y)
+        oracle_mod.adam(w, m, v, g, lr=3e-3, t=t)
+    loss, _ = oracle_mod.loss_grad(dims, w, x, y)
+    assert loss < 1e-6

@@ -1,0 +1,268 @@
+/*
+ * starnt.h - C ABI of libstarnt.so, the MI355X (gfx950) per-pixel hot path of
+ * STAR-NT neural order-independent transparency (Tsopouridis et al., arXiv
+ * 2606.16747, "STAR-NT: Spatiotemporal Acceleration of Real-Time Neural
+ * Transparency Rendering").
+ *
+ * Input is a frame's transparent fragments as per-pixel lists in CSR form (the
+ * role the paper's rasterisation passes play). The calls are:
+ *
+ *   starnt_features   passes 1-3 (Sec. 3, Fig. 1): nearest layer at full
+ *                     resolution, second layer on the pass-2 grid, tail
+ *                     statistics and the five network features on the pass-3
+ *                     grid (Sec. 3.2-3.3)
+ *   starnt_infer      tail-colour network f(x) at full resolution over the
+ *                     bilinearly upscaled pass-3 features (Sec. 3.2-3.3)
+ *   starnt_composite  eq (3), C = C_exact,2 + T2 f(x) + prod(1-a) C_b, with the
+ *                     upscaled pass-2 layer; or the exact A-buffer composite
+ *                     (eq (1) after a per-pixel sort; the paper's ground truth)
+ *   starnt_quadtree   screen-tile quadtree update from the composite (Sec. 3.1)
+ *                     and the pass scales of the next frame (Sec. 3.2, eq (4))
+ *   starnt_reproject  interpolated frame by depth reprojection (Sec. 3.3)
+ *   starnt_train_step one MSE + Adam step of the tail network (Sec. 3.3)
+ *
+ * Conventions for every call:
+ *  - Memory: all array arguments are DEVICE pointers owned by the caller unless
+ *    marked "host". The library keeps no pointer after a call returns. No call
+ *    allocates device memory; scratch comes from a caller workspace whose size
+ *    starnt_workspace_size() reports.
+ *  - Streams: `stream` is a hipStream_t (NULL = the default stream). Every call
+ *    only enqueues work on that stream and returns without synchronising; the
+ *    outputs are valid once the stream reaches that point.
+ *  - Status: each call returns STARNT_OK or an error code. Arguments are
+ *    validated on the host before anything is enqueued (EINVAL). Faults of the
+ *    data itself (depth outside [0,1], alpha outside [0,1], a list longer than
+ *    the declared maximum) are found by the kernels, which OR flags into a
+ *    caller-provided device error word; read it after synchronising and pass it
+ *    to starnt_check(). starnt_last_error() gives a message for the calling
+ *    thread's most recent failure.
+ *  - Pixels are row-major, p = y * width + x, y = 0 the top row.
+ */
+#ifndef STARNT_H
+#define STARNT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define STARNT_OK 0
+#define STARNT_EINVAL 1       /* bad argument: NULL, size, dtype, capacity     */
+#define STARNT_ERANGE 2       /* data outside the documented domain            */
+#define STARNT_ENOMEM 3       /* workspace smaller than starnt_workspace_size  */
+#define STARNT_EHIP 4         /* a HIP launch or runtime call failed           */
+#define STARNT_EUNSUPPORTED 5 /* valid but not implemented combination         */
+
+/* device error word flags (OR-ed by kernels) */
+#define STARNT_DERR_DEPTH 1u  /* a depth outside [0,1] or NaN                  */
+#define STARNT_DERR_ALPHA 2u  /* an alpha outside [0,1] or NaN                 */
+#define STARNT_DERR_COUNT 4u  /* a list longer than max_per_pixel              */
+
+/* ---- element types -------------------------------------------------------- */
+#define STARNT_F32 0
+#define STARNT_F16 1
+#define STARNT_BF16 2
+#define STARNT_FP8 3          /* OCP E4M3 (max 448), per-layer scales          */
+
+/* ---- fragment lists --------------------------------------------------------
+ * Pixel p owns fragments offsets[p] .. offsets[p+1]-1 (offsets[0] = 0,
+ * non-decreasing, offsets[P] = num_frags). Colour is straight (not
+ * premultiplied) RGBA. (depth, prim) must be unique within a pixel: the order
+ * of a pixel's fragments is ascending depth with ties broken by ascending
+ * primitive id, so results do not depend on the order of a list. */
+typedef struct {
+  int32_t width, height;
+  const uint32_t* offsets;  /* [P+1]                                         */
+  const float* depth;       /* [F]   NDC depth, 0 = near plane, 1 = far      */
+  const void* rgba;         /* [F][4] float (STARNT_F32) or half (STARNT_F16) */
+  int32_t rgba_dtype;       /* STARNT_F32 | STARNT_F16                       */
+  const uint32_t* prim;     /* [F]   primitive id (read on depth ties only)  */
+  uint64_t num_frags;       /* F (< 2^32)                                    */
+  uint32_t max_per_pixel;   /* declared bound on list length (>= 1)          */
+} starnt_frags;
+
+/* ---- frame schedule (device resident, 64 bytes) ----------------------------
+ * Grid sizes of passes 2 and 3 for the frame being rendered, and what the last
+ * quadtree update measured. starnt_quadtree overwrites it with the next frame's
+ * grids (eq (4)); starnt_sched_init() sets it explicitly. Grid W_s x H_s
+ * samples full-resolution pixel floor((2i+1) W / (2 W_s)) along each axis. */
+typedef struct {
+  int32_t w2, h2, w3, h3;   /* pass-2 / pass-3 grids, 1 <= w <= width etc.  */
+  uint32_t hist[4];         /* occupied quadtree leaves per level 0..3       */
+  float wbar, s2, s3;       /* complexity index and the two pass scales      */
+  uint32_t frames;          /* quadtree updates so far                        */
+  uint32_t pad[4];
+} starnt_sched;
+
+/* ---- per-pixel intermediates written by starnt_features ------------------- */
+typedef struct {
+  int32_t width, height; /* frame size (must match the fragment lists)          */
+  float* d1;          /* [P]    depth of layer 1; 1.0 when the list is empty    */
+  float* layer1;      /* [P][4] (a1 c1r, a1 c1g, a1 c1b, a1), zero when empty   */
+  uint32_t* count;    /* [P]    list length N                                   */
+  float* layer2;      /* [P][4] capacity; (a2 c2, a2) at pass-2 grid samples,
+                         row-major over the w2 x h2 grid                        */
+  float* tail;        /* [P][8] capacity; per pass-3 grid sample:
+                         x = (N, t_tail, Ct_r, Ct_g, Ct_b), then A, 0, 0, where
+                         over sorted positions 3..N: A = sum a,
+                         t_tail = prod (1 - a), Ct = sum a c / A (0 if A = 0)   */
+  uint32_t* sel;      /* optional [P][2]: global index of layers 1 and 2
+                         (0xFFFFFFFF when absent); NULL to skip                 */
+  uint32_t* err;      /* device error word (flags OR-ed in; caller zeroes it)   */
+} starnt_feats;
+
+/* ---- tail-colour network ----------------------------------------------------
+ * Three dense layers, ReLU after each (Sec. 3.3; the paper's widths are 32, 16;
+ * any h1, h2 <= 64 with in = 16, out = 3 here). Weights are FP32 masters in
+ * the layout W_l[out][in] row-major; `dtype` selects the arithmetic:
+ * STARNT_F32 (VALU FP32), STARNT_BF16 (bf16 operands on the matrix cores, FP32
+ * accumulate), STARNT_FP8 (E4M3 operands with per-layer scales, FP32
+ * accumulate). Input x = (N, t_tail, Ct_rgb) padded with 11 zeros. */
+typedef struct {
+  int32_t in, h1, h2, out;
+  int32_t dtype;
+  const float *W1, *b1, *W2, *b2, *W3, *b3;
+  const float* fp8_scales;  /* host [6]: sa1, sw1, sa2, sw2, sa3, sw3 (FP8 only):
+                               layer l computes (sum q(a/sa) q(W/sw)) sa sw + b  */
+} starnt_mlp;
+
+/* ---- composite modes ---------------------------------------------------- */
+#define STARNT_MODE_LEARNED 0 /* f = tail_rgb from starnt_infer                 */
+#define STARNT_MODE_F0 1      /* f = 0                                          */
+#define STARNT_MODE_FAVG 2    /* f = Ct (1 - t_tail)                            */
+#define STARNT_MODE_EXACT 3   /* exact A-buffer: per-pixel sort, eq (1)         */
+
+/* ---- quadtree parameters (Sec. 3.1) --------------------------------------- */
+typedef struct {
+  int32_t base;        /* base tile size in px, multiple of 8 (paper: 16)       */
+  float tau_split;     /* an unsplit node splits when D > tau_split            */
+  float tau_merge;     /* a split node merges when D < tau_merge (< tau_split) */
+  int32_t k_relax;     /* balance relaxation iterations (paper: 2), 0..8        */
+} starnt_qt_params;
+
+/* ---- training (Sec. 3.3: MSE, Adam) -------------------------------------- */
+typedef struct {
+  int32_t in, h1, h2, out;  /* in = 16, out = 3, h1, h2 in {16, 32, 48, 64}    */
+  int32_t dtype;            /* STARNT_F32 (check mode) | STARNT_BF16            */
+  float* params;            /* [n] FP32 masters: W1[h1][in], b1[h1], W2[h2][h1],
+                               b2[h2], W3[out][h2], b3[out]                     */
+  float* m;                 /* [n] Adam first moment                            */
+  float* v;                 /* [n] Adam second moment                           */
+  float* grad;              /* [n] written: gradient of this step's loss        */
+} starnt_train;
+
+typedef struct {
+  float lr, beta1, beta2, eps;
+  int32_t step;             /* 1-based Adam step (bias correction)             */
+} starnt_adam;
+
+/* workspace kinds for starnt_workspace_size */
+#define STARNT_WS_QUADTREE 1
+#define STARNT_WS_TRAIN 2
+
+/* ======================================================================== */
+
+/* Passes 1-3 over the fragment lists (Sec. 3; tail statistics and features
+ * Sec. 3.3). Every pixel gets d1, layer1 and count. Pixels sampled by the
+ * pass-2 grid of `sched` also get layer2, pixels sampled by the pass-3 grid get
+ * a tail record. sched == NULL means both grids at full resolution. Layer
+ * selection is by (depth, prim); the tail sums are exact fixed-point sums, so
+ * every output is independent of the order within a list. */
+int starnt_features(const starnt_frags* frags, const starnt_sched* sched, const starnt_feats* out,
+                    void* stream);
+
+/* Tail colour at full resolution (Sec. 3.3): for each pixel with count >= 3,
+ * x is the bilinear upscale (half-pixel centres, clamp to edge) of the tail
+ * records on the pass-3 grid of `sched` (NULL = full resolution) and
+ * tail_rgb[p] = f(x); tail_rgb[p] = 0 where count < 3. tail_rgb is [P][3]. */
+int starnt_infer(const starnt_mlp* mlp, const float* tail, const uint32_t* count, const starnt_sched* sched,
+                 int32_t width, int32_t height, float* tail_rgb, void* stream);
+
+/* Final colour rgb [P][3].
+ * MODE_LEARNED / F0 / FAVG (eq (3), Sec. 3.3): with layer 2 and x upscaled
+ *   from their grids, and the full-resolution count gating them (no layer 2
+ *   where N < 2, no tail where N < 3),
+ *   C = a1 c1 + (1 - a1) a2 c2 + T2 f + T2 t_tail C_b, T2 = (1 - a1)(1 - a2).
+ *   Reads feats->layer1, layer2, tail, count (frame size from feats);
+ *   `frags` may be NULL.
+ * MODE_EXACT: sorts each list by (depth, prim) and composites front to back,
+ *   C = sum_j a_j c_j prod_{k<j} (1 - a_k) + prod_j (1 - a_j) C_b (eq (1));
+ *   optional fstar [P][3] receives the exact tail colour, sorted positions
+ *   3..N composited alone. Reads only `frags` (+ feats->err for flags).
+ * bg is a host float[3]. */
+int starnt_composite(const starnt_frags* frags, const starnt_feats* feats, const float* tail_rgb,
+                     const starnt_sched* sched, const float* bg, int32_t mode, float* rgb, float* fstar,
+                     void* stream);
+
+/* Quadtree update from a real frame's composite rgb [P][3] and counts [P]
+ * (Sec. 3.1): per base tile, the corner-sample distance D of every internal
+ * node (mean of the six pairwise Euclidean RGB distances of its corners),
+ * top-down split/merge with hysteresis against prev_mask (NULL on the first
+ * frame: split iff D > tau_split, no temporal limit), leaf levels limited to
+ * +-1 from prev_mask, then k_relax raise-only relaxations
+ * r(c) = max(L(c), max over 4-neighbours L(n) - 1) on the global grid of
+ * base/8-px cells, each followed by re-deriving masks (a node at level l is
+ * split iff some cell under it has r > l).
+ * Outputs: mask [Tw*Th] 21-bit split masks (bit 0 root, bits 1-4 level 1,
+ * bits 5-20 level 2, Morton order), level [Cw*Ch] leaf level per cell,
+ * sched->hist (occupied leaves per level), sched->wbar = sum l N_l / sum N_l,
+ * sched->s2, s3 by eq (4) and the next frame's grids. The update reads and
+ * writes `sched` on the device, so frames chain without host round trips.
+ * Workspace: starnt_workspace_size(STARNT_WS_QUADTREE, W, H, base). */
+int starnt_quadtree(const float* rgb, const uint32_t* count, int32_t width, int32_t height,
+                    const starnt_qt_params* params, const uint32_t* prev_mask, uint32_t* mask, uint8_t* level,
+                    starnt_sched* sched, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Interpolated frame (Sec. 3.3): for each pixel p, X = (x_ndc, y_ndc, d1_prev[p],
+ * 1) with x_ndc = (2px+1)/W - 1, y_ndc = 1 - (2py+1)/H; h = X + (M - I) X with
+ * M = VP_prev VP_cur^-1; source q = (floor((u+1) W / 2), floor((1-v) H / 2)),
+ * (u, v) = (h_x, h_y) / h_w. rgb_out[p] = rgb_prev[q], src[p] = q; outside the
+ * frame or h_w <= 0: src[p] = -1 and rgb_out[p] = rgb_prev[p].
+ * m_minus_i is a host float[16], row-major, acting on column vectors.
+ * src may be NULL. */
+int starnt_reproject(const float* rgb_prev, const float* d1_prev, int32_t width, int32_t height,
+                     const float* m_minus_i, float* rgb_out, int32_t* src, void* stream);
+
+/* One training step on a batch (Sec. 3.3): loss = mean over batch x 3 of
+ * (f(x) - y)^2 (ReLU derivative 0 at 0), gradient into t->grad, then Adam on
+ * the FP32 masters with bias correction for step hp->step.
+ * x [batch][16] float features, y [batch][3] float targets, loss [1] float
+ * written on the device. Gradient sums over the batch use a fixed reduction
+ * order, so a step is bitwise reproducible.
+ * Workspace: starnt_workspace_size(STARNT_WS_TRAIN, batch, h1, h2). */
+int starnt_train_step(const starnt_train* t, const float* x, const float* y, int32_t batch,
+                      const starnt_adam* hp, float* loss, void* workspace, size_t workspace_bytes,
+                      void* stream);
+
+/* ---- host helpers (no GPU work) ------------------------------------------ */
+
+/* Set sched to grids (ceil(s2 W), ceil(s2 H), ceil(s3 W), ceil(s3 H)), each at
+ * least 1, on the device (a one-thread kernel on `stream`; hist etc. zeroed). */
+int starnt_sched_init(starnt_sched* sched, int32_t width, int32_t height, double s2, double s3, void* stream);
+
+/* wbar = sum l N_l / sum N_l over l = 0..3 (0 when all zero) (Sec. 3.2) */
+double starnt_wbar(const uint32_t* hist4);
+/* eq (4): s2 = clamp(2^(wbar - 2.2), 0.25, 1), s3 = clamp(2^(wbar - 3.0), 0.25, 1) */
+void starnt_pass_scales(double wbar, double* s2, double* s3);
+/* grid size max(1, min(n, ceil(s n))) */
+int32_t starnt_grid_dim(int32_t n, double s);
+
+/* bytes of workspace a call needs (a, b, c as listed at each call) */
+size_t starnt_workspace_size(int32_t kind, int64_t a, int64_t b, int64_t c);
+
+/* status for a device error word read back after the stream synchronised */
+int starnt_check(uint32_t err_word);
+
+/* message of the calling thread's last failure ("" if none) */
+const char* starnt_last_error(void);
+
+/* library version, e.g. "starnt 0.1 gfx950" */
+const char* starnt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STARNT_H */

@@ -1,0 +1,301 @@
+"""Python binding of libstarnt.so: the MI355X (gfx950) per-pixel hot path of
+STAR-NT neural order-independent transparency (arXiv 2606.16747).
+
+Argument marshalling only: torch tensors provide device memory and the stream;
+every step runs in the library's HIP kernels. The functions carry the C names
+(starnt_features, starnt_infer, starnt_composite, starnt_quadtree,
+starnt_reproject, starnt_train_step) and raise StarntError on a non-zero
+status. The library must be built (`python -m paper_2606_16747_amd.build` or
+__graft_entry__.build()); importing without it fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstarnt.so")
+
+F32, F16, BF16, FP8 = 0, 1, 2, 3
+MODE_LEARNED, MODE_F0, MODE_FAVG, MODE_EXACT = 0, 1, 2, 3
+WS_QUADTREE, WS_TRAIN = 1, 2
+DERR_DEPTH, DERR_ALPHA, DERR_COUNT = 1, 2, 4
+STATUS = {0: "OK", 1: "EINVAL", 2: "ERANGE", 3: "ENOMEM", 4: "EHIP", 5: "EUNSUPPORTED"}
+
+_P = ctypes.c_void_p
+
+
+class StarntError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Frags(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("offsets", _P), ("depth", _P),
+                ("rgba", _P), ("rgba_dtype", ctypes.c_int32), ("prim", _P), ("num_frags", ctypes.c_uint64),
+                ("max_per_pixel", ctypes.c_uint32)]
+
+
+class Sched(ctypes.Structure):
+    _fields_ = [("w2", ctypes.c_int32), ("h2", ctypes.c_int32), ("w3", ctypes.c_int32), ("h3", ctypes.c_int32),
+                ("hist", ctypes.c_uint32 * 4), ("wbar", ctypes.c_float), ("s2", ctypes.c_float),
+                ("s3", ctypes.c_float), ("frames", ctypes.c_uint32), ("pad", ctypes.c_uint32 * 4)]
+
+
+class Feats(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("d1", _P), ("layer1", _P),
+                ("count", _P), ("layer2", _P), ("tail", _P), ("sel", _P), ("err", _P)]
+
+
+class Mlp(ctypes.Structure):
+    _fields_ = [("in_", ctypes.c_int32), ("h1", ctypes.c_int32), ("h2", ctypes.c_int32), ("out", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("W1", _P), ("b1", _P), ("W2", _P), ("b2", _P), ("W3", _P), ("b3", _P),
+                ("fp8_scales", ctypes.POINTER(ctypes.c_float))]
+
+
+class QtParams(ctypes.Structure):
+    _fields_ = [("base", ctypes.c_int32), ("tau_split", ctypes.c_float), ("tau_merge", ctypes.c_float),
+                ("k_relax", ctypes.c_int32)]
+
+
+class Train(ctypes.Structure):
+    _fields_ = [("in_", ctypes.c_int32), ("h1", ctypes.c_int32), ("h2", ctypes.c_int32), ("out", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("params", _P), ("m", _P), ("v", _P), ("grad", _P)]
+
+
+class Adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("step", ctypes.c_int32)]
+
+
+assert ctypes.sizeof(Sched) == 64
+
+EXPORTS = ("starnt_features", "starnt_infer", "starnt_composite", "starnt_quadtree", "starnt_reproject",
+           "starnt_train_step", "starnt_sched_init", "starnt_wbar", "starnt_pass_scales", "starnt_grid_dim",
+           "starnt_workspace_size", "starnt_check", "starnt_last_error", "starnt_version")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libstarnt.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.starnt_features.argtypes = [ctypes.POINTER(Frags), _P, ctypes.POINTER(Feats), _P]
+    lib.starnt_infer.argtypes = [ctypes.POINTER(Mlp), _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]
+    lib.starnt_composite.argtypes = [ctypes.POINTER(Frags), ctypes.POINTER(Feats), _P, _P,
+                                     ctypes.POINTER(ctypes.c_float), ctypes.c_int32, _P, _P, _P]
+    lib.starnt_quadtree.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(QtParams), _P, _P, _P,
+                                    _P, _P, ctypes.c_size_t, _P]
+    lib.starnt_reproject.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), _P,
+                                     _P, _P]
+    lib.starnt_train_step.argtypes = [ctypes.POINTER(Train), _P, _P, ctypes.c_int32, ctypes.POINTER(Adam), _P, _P,
+                                      ctypes.c_size_t, _P]
+    lib.starnt_sched_init.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _P]
+    lib.starnt_wbar.restype = ctypes.c_double
+    lib.starnt_wbar.argtypes = [ctypes.POINTER(ctypes.c_uint32)]
+    lib.starnt_pass_scales.restype = None
+    lib.starnt_pass_scales.argtypes = [ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double)]
+    lib.starnt_grid_dim.restype = ctypes.c_int32
+    lib.starnt_grid_dim.argtypes = [ctypes.c_int32, ctypes.c_double]
+    lib.starnt_workspace_size.restype = ctypes.c_size_t
+    lib.starnt_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
+    lib.starnt_check.argtypes = [ctypes.c_uint32]
+    lib.starnt_last_error.restype = ctypes.c_char_p
+    lib.starnt_version.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc):
+    if rc != 0:
+        raise StarntError(rc, lib.starnt_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        return ctypes.c_void_p(t.data_ptr())
+    return t
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, dtype, device):
+    return torch.as_tensor(t).to(device=device, dtype=dtype).contiguous()
+
+
+# ---------------------------------------------------------------------------
+# device-side containers (torch tensors) and their C views
+
+class DeviceFrags:
+    """A frame's fragment lists in device memory (see starnt_frags)."""
+
+    def __init__(self, offsets, depth, rgba, prim, width, height, max_per_pixel, device="cuda"):
+        self.width, self.height = int(width), int(height)
+        self.offsets = _dev(np.asarray(offsets).view(np.int32), torch.int32, device)
+        self.depth = _dev(depth, torch.float32, device)
+        rgba = np.asarray(rgba)
+        if rgba.dtype == np.float16:
+            self.rgba = torch.from_numpy(rgba.view(np.int16)).to(device).contiguous()
+            self.rgba_dtype = F16
+        else:
+            self.rgba = _dev(rgba, torch.float32, device)
+            self.rgba_dtype = F32
+        self.prim = _dev(np.asarray(prim).view(np.int32), torch.int32, device)
+        self.num_frags = int(self.depth.shape[0])
+        self.max_per_pixel = int(max_per_pixel)
+        self._c = self.c()
+
+    @classmethod
+    def from_frame(cls, fr, max_per_pixel=None, device="cuda"):
+        mx = int(max_per_pixel or max(1, int(fr.stats.get("max_count", 1)), 1))
+        return cls(fr.offsets, fr.depth, fr.rgba, fr.prim, fr.width, fr.height, mx, device)
+
+    def c(self):
+        return Frags(self.width, self.height, self.offsets.data_ptr(), self.depth.data_ptr(), self.rgba.data_ptr(),
+                     self.rgba_dtype, self.prim.data_ptr(), self.num_frags, self.max_per_pixel)
+
+    @property
+    def bytes_streamed(self):
+        """Algorithmic bytes of one full-resolution pass: offsets + depth + RGBA."""
+        per = 8 if self.rgba_dtype == F16 else 16
+        return 4 * (self.width * self.height + 1) + self.num_frags * (4 + per)
+
+
+class FeatBuffers:
+    """Outputs of starnt_features (full-resolution capacity)."""
+
+    def __init__(self, width, height, device="cuda", with_sel=False):
+        P = int(width) * int(height)
+        self.width, self.height = int(width), int(height)
+        self.d1 = torch.empty(P, dtype=torch.float32, device=device)
+        self.layer1 = torch.empty(P, 4, dtype=torch.float32, device=device)
+        self.count = torch.empty(P, dtype=torch.int32, device=device)
+        self.layer2 = torch.zeros(P, 4, dtype=torch.float32, device=device)
+        self.tail = torch.zeros(P, 8, dtype=torch.float32, device=device)
+        self.sel = torch.empty(P, 2, dtype=torch.int32, device=device) if with_sel else None
+        self.err = torch.zeros(1, dtype=torch.int32, device=device)
+        self._c = self.c()
+
+    def c(self):
+        return Feats(self.width, self.height, self.d1.data_ptr(), self.layer1.data_ptr(), self.count.data_ptr(),
+                     self.layer2.data_ptr(), self.tail.data_ptr(),
+                     self.sel.data_ptr() if self.sel is not None else None, self.err.data_ptr())
+
+
+def new_sched(width, height, s2=1.0, s3=1.0, device="cuda", stream=None):
+    """A device schedule (64 bytes) initialised to the given pass scales."""
+    t = torch.zeros(16, dtype=torch.int32, device=device)
+    starnt_sched_init(t, width, height, s2, s3, stream)
+    return t
+
+
+def read_sched(t):
+    """Host copy of a device schedule as a dict (synchronises)."""
+    raw = t.detach().cpu().numpy().astype(np.int32)
+    s = Sched.from_buffer_copy(raw.tobytes())
+    return {"w2": s.w2, "h2": s.h2, "w3": s.w3, "h3": s.h3, "hist": list(s.hist), "wbar": s.wbar, "s2": s.s2,
+            "s3": s.s3, "frames": s.frames}
+
+
+class DeviceMlp:
+    """FP32 master weights of the tail network on the device."""
+
+    def __init__(self, Ws, bs, dtype=F32, fp8_scales=None, device="cuda"):
+        self.Ws = [_dev(w, torch.float32, device) for w in Ws]
+        self.bs = [_dev(b, torch.float32, device) for b in bs]
+        self.dims = (self.Ws[0].shape[1], self.Ws[0].shape[0], self.Ws[1].shape[0], self.Ws[2].shape[0])
+        self.set_dtype(dtype, fp8_scales)
+
+    def set_dtype(self, dtype, fp8_scales=None):
+        self.dtype = dtype
+        self._scales = None if fp8_scales is None else (ctypes.c_float * 6)(*[float(v) for v in fp8_scales])
+        W, b = self.Ws, self.bs
+        self._c = Mlp(self.dims[0], self.dims[1], self.dims[2], self.dims[3], dtype, W[0].data_ptr(),
+                      b[0].data_ptr(), W[1].data_ptr(), b[1].data_ptr(), W[2].data_ptr(), b[2].data_ptr(),
+                      self._scales)
+        return self
+
+
+# ---------------------------------------------------------------------------
+# the C calls
+
+def starnt_features(frags: DeviceFrags, sched, feats: FeatBuffers, stream=None):
+    _check(lib.starnt_features(ctypes.byref(frags._c), _ptr(sched), ctypes.byref(feats._c), _stream(stream)))
+
+
+def starnt_infer(mlp: DeviceMlp, tail, count, sched, width, height, tail_rgb, stream=None):
+    _check(lib.starnt_infer(ctypes.byref(mlp._c), _ptr(tail), _ptr(count), _ptr(sched), int(width), int(height),
+                            _ptr(tail_rgb), _stream(stream)))
+
+
+def starnt_composite(frags, feats, tail_rgb, sched, bg, mode, rgb, fstar=None, stream=None):
+    bgc = (ctypes.c_float * 3)(*[float(v) for v in bg])
+    _check(lib.starnt_composite(ctypes.byref(frags._c) if frags is not None else None,
+                                ctypes.byref(feats._c) if feats is not None else None, _ptr(tail_rgb), _ptr(sched),
+                                bgc, int(mode), _ptr(rgb), _ptr(fstar), _stream(stream)))
+
+
+def starnt_quadtree(rgb, count, width, height, params: QtParams, prev_mask, mask, level, sched, workspace,
+                    stream=None):
+    _check(lib.starnt_quadtree(_ptr(rgb), _ptr(count), int(width), int(height), ctypes.byref(params),
+                               _ptr(prev_mask), _ptr(mask), _ptr(level), _ptr(sched), _ptr(workspace),
+                               workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def starnt_reproject(rgb_prev, d1_prev, width, height, m_minus_i, rgb_out, src=None, stream=None):
+    m = np.asarray(m_minus_i, np.float32).ravel()
+    mc = (ctypes.c_float * 16)(*[float(v) for v in m])
+    _check(lib.starnt_reproject(_ptr(rgb_prev), _ptr(d1_prev), int(width), int(height), mc, _ptr(rgb_out), _ptr(src),
+                                _stream(stream)))
+
+
+def starnt_train_step(train: Train, x, y, batch, adam: Adam, loss, workspace, stream=None):
+    _check(lib.starnt_train_step(ctypes.byref(train), _ptr(x), _ptr(y), int(batch), ctypes.byref(adam), _ptr(loss),
+                                 _ptr(workspace), workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def starnt_sched_init(sched, width, height, s2, s3, stream=None):
+    _check(lib.starnt_sched_init(_ptr(sched), int(width), int(height), float(s2), float(s3), _stream(stream)))
+
+
+def starnt_wbar(hist4):
+    h = (ctypes.c_uint32 * 4)(*[int(v) for v in hist4])
+    return float(lib.starnt_wbar(h))
+
+
+def starnt_pass_scales(wbar):
+    a, b = ctypes.c_double(), ctypes.c_double()
+    lib.starnt_pass_scales(float(wbar), ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def starnt_grid_dim(n, s):
+    return int(lib.starnt_grid_dim(int(n), float(s)))
+
+
+def starnt_workspace_size(kind, a, b, c):
+    return int(lib.starnt_workspace_size(int(kind), int(a), int(b), int(c)))
+
+
+def starnt_check(err_word):
+    _check(lib.starnt_check(int(err_word) & 0xFFFFFFFF))
+
+
+def starnt_version():
+    return lib.starnt_version().decode()
+
+
+def workspace(nbytes, device="cuda"):
+    return torch.empty(max(1, (int(nbytes) + 255) // 256 * 256), dtype=torch.uint8, device=device)

@@ -1,0 +1,206 @@
+// C ABI of libstarnt: argument validation on the host, then the launchers.
+// Every function enqueues on the caller's stream and returns without waiting.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.h"
+
+namespace starnt {
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_status(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return STARNT_EHIP;
+}
+
+}  // namespace starnt
+
+using namespace starnt;
+
+namespace {
+
+constexpr int64_t kMaxSide = 16384;
+
+int check_frame(int32_t W, int32_t H, const char* who) {
+  if (W <= 0 || H <= 0 || W > kMaxSide || H > kMaxSide)
+    return fail(STARNT_EINVAL, std::string(who) + ": width/height must be in [1, 16384]");
+  return STARNT_OK;
+}
+
+int check_frags(const starnt_frags* f, const char* who) {
+  if (!f) return fail(STARNT_EINVAL, std::string(who) + ": frags is NULL");
+  int rc = check_frame(f->width, f->height, who);
+  if (rc) return rc;
+  if (!f->offsets) return fail(STARNT_EINVAL, std::string(who) + ": offsets is NULL");
+  if (f->num_frags > 0 && (!f->depth || !f->rgba || !f->prim))
+    return fail(STARNT_EINVAL, std::string(who) + ": NULL fragment array");
+  if (f->rgba_dtype != STARNT_F32 && f->rgba_dtype != STARNT_F16)
+    return fail(STARNT_EINVAL, std::string(who) + ": rgba_dtype must be STARNT_F32 or STARNT_F16");
+  if (f->num_frags >= (1ull << 32))
+    return fail(STARNT_EINVAL, std::string(who) + ": num_frags must be below 2^32");
+  if (f->max_per_pixel == 0) return fail(STARNT_EINVAL, std::string(who) + ": max_per_pixel must be >= 1");
+  return STARNT_OK;
+}
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+int starnt_features(const starnt_frags* frags, const starnt_sched* sched, const starnt_feats* out,
+                    void* stream) {
+  int rc = check_frags(frags, "starnt_features");
+  if (rc) return rc;
+  if (!out || !out->d1 || !out->layer1 || !out->count || !out->layer2 || !out->tail || !out->err)
+    return fail(STARNT_EINVAL, "starnt_features: NULL output array (d1, layer1, count, layer2, tail, err)");
+  if (out->width != frags->width || out->height != frags->height)
+    return fail(STARNT_EINVAL, "starnt_features: feats and frags differ in width/height");
+  return launch_features(*frags, sched, *out, as_stream(stream));
+}
+
+int starnt_infer(const starnt_mlp* mlp, const float* tail, const uint32_t* count, const starnt_sched* sched,
+                 int32_t width, int32_t height, float* tail_rgb, void* stream) {
+  int rc = check_frame(width, height, "starnt_infer");
+  if (rc) return rc;
+  if (!mlp || !tail || !count || !tail_rgb) return fail(STARNT_EINVAL, "starnt_infer: NULL argument");
+  if (mlp->in != 16 || mlp->out != 3)
+    return fail(STARNT_EINVAL, "starnt_infer: the network must have in = 16 and out = 3");
+  if (mlp->h1 < 1 || mlp->h1 > 64 || mlp->h2 < 1 || mlp->h2 > 64)
+    return fail(STARNT_EINVAL, "starnt_infer: hidden widths must be in [1, 64]");
+  if (!mlp->W1 || !mlp->b1 || !mlp->W2 || !mlp->b2 || !mlp->W3 || !mlp->b3)
+    return fail(STARNT_EINVAL, "starnt_infer: NULL weight array");
+  if (mlp->dtype == STARNT_FP8 && !mlp->fp8_scales)
+    return fail(STARNT_EINVAL, "starnt_infer: FP8 needs fp8_scales");
+  if (mlp->fp8_scales)
+    for (int i = 0; i < 6; ++i)
+      if (!(mlp->fp8_scales[i] > 0.0f) || !std::isfinite(mlp->fp8_scales[i]))
+        return fail(STARNT_EINVAL, "starnt_infer: fp8 scales must be finite and positive");
+  return launch_infer(*mlp, tail, count, sched, width, height, tail_rgb, as_stream(stream));
+}
+
+int starnt_composite(const starnt_frags* frags, const starnt_feats* feats, const float* tail_rgb,
+                     const starnt_sched* sched, const float* bg, int32_t mode, float* rgb, float* fstar,
+                     void* stream) {
+  if (!bg || !rgb) return fail(STARNT_EINVAL, "starnt_composite: NULL bg or rgb");
+  if (mode == STARNT_MODE_EXACT) {
+    int rc = check_frags(frags, "starnt_composite");
+    if (rc) return rc;
+    uint32_t* err = feats ? feats->err : nullptr;
+    return launch_exact(*frags, bg, rgb, fstar, err, as_stream(stream));
+  }
+  if (mode != STARNT_MODE_LEARNED && mode != STARNT_MODE_F0 && mode != STARNT_MODE_FAVG)
+    return fail(STARNT_EINVAL, "starnt_composite: unknown mode");
+  if (!feats || !feats->layer1 || !feats->count || !feats->layer2 || !feats->tail)
+    return fail(STARNT_EINVAL, "starnt_composite: NULL feature array");
+  if (mode == STARNT_MODE_LEARNED && !tail_rgb)
+    return fail(STARNT_EINVAL, "starnt_composite: learned mode needs tail_rgb");
+  const int W = feats->width, H = feats->height;
+  int rc = check_frame(W, H, "starnt_composite");
+  if (rc) return rc;
+  return launch_composite(*feats, tail_rgb, sched, W, H, bg, mode, rgb, as_stream(stream));
+}
+
+int starnt_quadtree(const float* rgb, const uint32_t* count, int32_t width, int32_t height,
+                    const starnt_qt_params* params, const uint32_t* prev_mask, uint32_t* mask, uint8_t* level,
+                    starnt_sched* sched, void* workspace, size_t workspace_bytes, void* stream) {
+  int rc = check_frame(width, height, "starnt_quadtree");
+  if (rc) return rc;
+  if (!rgb || !count || !params || !mask || !level || !sched)
+    return fail(STARNT_EINVAL, "starnt_quadtree: NULL argument");
+  if (params->base < 8 || params->base % 8 || params->base > 4096)
+    return fail(STARNT_EINVAL, "starnt_quadtree: base must be a multiple of 8 in [8, 4096]");
+  if (params->k_relax < 0 || params->k_relax > 8)
+    return fail(STARNT_EINVAL, "starnt_quadtree: k_relax must be in [0, 8]");
+  if (!(params->tau_merge <= params->tau_split))
+    return fail(STARNT_EINVAL, "starnt_quadtree: tau_merge must not exceed tau_split");
+  if (prev_mask && prev_mask == mask) return fail(STARNT_EINVAL, "starnt_quadtree: prev_mask aliases mask");
+  const size_t need = quadtree_ws_bytes(width, height, params->base);
+  if (!workspace || workspace_bytes < need) return fail(STARNT_ENOMEM, "starnt_quadtree: workspace too small");
+  return launch_quadtree(rgb, count, width, height, *params, prev_mask, mask, level, sched, workspace,
+                         as_stream(stream));
+}
+
+int starnt_reproject(const float* rgb_prev, const float* d1_prev, int32_t width, int32_t height,
+                     const float* m_minus_i, float* rgb_out, int32_t* src, void* stream) {
+  int rc = check_frame(width, height, "starnt_reproject");
+  if (rc) return rc;
+  if (!rgb_prev || !d1_prev || !m_minus_i || !rgb_out) return fail(STARNT_EINVAL, "starnt_reproject: NULL argument");
+  if (rgb_prev == rgb_out) return fail(STARNT_EINVAL, "starnt_reproject: rgb_out aliases rgb_prev");
+  for (int i = 0; i < 16; ++i)
+    if (!std::isfinite(m_minus_i[i])) return fail(STARNT_EINVAL, "starnt_reproject: non-finite matrix");
+  return launch_reproject(rgb_prev, d1_prev, width, height, m_minus_i, rgb_out, src, as_stream(stream));
+}
+
+int starnt_train_step(const starnt_train* t, const float* x, const float* y, int32_t batch,
+                      const starnt_adam* hp, float* loss, void* workspace, size_t workspace_bytes,
+                      void* stream) {
+  if (!t || !x || !y || !hp || !loss) return fail(STARNT_EINVAL, "starnt_train_step: NULL argument");
+  if (!t->params || !t->m || !t->v || !t->grad) return fail(STARNT_EINVAL, "starnt_train_step: NULL state array");
+  if (t->in != 16 || t->out != 3) return fail(STARNT_EINVAL, "starnt_train_step: in must be 16 and out 3");
+  if (t->dtype != STARNT_F32 && t->dtype != STARNT_BF16)
+    return fail(STARNT_EINVAL, "starnt_train_step: dtype must be STARNT_F32 or STARNT_BF16");
+  if (batch < 1 || batch > (1 << 24)) return fail(STARNT_EINVAL, "starnt_train_step: batch must be in [1, 2^24]");
+  if (hp->step < 1) return fail(STARNT_EINVAL, "starnt_train_step: Adam step is 1-based");
+  if (!(hp->beta1 >= 0.0f && hp->beta1 < 1.0f && hp->beta2 >= 0.0f && hp->beta2 < 1.0f))
+    return fail(STARNT_EINVAL, "starnt_train_step: betas must be in [0, 1)");
+  const size_t need = train_ws_bytes(batch, t->h1, t->h2);
+  if (!workspace || workspace_bytes < need) return fail(STARNT_ENOMEM, "starnt_train_step: workspace too small");
+  return launch_train(*t, x, y, batch, *hp, loss, workspace, workspace_bytes, as_stream(stream));
+}
+
+int starnt_sched_init(starnt_sched* sched, int32_t width, int32_t height, double s2, double s3, void* stream) {
+  int rc = check_frame(width, height, "starnt_sched_init");
+  if (rc) return rc;
+  if (!sched) return fail(STARNT_EINVAL, "starnt_sched_init: NULL sched");
+  if (!(s2 > 0.0 && s2 <= 1.0 && s3 > 0.0 && s3 <= 1.0))
+    return fail(STARNT_EINVAL, "starnt_sched_init: scales must be in (0, 1]");
+  return launch_sched_init(sched, starnt_grid_dim(width, s2), starnt_grid_dim(height, s2),
+                           starnt_grid_dim(width, s3), starnt_grid_dim(height, s3), as_stream(stream));
+}
+
+double starnt_wbar(const uint32_t* h) {
+  if (!h) return 0.0;
+  const double den = (double)h[0] + h[1] + h[2] + h[3];
+  return den > 0 ? ((double)h[1] + 2.0 * h[2] + 3.0 * h[3]) / den : 0.0;
+}
+
+void starnt_pass_scales(double wbar, double* s2, double* s3) {
+  const double a = std::exp2(wbar - 2.2), b = std::exp2(wbar - 3.0);
+  if (s2) *s2 = std::fmin(1.0, std::fmax(0.25, a));
+  if (s3) *s3 = std::fmin(1.0, std::fmax(0.25, b));
+}
+
+int32_t starnt_grid_dim(int32_t n, double s) {
+  double v = std::ceil(s * (double)n);
+  v = std::fmax(1.0, std::fmin((double)n, v));
+  return (int32_t)v;
+}
+
+size_t starnt_workspace_size(int32_t kind, int64_t a, int64_t b, int64_t c) {
+  if (kind == STARNT_WS_QUADTREE) return quadtree_ws_bytes(a, b, c);
+  if (kind == STARNT_WS_TRAIN) return train_ws_bytes(a, b, c);
+  return 0;
+}
+
+int starnt_check(uint32_t err_word) {
+  if (!err_word) return STARNT_OK;
+  std::string m = "device error word:";
+  if (err_word & STARNT_DERR_DEPTH) m += " depth outside [0,1];";
+  if (err_word & STARNT_DERR_ALPHA) m += " alpha outside [0,1];";
+  if (err_word & STARNT_DERR_COUNT) m += " list longer than max_per_pixel;";
+  return fail(STARNT_ERANGE, m);
+}
+
+const char* starnt_last_error(void) { return g_last_error.c_str(); }
+
+const char* starnt_version(void) { return "starnt 0.1 gfx950"; }
+
+}  // extern "C"

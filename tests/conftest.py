@@ -30,3 +30,23 @@ def sg():
     import scenegen
     scenegen.build(force=False)
     return scenegen
+
+
+@pytest.fixture(scope="session")
+def starnt():
+    """The product binding; builds libstarnt.so first when it is missing."""
+    import os
+    lib = os.path.join(ROOT, "paper_2606_16747_amd", "libstarnt.so")
+    if not os.path.exists(lib):
+        from paper_2606_16747_amd import build as b
+        b.build()
+    import paper_2606_16747_amd as m
+    return m
+
+
+@pytest.fixture(scope="session")
+def gpu(starnt):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test selected but no GPU is visible")
+    return torch.device("cuda:0")

@@ -1,0 +1,382 @@
+"""Parity of every HIP entry point with the FP64 oracle, element by element on
+seeded inputs (config-1 sized frames and small hand-built cases).
+
+Bars (written in each test): bit-exact for counts, layer selection and
+reprojection indices; <= 1e-4 per channel for FP32 floating point results
+against FP64; BF16 results against the oracle on the same bf16 operands."""
+import numpy as np
+import pytest
+import torch
+
+from csr_util import make_csr, random_lists
+from gpu_util import run_exact, run_features, run_learned, sel_np, sync, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def _frame(sg, name="c1_256", **kw):
+    return sg.Scene(name, **kw).frame(0)
+
+
+def _check_features(fr, fb, o):
+    N = to_np(fb.count).view(np.uint32)
+    np.testing.assert_array_equal(N, o["lay"][:, 0].astype(np.uint32))
+    np.testing.assert_array_equal(sel_np(fb), o["sel"])
+    np.testing.assert_array_equal(to_np(fb.d1), o["lay"][:, 1].astype(np.float32))
+    L1 = to_np(fb.layer1)
+    lay = o["lay"]
+    np.testing.assert_allclose(L1[:, 3], lay[:, 2], atol=1e-7)
+    np.testing.assert_allclose(L1[:, 0:3], lay[:, 2:3] * lay[:, 3:6], atol=1e-7)
+    T = to_np(fb.tail)
+    A = o["tail"][:, 0]
+    ct = np.where(A[:, None] > 0, o["tail"][:, 1:4] / np.where(A > 0, A, 1)[:, None], 0.0)
+    np.testing.assert_array_equal(T[:, 0], lay[:, 0].astype(np.float32))
+    np.testing.assert_allclose(T[:, 1], o["tail"][:, 4], atol=2e-6, rtol=1e-5)   # t_tail
+    np.testing.assert_allclose(T[:, 2:5], ct, atol=2e-6)                          # normalised tail colour
+    np.testing.assert_allclose(T[:, 5], A, atol=1e-5, rtol=1e-6)                   # tail opacity sum
+    assert int(to_np(fb.err)[0]) == 0
+
+
+def test_features_full_resolution_config1(starnt, gpu, sg, oracle_mod):
+    fr = _frame(sg)
+    _, fb = run_features(starnt, fr, max_per_pixel=24)
+    _check_features(fr, fb, oracle_mod.frame_of(fr))
+
+
+def test_features_order_independent_bitwise(starnt, gpu, sg):
+    """Permuting every list leaves all features bit-identical and selects the
+    same fragments."""
+    fr = _frame(sg)
+    fr2 = sg.shuffled(fr, 5)
+    _, a = run_features(starnt, fr, max_per_pixel=24)
+    _, b = run_features(starnt, fr2, max_per_pixel=24)
+    for name in ("count", "d1", "layer1", "tail", "layer2"):
+        assert torch.equal(getattr(a, name), getattr(b, name)), name
+    sa, sb = sel_np(a), sel_np(b)
+    ok = sa != 0xFFFFFFFF
+    assert np.array_equal(sa == 0xFFFFFFFF, sb == 0xFFFFFFFF)
+    assert np.array_equal(fr.prim[sa[ok]], fr2.prim[sb[ok]])
+    assert np.array_equal(fr.depth[sa[ok]], fr2.depth[sb[ok]])
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_features_and_exact_ties_8x8(starnt, gpu, oracle_mod, seed):
+    """Hand-built 8x8 frames where equal depths are common: selection breaks
+    ties on primitive id exactly as the oracle's sort does."""
+    rng = np.random.default_rng(seed)
+    lists = random_lists(rng, 8, 8, 12, ties=True)
+    off, dep, rgba, prim = make_csr(lists, 8, 8)
+    df = starnt.DeviceFrags(off, dep, rgba, prim, 8, 8, 12)
+    fb = starnt.FeatBuffers(8, 8, with_sel=True)
+    starnt.starnt_features(df, None, fb)
+    sync()
+    o = oracle_mod.frame(off, dep, rgba, prim, 8, 8, bg=(0.2, 0.4, 0.6))
+    np.testing.assert_array_equal(sel_np(fb), o["sel"])
+    rgb, fstar = run_exact(starnt, df, bg=(0.2, 0.4, 0.6))
+    np.testing.assert_allclose(rgb, o["rgb"], atol=TOL)
+    np.testing.assert_allclose(fstar, o["fstar"], atol=TOL)
+
+
+@pytest.mark.parametrize("bg", [(0.0, 0.0, 0.0), (1.0, 1.0, 1.0)])
+def test_exact_composite_config1(starnt, gpu, sg, oracle_mod, bg):
+    fr = _frame(sg)
+    df = starnt.DeviceFrags.from_frame(fr, max_per_pixel=24)
+    rgb, fstar = run_exact(starnt, df, bg=bg)
+    o = oracle_mod.frame_of(fr, bg=bg)
+    err = np.abs(rgb - o["rgb"]).max()
+    assert err <= TOL, err
+    assert np.abs(fstar - o["fstar"]).max() <= TOL
+    # bit-identical under permutation of the lists
+    df2 = starnt.DeviceFrags.from_frame(sg.shuffled(fr, 9), max_per_pixel=24)
+    rgb2, fstar2 = run_exact(starnt, df2, bg=bg)
+    assert np.array_equal(rgb, rgb2) and np.array_equal(fstar, fstar2)
+
+
+def test_exact_long_lists_and_batches(starnt, gpu, oracle_mod):
+    """Lists up to the 2048-fragment staging capacity, windows that need
+    several LDS batches, and empty pixels."""
+    rng = np.random.default_rng(3)
+    W, H = 37, 9
+    lists = []
+    for p in range(W * H):
+        n = int(rng.choice([0, 1, 2, 3, 40, 300]))
+        if p == 5:
+            n = 2048
+        z = rng.permutation(n).astype(np.float32) / max(n, 1)
+        lists.append([(float(z[k]), k, *rng.random(3), float(rng.uniform(0.01, 0.2))) for k in range(n)])
+    csr = make_csr(lists, W, H)
+    df = starnt.DeviceFrags(*csr, W, H, 2048)
+    rgb, fstar = run_exact(starnt, df, bg=(0.3, 0.6, 0.9))
+    o = oracle_mod.frame(*csr, W, H, bg=(0.3, 0.6, 0.9))
+    assert np.abs(rgb - o["rgb"]).max() <= TOL
+    assert np.abs(fstar - o["fstar"]).max() <= TOL
+    fb = starnt.FeatBuffers(W, H, with_sel=True)
+    starnt.starnt_features(df, None, fb)
+    sync()
+    np.testing.assert_array_equal(sel_np(fb), o["sel"])
+
+
+def test_empty_and_tiny_frames(starnt, gpu, oracle_mod):
+    for W, H, nmax in ((1, 1, 0), (3, 2, 0), (1, 1, 3), (5, 1, 4)):
+        rng = np.random.default_rng(W * 10 + H + nmax)
+        lists = random_lists(rng, W, H, nmax)
+        csr = make_csr(lists, W, H)
+        df = starnt.DeviceFrags(*csr, W, H, max(1, nmax))
+        fb = starnt.FeatBuffers(W, H, with_sel=True)
+        starnt.starnt_features(df, None, fb)
+        rgb, fstar = run_exact(starnt, df, bg=(0.5, 0.25, 1.0))
+        o = oracle_mod.frame(*csr, W, H, bg=(0.5, 0.25, 1.0))
+        np.testing.assert_array_equal(to_np(fb.count).view(np.uint32), o["lay"][:, 0].astype(np.uint32))
+        np.testing.assert_array_equal(to_np(fb.d1), o["lay"][:, 1].astype(np.float32))
+        assert np.abs(rgb - o["rgb"]).max() <= TOL
+
+
+def test_device_error_word(starnt, gpu, sg):
+    """Depth outside [0,1] and lists longer than the declared maximum are
+    reported through the error word; the kernels still finish."""
+    fr = _frame(sg)
+    depth = fr.depth.copy()
+    depth[100] = 1.5
+    df = starnt.DeviceFrags(fr.offsets, depth, fr.rgba, fr.prim, fr.width, fr.height, 24)
+    fb = starnt.FeatBuffers(fr.width, fr.height)
+    starnt.starnt_features(df, None, fb)
+    sync()
+    w = int(to_np(fb.err)[0])
+    assert w & starnt.DERR_DEPTH
+    with pytest.raises(starnt.StarntError):
+        starnt.starnt_check(w)
+    df = starnt.DeviceFrags(fr.offsets, fr.depth, fr.rgba, fr.prim, fr.width, fr.height, 3)
+    fb = starnt.FeatBuffers(fr.width, fr.height)
+    starnt.starnt_features(df, None, fb)
+    sync()
+    assert int(to_np(fb.err)[0]) & starnt.DERR_COUNT
+
+
+def _grids_for(oracle_mod, W, H, s2, s3):
+    return (oracle_mod.grid_dim(W, s2), oracle_mod.grid_dim(H, s2), oracle_mod.grid_dim(W, s3),
+            oracle_mod.grid_dim(H, s3))
+
+
+@pytest.mark.parametrize("s2,s3", [(1.0, 1.0), (0.5, 0.25), (0.77, 0.31)])
+@pytest.mark.parametrize("mode", ["learned", "f0", "favg"])
+def test_learned_composite_fp32_mixed_resolution(starnt, gpu, sg, oracle_mod, s2, s3, mode):
+    """Passes 2/3 on reduced grids, bilinear upscale, FP32 network and eq (3)
+    composite against the FP64 oracle (per channel <= 1e-4)."""
+    fr = _frame(sg, width=250, height=131, num_tris=60)
+    W, H = fr.width, fr.height
+    sched = starnt.new_sched(W, H, s2, s3)
+    df, fb = run_features(starnt, fr, sched=sched, max_per_pixel=64)
+    s = starnt.read_sched(sched)
+    grids = _grids_for(oracle_mod, W, H, s2, s3)
+    assert (s["w2"], s["h2"], s["w3"], s["h3"]) == grids
+    Ws, bs = sg.init_mlp((16, 32, 32, 3), out_bias=0.05)
+    mlp = starnt.DeviceMlp(Ws, bs, starnt.F32)
+    m = {"learned": starnt.MODE_LEARNED, "f0": starnt.MODE_F0, "favg": starnt.MODE_FAVG}[mode]
+    rgb, f = run_learned(starnt, df, fb, mlp, sched, bg=(0.9, 0.8, 0.7), mode=m)
+    o = oracle_mod.frame_of(fr)
+    om = {"learned": oracle_mod.MODE_LEARNED, "f0": oracle_mod.MODE_F0, "favg": oracle_mod.MODE_FAVG}[mode]
+    want, _, fw = oracle_mod.learned(o["lay"], o["tail"], W, H, grids, oracle_mod.Mlp(Ws, bs), om,
+                                     bg=(0.9, 0.8, 0.7))
+    if mode == "learned":
+        assert np.abs(f - fw).max() <= TOL
+    err = np.abs(rgb - want).max()
+    assert err <= TOL, err
+
+
+def test_learned_equals_exact_when_f_is_the_exact_tail(starnt, gpu, sg, oracle_mod):
+    """eq (3) on the GPU with f = f* (the exact tail colour from the GPU exact
+    path) reproduces the exact composite at full resolution."""
+    fr = _frame(sg)
+    df, fb = run_features(starnt, fr, max_per_pixel=24)
+    P = fr.num_pixels
+    _, fstar = run_exact(starnt, df, bg=(1, 1, 1))
+    tail_rgb = torch.from_numpy(fstar).cuda()
+    N = to_np(fb.count)
+    rgb = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+    starnt.starnt_composite(df, fb, tail_rgb, None, (1, 1, 1), starnt.MODE_LEARNED, rgb)
+    exact, _ = run_exact(starnt, df, bg=(1, 1, 1))
+    assert np.abs(to_np(rgb) - exact).max() <= TOL
+    assert (N >= 3).sum() > 1000
+
+
+@pytest.mark.parametrize("dims", [(16, 32, 32, 3), (16, 64, 64, 3), (16, 32, 16, 3)])
+def test_infer_bf16_against_same_operands(starnt, gpu, sg, oracle_mod, dims):
+    """BF16 matrix-core inference against the FP64 evaluation of the same
+    network with bf16-rounded weights and activations. Rounding of an
+    activation can flip between FP32 and FP64 accumulation, so the bar is:
+    99.5% of pixels within 2e-4, every pixel within 2e-2."""
+    fr = _frame(sg)
+    df, fb = run_features(starnt, fr, max_per_pixel=24)
+    Ws, bs = sg.init_mlp(dims, seed=123, out_bias=0.1)
+    mlp = starnt.DeviceMlp(Ws, bs, starnt.BF16)
+    P = fr.num_pixels
+    out = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+    starnt.starnt_infer(mlp, fb.tail, fb.count, None, fr.width, fr.height, out)
+    sync()
+    y = to_np(out)
+    x = np.zeros((P, 16))
+    x[:, :5] = to_np(fb.tail)[:, :5]
+    N = to_np(fb.count)
+    om = oracle_mod.Mlp(Ws, bs)
+    want = np.where(N[:, None] >= 3, om.forward_q(x, 1), 0.0)
+    err = np.abs(y - want).max(axis=1)
+    assert np.mean(err <= 2e-4) >= 0.995, np.mean(err <= 2e-4)
+    assert err.max() <= 2e-2
+    # and against the unquantised FP64 network: stated, loosely bounded
+    full = np.where(N[:, None] >= 3, om.forward(x), 0.0)
+    assert np.abs(y - full).mean() < 2e-2
+
+
+def test_quadtree_matches_oracle_over_frames(starnt, gpu, sg, oracle_mod):
+    """Quadtree decisions on the GPU's FP32 composites of three frames of a
+    moving scene, chained through prev masks, against the oracle given the
+    same image, counts and prev mask. Tiles near a node whose FP64 distance is
+    within 1e-6 of a threshold are excluded (none expected)."""
+    sc = sg.Scene("c2_1080p", width=480, height=270, num_tris=300)
+    W, H = 480, 270
+    qp = starnt.QtParams(64, 0.10, 0.05, 2)
+    T = ((W + 63) // 64) * ((H + 63) // 64)
+    Cw, Ch = W // 8 + (W % 8 > 0), H // 8 + (H % 8 > 0)
+    ws = starnt.workspace(starnt.starnt_workspace_size(starnt.WS_QUADTREE, W, H, 64))
+    masks = [torch.zeros(T, dtype=torch.int32, device="cuda") for _ in range(2)]
+    level = torch.zeros(Cw * Ch, dtype=torch.uint8, device="cuda")
+    sched = starnt.new_sched(W, H)
+    prev = None
+    for t in range(3):
+        fr = sc.frame(t)
+        df, fb = run_features(starnt, fr, max_per_pixel=64)
+        rgb, _ = run_exact(starnt, df)
+        rgb_t = torch.from_numpy(rgb).cuda()
+        cur = masks[t % 2]
+        starnt.starnt_quadtree(rgb_t, fb.count, W, H, qp, prev, cur, level, sched, ws)
+        sync()
+        pm = None if prev is None else to_np(prev).view(np.uint32)
+        m, lv, hist, D = oracle_mod.quadtree(rgb, to_np(fb.count).view(np.uint32), W, H, base=64,
+                                             tau_split=0.10, tau_merge=0.05, k_relax=2, prev_mask=pm)
+        border = (np.abs(D - 0.10) < 1e-6) | (np.abs(D - 0.05) < 1e-6)
+        assert not border.any()
+        np.testing.assert_array_equal(to_np(cur).view(np.uint32), m)
+        np.testing.assert_array_equal(to_np(level).reshape(Ch, Cw), lv)
+        s = starnt.read_sched(sched)
+        assert s["hist"] == list(hist)
+        wb = oracle_mod.wbar(hist)
+        assert abs(s["wbar"] - wb) < 1e-6
+        s2, s3 = oracle_mod.pass_scales(wb)
+        assert (s["w2"], s["h2"], s["w3"], s["h3"]) == _grids_for(oracle_mod, W, H, s2, s3)
+        assert s["frames"] == t + 1
+        prev = cur
+    assert sum(s["hist"][1:]) > 0  # something split
+
+
+@pytest.mark.parametrize("base", [16, 64])
+def test_quadtree_ragged_edges(starnt, gpu, oracle_mod, base):
+    rng = np.random.default_rng(base)
+    W, H = 203, 77
+    img = np.zeros((H, W, 3), np.float32)
+    img[20:60, 30:150] = rng.random((40, 120, 3))
+    img[:, 190:] = 0.8
+    N = (rng.random(W * H) < 0.8).astype(np.uint32)
+    T = ((W + base - 1) // base) * ((H + base - 1) // base)
+    cs = base // 8
+    Cw, Ch = (W + cs - 1) // cs, (H + cs - 1) // cs
+    ws = starnt.workspace(starnt.starnt_workspace_size(starnt.WS_QUADTREE, W, H, base))
+    mask = torch.zeros(T, dtype=torch.int32, device="cuda")
+    level = torch.zeros(Cw * Ch, dtype=torch.uint8, device="cuda")
+    sched = starnt.new_sched(W, H)
+    for k in (0, 1, 2, 3):
+        qp = starnt.QtParams(base, 0.2, 0.1, k)
+        starnt.starnt_quadtree(torch.from_numpy(img.reshape(-1, 3)).cuda(), torch.from_numpy(N.view(np.int32)).cuda(),
+                               W, H, qp, None, mask, level, sched, ws)
+        sync()
+        m, lv, hist, D = oracle_mod.quadtree(img, N, W, H, base=base, tau_split=0.2, tau_merge=0.1, k_relax=k)
+        assert not ((np.abs(D - 0.2) < 1e-6) | (np.abs(D - 0.1) < 1e-6)).any()
+        np.testing.assert_array_equal(to_np(mask).view(np.uint32), m)
+        np.testing.assert_array_equal(to_np(level).reshape(Ch, Cw), lv)
+        assert starnt.read_sched(sched)["hist"] == list(hist)
+
+
+def test_reproject_matches_oracle(starnt, gpu, sg, oracle_mod):
+    """Reprojection indices bit-exact against FP64 given the same FP32 depth
+    and M - I, except where the FP64 source coordinate lies within 1e-4 px of
+    a rounding boundary (counted, must be rare)."""
+    sc = sg.Scene("c2_1080p", width=640, height=360, num_tris=400)
+    fr = sc.frame(2)
+    W, H = 640, 360
+    df, fb = run_features(starnt, fr, max_per_pixel=64)
+    rgb, _ = run_exact(starnt, df)
+    mmi = oracle_mod.m_minus_i(sc.camera(2), sc.camera(3)).astype(np.float32)
+    out = torch.empty(W * H, 3, dtype=torch.float32, device="cuda")
+    src = torch.empty(W * H, dtype=torch.int32, device="cuda")
+    starnt.starnt_reproject(torch.from_numpy(rgb).cuda(), fb.d1, W, H, mmi, out, src)
+    sync()
+    d1 = to_np(fb.d1)
+    want_rgb, want_src, margin = oracle_mod.reproject(rgb, d1, mmi.astype(np.float64), W, H)
+    ok = margin >= 1e-4
+    assert ok.mean() > 0.999
+    np.testing.assert_array_equal(to_np(src)[ok], want_src[ok])
+    np.testing.assert_array_equal(to_np(out)[ok], want_rgb[ok])
+    assert (want_src != np.arange(W * H)).mean() > 0.3
+
+
+def _train_setup(sg, oracle_mod, dims, batch, seed=0):
+    fr = sg.Scene("c3_512", width=128, height=128, num_tris=200).frame(0)
+    o = oracle_mod.frame_of(fr)
+    x = oracle_mod.features(o["lay"], o["tail"])
+    keep = o["lay"][:, 0] >= 3
+    x, y = x[keep], o["fstar"][keep]
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(len(x), batch, replace=len(x) < batch)
+    Ws, bs = sg.init_mlp(dims, seed=77, out_bias=0.1)
+    params = oracle_mod.Mlp(Ws, bs).params().astype(np.float32)
+    return x[idx].astype(np.float32), y[idx].astype(np.float32), params
+
+
+@pytest.mark.parametrize("dims,batch", [((16, 32, 32, 3), 1000), ((16, 64, 64, 3), 4096)])
+def test_train_step_fp32_gradient_and_adam(starnt, gpu, sg, oracle_mod, dims, batch):
+    x, y, params = _train_setup(sg, oracle_mod, dims, batch)
+    n = params.size
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    p, m, v, g = dev(params.copy()), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    tr = starnt.Train(16, dims[1], dims[2], 3, starnt.F32, p.data_ptr(), m.data_ptr(), v.data_ptr(), g.data_ptr())
+    ad = starnt.Adam(1e-3, 0.9, 0.999, 1e-8, 1)
+    loss = torch.zeros(1, device="cuda")
+    ws = starnt.workspace(starnt.starnt_workspace_size(starnt.WS_TRAIN, batch, dims[1], dims[2]))
+    starnt.starnt_train_step(tr, dev(x), dev(y), batch, ad, loss, ws)
+    sync()
+    lw, gw = oracle_mod.loss_grad(dims, params.astype(np.float64), x, y)
+    gg = to_np(g).astype(np.float64)
+    rel = np.linalg.norm(gg - gw) / np.linalg.norm(gw)
+    assert rel <= 1e-5, rel
+    assert abs(float(to_np(loss)[0]) - lw) <= 1e-5 * lw + 1e-9
+    w = params.astype(np.float64).copy()
+    mm, vv = np.zeros(n), np.zeros(n)
+    oracle_mod.adam(w, mm, vv, gw, lr=1e-3, t=1)
+    # step 1 moves each weight by ~lr sign(g); allow for |g| near eps
+    assert np.abs(to_np(p) - w).max() <= 2e-6
+    # a second identical run is bitwise identical
+    p2, m2, v2, g2 = dev(params.copy()), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    tr2 = starnt.Train(16, dims[1], dims[2], 3, starnt.F32, p2.data_ptr(), m2.data_ptr(), v2.data_ptr(), g2.data_ptr())
+    starnt.starnt_train_step(tr2, dev(x), dev(y), batch, ad, loss, ws)
+    sync()
+    assert torch.equal(p, p2) and torch.equal(g, g2)
+
+
+def test_train_step_bf16_gradient_direction(starnt, gpu, sg, oracle_mod):
+    """BF16 mode: gradient against FP64 (cosine similarity and rel-L2 stated)."""
+    dims, batch = (16, 64, 64, 3), 8192
+    x, y, params = _train_setup(sg, oracle_mod, dims, batch, seed=1)
+    n = params.size
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    p, m, v, g = dev(params.copy()), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    tr = starnt.Train(16, 64, 64, 3, starnt.BF16, p.data_ptr(), m.data_ptr(), v.data_ptr(), g.data_ptr())
+    loss = torch.zeros(1, device="cuda")
+    ws = starnt.workspace(starnt.starnt_workspace_size(starnt.WS_TRAIN, batch, 64, 64))
+    starnt.starnt_train_step(tr, dev(x), dev(y), batch, starnt.Adam(1e-3, 0.9, 0.999, 1e-8, 1), loss, ws)
+    sync()
+    _, gw = oracle_mod.loss_grad(dims, params.astype(np.float64), x, y)
+    gg = to_np(g).astype(np.float64)
+    cos = gg @ gw / (np.linalg.norm(gg) * np.linalg.norm(gw))
+    assert cos > 0.999, cos
+    assert np.linalg.norm(gg - gw) / np.linalg.norm(gw) < 0.05

@@ -1,0 +1,369 @@
+#!/usr/bin/env python
+"""Benchmark of the STAR-NT per-pixel hot path on one MI355X.
+
+Workload (the 1080p configuration): 1920x1080, 2000 seeded triangles,
+heavy-tailed depth complexity (mean ~8, max 64), an 8-frame seeded camera
+path. One step renders the 8 frames: real frames (0, 2, 4, 6) run passes 1-3
+on the grids the quadtree chose, the BF16 tail network, the eq (3) composite
+and the quadtree update; odd frames are reprojected from the last real frame.
+The same 8 frames are also rendered by the exact sort-and-over path on the
+same GPU, which is the reference for PSNR and the time to beat.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ms/frame + Gfrag/s at 1080p: quadtree+NN vs exact sort, PSNR vs exact"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench %6.1fs]" % (time.time() - T0), *a, file=sys.stderr, flush=True)
+
+
+T0 = time.time()
+
+
+def sample_mask(n, ns):
+    """Boolean mask of the full-resolution coordinates a grid of ns samples uses."""
+    m = np.zeros(n, bool)
+    i = np.arange(ns, dtype=np.int64)
+    m[((2 * i + 1) * n) // (2 * ns)] = True
+    return m
+
+
+def feature_pass_bytes(fr, grids):
+    """Algorithmic HBM bytes of one starnt_features launch on these grids:
+    offsets + every depth + RGBA of the pass-3 samples' fragments + one RGBA
+    gather per remaining layer read, and the outputs."""
+    W, H = fr.width, fr.height
+    w2, h2, w3, h3 = grids
+    n = fr.counts().astype(np.int64).reshape(H, W)
+    s2 = sample_mask(H, h2)[:, None] & sample_mask(W, w2)[None, :]
+    s3 = sample_mask(H, h3)[:, None] & sample_mask(W, w3)[None, :]
+    rgba_b = fr.rgba.dtype.itemsize * 4
+    reads = 4 * (W * H + 1) + 4 * fr.num_frags + rgba_b * int(n[s3].sum())
+    reads += rgba_b * int(((n >= 1) & ~s3).sum()) + rgba_b * int(((n >= 2) & s2 & ~s3).sum())
+    writes = (4 + 16 + 4) * W * H + 16 * w2 * h2 + 32 * w3 * h3
+    return reads + writes, int(n[s3].sum())
+
+
+def counters_traffic(path, src_hash):
+    """HBM bytes per features launch measured by rocprofv3 counters, if the
+    committed record was taken on the current kernel source."""
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("features_hip_sha256") != src_hash:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(fr0, fr1, mlp_w, mlp_b, bg, budget_s):
+    """The FP64 oracle on the host: frame 0 (exact sort and over, tail
+    features, FP64 network, eq (3) composite at full resolution, quadtree) and
+    frame 1 (reprojection), single-threaded."""
+    import oracle
+    oracle.build(force=False)
+    t = time.perf_counter()
+    o = oracle.frame_of(fr0, bg=bg, nthreads=1, want=("rgb", "lay", "tail"))
+    W, H = fr0.width, fr0.height
+    rgb, _, _ = oracle.learned(o["lay"], o["tail"], W, H, (W, H, W, H), oracle.Mlp(mlp_w, mlp_b), bg=bg)
+    oracle.quadtree(rgb.astype(np.float32), o["lay"][:, 0].astype(np.uint32), W, H, base=64)
+    mmi = oracle.m_minus_i(fr0.vp, fr1.vp)
+    oracle.reproject(rgb.astype(np.float32), o["lay"][:, 1].astype(np.float32), mmi, W, H)
+    dt = time.perf_counter() - t
+    frags = fr0.num_frags + fr1.num_frags
+    return {"value": frags / dt / 1e9, "unit": "Gfrag/s", "cores": 1, "kind": "oracle",
+            "sample": "frames 0 (real: sort+over, features, FP64 MLP 16-32-32-3, eq (3), quadtree) and 1 "
+                      "(reprojection) of the 1080p sequence, %.1f s" % dt,
+            "ms_per_frame": dt * 1e3 / 2}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--train-steps", type=int, default=1500)
+    ap.add_argument("--train-scenes", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=30.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import scenegen as sg
+    import paper_2606_16747_amd as st
+    from paper_2606_16747_amd import frames as fm
+    from paper_2606_16747_amd import learn
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    bg = (1.0, 1.0, 1.0)
+
+    # ---- workload --------------------------------------------------------
+    scene = sg.Scene("c2_1080p")
+    NF = scene.params.num_frames
+    W, H = scene.params.width, scene.params.height
+    P = W * H
+    host = []
+    for t in range(NF):
+        host.append(scene.frame(t))
+        log("frame %d: %d fragments, mean %.2f, max %d" % (t, host[-1].num_frags, host[-1].stats["mean_count"],
+                                                             host[-1].stats["max_count"]))
+    frags = [st.DeviceFrags.from_frame(f, max_per_pixel=64) for f in host]
+
+    # ---- the network, trained on the GPU by the library ------------------
+    dims = (16, 32, 32, 3)
+    Ws0, bs0 = sg.init_mlp(dims, seed=sg.BASE_SEED + 100, out_bias=0.05)
+    xs, ys = [], []
+    for k in range(args.train_scenes):
+        tf = sg.Scene("c3_512", seed=sg.BASE_SEED + 3 + 1000 * (k + 1)).frame(0)
+        x, y = learn.pairs_from(st.DeviceFrags.from_frame(tf, max_per_pixel=128), bg)
+        xs.append(x)
+        ys.append(y)
+    x = np.concatenate(xs)
+    y = np.concatenate(ys)
+    if len(x) > 4_000_000:
+        pick = np.random.default_rng(0).choice(len(x), 4_000_000, replace=False)
+        x, y = x[pick], y[pick]
+    log("training pairs: %d" % len(x))
+    tt = time.perf_counter()
+    Ws, bs, losses = learn.train(x, y, Ws0, bs0, steps=args.train_steps, batch=65536, dtype=st.BF16)
+    train_s = time.perf_counter() - tt
+    log("trained %d steps in %.2f s, loss %.3e -> %.3e" % (args.train_steps, train_s, losses[0], losses[-1]))
+    mlp = st.DeviceMlp(Ws, bs, st.BF16)
+
+    # ---- exact references -------------------------------------------------
+    exact = [torch.empty(P, 3, dtype=torch.float32, device=dev) for _ in range(NF)]
+    for t in range(NF):
+        fm.exact_frame(frags[t], exact[t], bg)
+    torch.cuda.synchronize()
+
+    mmis = [fm.m_minus_i(host[t - 1].vp, host[t].vp) if t % 2 else None for t in range(NF)]
+    outs = [torch.empty(P, 3, dtype=torch.float32, device=dev) for _ in range(NF)]
+    rend = fm.Renderer(W, H, mlp, base=64, bg=bg)
+
+    def star_step():
+        rend.reset()
+        for t in range(NF):
+            if t % 2 == 0:
+                rend.real_frame(frags[t], outs[t])
+            else:
+                rend.interpolated_frame(mmis[t], outs[t])
+
+    def exact_step():
+        for t in range(NF):
+            fm.exact_frame(frags[t], exact[t], bg)
+
+    # grids used by each real frame (deterministic): one untimed pass reading
+    # the device schedule before every real frame
+    grids = {}
+    rend.reset()
+    for t in range(NF):
+        if t % 2 == 0:
+            torch.cuda.synchronize()
+            s = st.read_sched(rend.sched)
+            grids[t] = (s["w2"], s["h2"], s["w3"], s["h3"])
+            rend.real_frame(frags[t], outs[t])
+        else:
+            rend.interpolated_frame(mmis[t], outs[t])
+    torch.cuda.synchronize()
+    log("grids per real frame: %s" % grids)
+
+    # ---- timed region -----------------------------------------------------
+    # events around every features launch, on the stream the launches use
+    ev = []
+
+    def timer(name, fn):
+        if name == "features":
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            ev.append((a, b))
+        else:
+            fn()
+
+    for _ in range(args.warmup):
+        star_step()
+    torch.cuda.synchronize()
+    rend.timer = timer
+    ev.clear()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        star_step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    rend.timer = None
+    step_ms = e0.elapsed_time(e1) / args.steps
+    feat_ms = [a.elapsed_time(b) for a, b in ev]
+    log("STAR-NT step %.3f ms (wall %.3f ms/step)" % (step_ms, wall * 1e3 / args.steps))
+
+    # exact path on the same GPU
+    for _ in range(args.warmup):
+        exact_step()
+    torch.cuda.synchronize()
+    x0 = torch.cuda.Event(enable_timing=True)
+    x1 = torch.cuda.Event(enable_timing=True)
+    x0.record()
+    for _ in range(args.steps):
+        exact_step()
+    x1.record()
+    torch.cuda.synchronize()
+    exact_step_ms = x0.elapsed_time(x1) / args.steps
+    log("exact step %.3f ms" % exact_step_ms)
+
+    # quality of the last timed step against the exact composite
+    star_step()
+    torch.cuda.synchronize()
+    psnr, maxerr = [], []
+    for t in range(NF):
+        d = (outs[t] - exact[t]).double()
+        mse = float((d * d).mean())
+        psnr.append(10 * np.log10(1.0 / mse) if mse > 0 else float("inf"))
+        maxerr.append(float(d.abs().max()))
+
+    # per-call breakdown (one extra step with events around every call)
+    names = {}
+
+    def timer_all(name, fn):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        names.setdefault(name, []).append((a, b))
+
+    rend.timer = timer_all
+    for _ in range(3):
+        star_step()
+    torch.cuda.synchronize()
+    rend.timer = None
+    breakdown = {k: round(1e3 * float(np.mean([a.elapsed_time(b) for a, b in v])), 2) for k, v in names.items()}
+
+    # variants: FP32 network, and the plain full-resolution learned path
+    mlp.set_dtype(st.F32)
+    for _ in range(2):
+        star_step()
+    torch.cuda.synchronize()
+    v0 = torch.cuda.Event(enable_timing=True)
+    v1 = torch.cuda.Event(enable_timing=True)
+    v0.record()
+    for _ in range(max(3, args.steps // 4)):
+        star_step()
+    v1.record()
+    torch.cuda.synchronize()
+    fp32_step_ms = v0.elapsed_time(v1) / max(3, args.steps // 4)
+    mlp.set_dtype(st.BF16)
+
+    plain = fm.Renderer(W, H, mlp, base=64, bg=bg)
+
+    def plain_step():
+        for t in range(NF):
+            plain.reset()
+            plain.real_frame(frags[t], outs[t])
+
+    plain_step()
+    torch.cuda.synchronize()
+    p0 = torch.cuda.Event(enable_timing=True)
+    p1 = torch.cuda.Event(enable_timing=True)
+    p0.record()
+    for _ in range(max(3, args.steps // 4)):
+        plain_step()
+    p1.record()
+    torch.cuda.synchronize()
+    plain_step_ms = p0.elapsed_time(p1) / max(3, args.steps // 4)
+    plain_psnr = []
+    for t in range(NF):
+        d = (outs[t] - exact[t]).double()
+        plain_psnr.append(10 * np.log10(1.0 / float((d * d).mean())))
+
+    # ---- roofline of the fragment pass --------------------------------------
+    real_ts = [t for t in range(NF) if t % 2 == 0]
+    per_step = [feature_pass_bytes(host[t], grids[t]) for t in real_ts]
+    alg_bytes = sum(b for b, _ in per_step) * args.steps
+    feat_total_s = sum(feat_ms) / 1e3
+    achieved = alg_bytes / feat_total_s / 1e9
+    frags_read = sum(host[t].num_frags for t in real_ts) * args.steps
+    src = open(os.path.join(ROOT, "paper_2606_16747_amd", "csrc", "features.hip"), "rb").read()
+    traffic = counters_traffic(os.path.join(ROOT, "profiles", "features_c2_1080p_counters.json"),
+                               hashlib.sha256(src).hexdigest())
+
+    total_frags = sum(f.num_frags for f in host)
+    value = total_frags / (step_ms / 1e3) / 1e9
+    res = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gfrag/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {
+            "workload": "1080p sequence: 1920x1080, 2000 seeded triangles, depth complexity mean %.2f max %d, "
+                        "8-frame camera path; quadtree 64->8 px, reprojection on odd frames, BF16 MLP 16-32-32-3"
+                        % (np.mean([f.stats["mean_count"] for f in host]), max(f.stats["max_count"] for f in host)),
+            "frames_per_step": NF,
+            "fragments_per_step": total_frags,
+            "pixels": P,
+        },
+        "ms_per_frame": round(step_ms / NF, 4),
+        "mpixel_per_s": round(P * NF / (step_ms / 1e3) / 1e6, 1),
+        "exact_ms_per_frame": round(exact_step_ms / NF, 4),
+        "exact_gfrag_per_s": round(total_frags / (exact_step_ms / 1e3) / 1e9, 3),
+        "speedup_vs_exact": round(exact_step_ms / step_ms, 3),
+        "psnr_db": {"min": round(min(psnr), 2), "mean": round(float(np.mean(psnr)), 2),
+                    "per_frame": [round(v, 2) for v in psnr]},
+        "max_abs_err": round(max(maxerr), 4),
+        "kernel_gfrag_per_s": round(frags_read / feat_total_s / 1e9, 2),
+        "kernels_us": breakdown,
+        "grids": {str(k): v for k, v in grids.items()},
+        "fp32_mlp_ms_per_frame": round(fp32_step_ms / NF, 4),
+        "plain_fullres_ms_per_frame": round(plain_step_ms / NF, 4),
+        "plain_fullres_psnr_db_mean": round(float(np.mean(plain_psnr)), 2),
+        "train": {"steps": args.train_steps, "batch": 65536, "pairs": int(len(x)), "seconds": round(train_s, 3),
+                  "loss_first": float(losses[0]), "loss_last": float(losses[-1])},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "starnt_features (passes 1-3)",
+                     "algorithmic_bytes_per_launch": int(alg_bytes / args.steps / len(real_ts)),
+                     "avg_launch_us": round(1e3 * float(np.mean(feat_ms)), 2)},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        res["cpu_baseline"] = cpu_baseline(host[0], host[1], Ws, bs, bg, args.cpu_budget)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

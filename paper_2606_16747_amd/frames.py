@@ -1,0 +1,87 @@
+"""Frame scheduler of STAR-NT (Sec. 3, Fig. 1; interpolated frames Sec. 3.3).
+
+A real frame runs passes 1-3 on the grids the device schedule holds, the tail
+network, the eq (3) composite and the quadtree update, which leaves the next
+frame's grids in the schedule (eq (4)); no host round trip is needed between
+frames. An interpolated frame is one reprojection gather from the last real
+frame. Every step is a libstarnt call on the caller's stream.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import (MODE_EXACT, MODE_LEARNED, WS_QUADTREE, DeviceFrags, DeviceMlp, FeatBuffers, QtParams,
+               starnt_composite, starnt_features, starnt_infer, starnt_quadtree, starnt_reproject,
+               starnt_sched_init, starnt_workspace_size, workspace)
+
+
+def m_minus_i(vp_real, vp_cur):
+    """M - I with M = VP_real VP_cur^-1 (FP64 on the host, then FP32)."""
+    M = np.asarray(vp_real, np.float64).reshape(4, 4) @ np.linalg.inv(np.asarray(vp_cur, np.float64).reshape(4, 4))
+    return (M - np.eye(4)).astype(np.float32)
+
+
+class Renderer:
+    """Buffers and calls for one frame size. Outputs are [P, 3] float32."""
+
+    def __init__(self, width, height, mlp: DeviceMlp, base=64, tau_split=0.10, tau_merge=0.05, k_relax=2,
+                 bg=(1.0, 1.0, 1.0), device="cuda", mode=MODE_LEARNED):
+        self.W, self.H = int(width), int(height)
+        P = self.W * self.H
+        self.mlp = mlp
+        self.mode = mode
+        self.bg = tuple(float(v) for v in bg)
+        self.qp = QtParams(int(base), float(tau_split), float(tau_merge), int(k_relax))
+        self.feats = FeatBuffers(self.W, self.H, device)
+        self.tail_rgb = torch.zeros(P, 3, dtype=torch.float32, device=device)
+        self.sched = torch.zeros(16, dtype=torch.int32, device=device)
+        T = ((self.W + base - 1) // base) * ((self.H + base - 1) // base)
+        cs = base // 8
+        C = ((self.W + cs - 1) // cs) * ((self.H + cs - 1) // cs)
+        self.masks = [torch.zeros(T, dtype=torch.int32, device=device) for _ in range(2)]
+        self.level = torch.zeros(C, dtype=torch.uint8, device=device)
+        self.ws = workspace(starnt_workspace_size(WS_QUADTREE, self.W, self.H, base), device)
+        self.rgb_real = None
+        self.n_real = 0
+        self.timer = None  # optional callable(name, fn) wrapping each call
+
+    def _call(self, name, fn):
+        if self.timer is None:
+            fn()
+        else:
+            self.timer(name, fn)
+
+    def reset(self, stream=None):
+        """Start a sequence: full-resolution grids, no quadtree history."""
+        starnt_sched_init(self.sched, self.W, self.H, 1.0, 1.0, stream)
+        self.n_real = 0
+        self.rgb_real = None
+
+    def real_frame(self, frags: DeviceFrags, out, stream=None):
+        self._call("features", lambda: starnt_features(frags, self.sched, self.feats, stream))
+        if self.mode == MODE_LEARNED:
+            self._call("infer", lambda: starnt_infer(self.mlp, self.feats.tail, self.feats.count, self.sched, self.W,
+                                                     self.H, self.tail_rgb, stream))
+        self._call("composite", lambda: starnt_composite(frags, self.feats, self.tail_rgb, self.sched, self.bg,
+                                                         self.mode, out, None, stream))
+        prev = None if self.n_real == 0 else self.masks[(self.n_real - 1) % 2]
+        cur = self.masks[self.n_real % 2]
+        self._call("quadtree", lambda: starnt_quadtree(out, self.feats.count, self.W, self.H, self.qp, prev, cur,
+                                                       self.level, self.sched, self.ws, stream))
+        # feats.d1 keeps this frame's first-fragment depth until the next real
+        # frame overwrites it, which stream order places after the gathers
+        self.rgb_real = out
+        self.n_real += 1
+        return out
+
+    def interpolated_frame(self, mmi, out, stream=None):
+        assert self.rgb_real is not None, "an interpolated frame needs a real frame before it"
+        self._call("reproject", lambda: starnt_reproject(self.rgb_real, self.feats.d1, self.W, self.H, mmi, out, None,
+                                                         stream))
+        return out
+
+
+def exact_frame(frags: DeviceFrags, out, bg=(1.0, 1.0, 1.0), fstar=None, stream=None):
+    starnt_composite(frags, None, None, None, bg, MODE_EXACT, out, fstar, stream)
+    return out

@@ -1,0 +1,95 @@
+"""Training driver for the tail-colour network (Sec. 3.3: MSE, Adam).
+
+Pairs (x, f*) come from the library itself: starnt_features gives the five
+features at full resolution and the exact A-buffer path gives the exact tail
+colour f* of every pixel with at least three fragments. Inputs are
+standardised for training; the affine map is folded into layer 1 afterwards,
+so inference sees raw features. Every gradient step is starnt_train_step.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import (BF16, F32, WS_TRAIN, Adam, DeviceFrags, DeviceMlp, FeatBuffers, Train, starnt_features,
+               starnt_train_step, starnt_workspace_size, workspace)
+from .frames import exact_frame
+
+
+def pairs_from(frags: DeviceFrags, bg=(1.0, 1.0, 1.0)):
+    """(x [M, 16], f* [M, 3]) on the host for the pixels with N >= 3."""
+    fb = FeatBuffers(frags.width, frags.height)
+    starnt_features(frags, None, fb)
+    P = frags.width * frags.height
+    rgb = torch.empty(P, 3, dtype=torch.float32, device=fb.d1.device)
+    fstar = torch.empty(P, 3, dtype=torch.float32, device=fb.d1.device)
+    exact_frame(frags, rgb, bg, fstar)
+    torch.cuda.synchronize()
+    n = fb.count.cpu().numpy()
+    keep = n >= 3
+    x = np.zeros((int(keep.sum()), 16), np.float32)
+    x[:, :5] = fb.tail.cpu().numpy()[keep, :5]
+    return x, fstar.cpu().numpy()[keep]
+
+
+class Standardiser:
+    def __init__(self, x):
+        self.mu = np.zeros(16)
+        self.sd = np.ones(16)
+        self.mu[:5] = x[:, :5].mean(0)
+        self.sd[:5] = np.maximum(x[:, :5].std(0), 1e-6)
+
+    def apply(self, x):
+        return ((x - self.mu) / self.sd).astype(np.float32)
+
+    def fold(self, W1, b1):
+        """Layer 1 on raw x equal to layer 1 on standardised x."""
+        W = W1 / self.sd[None, :]
+        b = b1 - (W1 * (self.mu / self.sd)[None, :]).sum(1)
+        return W.astype(np.float32), b.astype(np.float32)
+
+
+def train(x, y, Ws, bs, steps=3000, batch=65536, lr=2e-3, lr_min=1e-4, dtype=BF16, seed=0, log_every=0,
+          device="cuda", stream=None):
+    """Train from initial weights (Ws, bs); returns (Ws, bs, losses) with the
+    standardisation folded into layer 1."""
+    dims = (Ws[0].shape[1], Ws[0].shape[0], Ws[1].shape[0], Ws[2].shape[0])
+    st = Standardiser(x)
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(len(x))
+    xs = torch.from_numpy(st.apply(x[order])).to(device)
+    ys = torch.from_numpy(np.ascontiguousarray(y[order], np.float32)).to(device)
+    M = len(x)
+    batch = min(batch, M)
+    nb = M // batch
+    flat = np.concatenate([np.concatenate([np.asarray(w, np.float32).ravel(), np.asarray(b, np.float32).ravel()])
+                           for w, b in zip(Ws, bs)])
+    p = torch.from_numpy(flat).to(device)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    g = torch.zeros_like(p)
+    tr = Train(16, dims[1], dims[2], 3, dtype, p.data_ptr(), m.data_ptr(), v.data_ptr(), g.data_ptr())
+    ws = workspace(starnt_workspace_size(WS_TRAIN, batch, dims[1], dims[2]), device)
+    loss = torch.zeros(steps, dtype=torch.float32, device=device)
+    for t in range(steps):
+        b = int(rng.integers(nb))
+        lr_t = lr_min + 0.5 * (lr - lr_min) * (1 + np.cos(np.pi * t / max(1, steps)))
+        ad = Adam(lr_t, 0.9, 0.999, 1e-8, t + 1)
+        xb = xs[b * batch:(b + 1) * batch]
+        yb = ys[b * batch:(b + 1) * batch]
+        starnt_train_step(tr, xb, yb, batch, ad, loss[t:t + 1], ws, stream)
+        if log_every and (t % log_every == 0 or t == steps - 1):
+            torch.cuda.synchronize()
+            print("step %d loss %.3e" % (t, float(loss[t])), flush=True)
+    torch.cuda.synchronize()
+    out = p.cpu().numpy()
+    i, h1, h2, o = dims
+    k = 0
+    shapes = [(h1, i), (h1,), (h2, h1), (h2,), (o, h2), (o,)]
+    parts = []
+    for s in shapes:
+        n = int(np.prod(s))
+        parts.append(out[k:k + n].reshape(s))
+        k += n
+    W1, b1 = st.fold(parts[0].astype(np.float64), parts[1].astype(np.float64))
+    return [W1, parts[2], parts[4]], [b1, parts[3], parts[5]], loss.cpu().numpy()

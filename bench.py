@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--train-scenes", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
@@ -301,6 +303,13 @@ def main():
     for t in range(NF):
         d = (outs[t] - exact[t]).double()
         plain_psnr.append(10 * np.log10(1.0 / float((d * d).mean())))
+
+    if args.calib_copy_mb:
+        src_t = torch.ones(args.calib_copy_mb * (1 << 20) // 4, dtype=torch.float32, device=dev)
+        dst_t = torch.empty_like(src_t)
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        del src_t, dst_t
 
     # ---- roofline of the fragment pass --------------------------------------
     real_ts = [t for t in range(NF) if t % 2 == 0]

@@ -12,7 +12,8 @@
  *                     statistics and the five network features on the pass-3
  *                     grid (Sec. 3.2-3.3)
  *   starnt_infer      tail-colour network f(x) at full resolution over the
- *                     bilinearly upscaled pass-3 features (Sec. 3.2-3.3)
+ *                     bilinearly upscaled pass-3 features (Sec. 3.2-3.3);
+ *                     starnt_infer_composite fuses it with eq (3)
  *   starnt_composite  eq (3), C = C_exact,2 + T2 f(x) + prod(1-a) C_b, with the
  *                     upscaled pass-2 layer; or the exact A-buffer composite
  *                     (eq (1) after a per-pixel sort; the paper's ground truth)
@@ -180,6 +181,13 @@ int starnt_features(const starnt_frags* frags, const starnt_sched* sched, const 
  * tail_rgb[p] = f(x); tail_rgb[p] = 0 where count < 3. tail_rgb is [P][3]. */
 int starnt_infer(const starnt_mlp* mlp, const float* tail, const uint32_t* count, const starnt_sched* sched,
                  int32_t width, int32_t height, float* tail_rgb, void* stream);
+
+/* starnt_infer followed by starnt_composite(STARNT_MODE_LEARNED) in one pass
+ * (same results): per pixel the upscaled features feed the network and its
+ * output goes straight into eq (3), so the tail colour is never stored.
+ * Frame size from feats; rgb is [P][3]; bg is a host float[3]. */
+int starnt_infer_composite(const starnt_mlp* mlp, const starnt_feats* feats, const starnt_sched* sched,
+                           const float* bg, float* rgb, void* stream);
 
 /* Final colour rgb [P][3].
  * MODE_LEARNED / F0 / FAVG (eq (3), Sec. 3.3): with layer 2 and x upscaled

@@ -74,7 +74,7 @@ class Adam(ctypes.Structure):
 
 assert ctypes.sizeof(Sched) == 64
 
-EXPORTS = ("starnt_features", "starnt_infer", "starnt_composite", "starnt_quadtree", "starnt_reproject",
+EXPORTS = ("starnt_features", "starnt_infer", "starnt_infer_composite", "starnt_composite", "starnt_quadtree", "starnt_reproject",
            "starnt_train_step", "starnt_sched_init", "starnt_wbar", "starnt_pass_scales", "starnt_grid_dim",
            "starnt_workspace_size", "starnt_check", "starnt_last_error", "starnt_version")
 
@@ -85,6 +85,8 @@ def _load():
     lib = ctypes.CDLL(LIB_PATH)
     lib.starnt_features.argtypes = [ctypes.POINTER(Frags), _P, ctypes.POINTER(Feats), _P]
     lib.starnt_infer.argtypes = [ctypes.POINTER(Mlp), _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]
+    lib.starnt_infer_composite.argtypes = [ctypes.POINTER(Mlp), ctypes.POINTER(Feats), _P,
+                                           ctypes.POINTER(ctypes.c_float), _P, _P]
     lib.starnt_composite.argtypes = [ctypes.POINTER(Frags), ctypes.POINTER(Feats), _P, _P,
                                      ctypes.POINTER(ctypes.c_float), ctypes.c_int32, _P, _P, _P]
     lib.starnt_quadtree.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(QtParams), _P, _P, _P,
@@ -238,6 +240,12 @@ def starnt_features(frags: DeviceFrags, sched, feats: FeatBuffers, stream=None):
 def starnt_infer(mlp: DeviceMlp, tail, count, sched, width, height, tail_rgb, stream=None):
     _check(lib.starnt_infer(ctypes.byref(mlp._c), _ptr(tail), _ptr(count), _ptr(sched), int(width), int(height),
                             _ptr(tail_rgb), _stream(stream)))
+
+
+def starnt_infer_composite(mlp: DeviceMlp, feats: FeatBuffers, sched, bg, rgb, stream=None):
+    bgc = (ctypes.c_float * 3)(*[float(v) for v in bg])
+    _check(lib.starnt_infer_composite(ctypes.byref(mlp._c), ctypes.byref(feats._c), _ptr(sched), bgc, _ptr(rgb),
+                                      _stream(stream)))
 
 
 def starnt_composite(frags, feats, tail_rgb, sched, bg, mode, rgb, fstar=None, stream=None):

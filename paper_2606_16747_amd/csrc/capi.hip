@@ -49,6 +49,24 @@ int check_frags(const starnt_frags* f, const char* who) {
   return STARNT_OK;
 }
 
+int check_mlp(const starnt_mlp* mlp, const char* who) {
+  const std::string w(who);
+  if (!mlp) return fail(STARNT_EINVAL, w + ": NULL network");
+  if (mlp->in != 16 || mlp->out != 3) return fail(STARNT_EINVAL, w + ": the network must have in = 16 and out = 3");
+  if (mlp->h1 < 1 || mlp->h1 > 64 || mlp->h2 < 1 || mlp->h2 > 64)
+    return fail(STARNT_EINVAL, w + ": hidden widths must be in [1, 64]");
+  if (!mlp->W1 || !mlp->b1 || !mlp->W2 || !mlp->b2 || !mlp->W3 || !mlp->b3)
+    return fail(STARNT_EINVAL, w + ": NULL weight array");
+  if (mlp->dtype != STARNT_F32 && mlp->dtype != STARNT_BF16 && mlp->dtype != STARNT_FP8)
+    return fail(STARNT_EINVAL, w + ": dtype must be STARNT_F32, STARNT_BF16 or STARNT_FP8");
+  if (mlp->dtype == STARNT_FP8 && !mlp->fp8_scales) return fail(STARNT_EINVAL, w + ": FP8 needs fp8_scales");
+  if (mlp->fp8_scales)
+    for (int i = 0; i < 6; ++i)
+      if (!(mlp->fp8_scales[i] > 0.0f) || !std::isfinite(mlp->fp8_scales[i]))
+        return fail(STARNT_EINVAL, w + ": fp8 scales must be finite and positive");
+  return STARNT_OK;
+}
+
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 }  // namespace
@@ -70,20 +88,22 @@ int starnt_infer(const starnt_mlp* mlp, const float* tail, const uint32_t* count
                  int32_t width, int32_t height, float* tail_rgb, void* stream) {
   int rc = check_frame(width, height, "starnt_infer");
   if (rc) return rc;
-  if (!mlp || !tail || !count || !tail_rgb) return fail(STARNT_EINVAL, "starnt_infer: NULL argument");
-  if (mlp->in != 16 || mlp->out != 3)
-    return fail(STARNT_EINVAL, "starnt_infer: the network must have in = 16 and out = 3");
-  if (mlp->h1 < 1 || mlp->h1 > 64 || mlp->h2 < 1 || mlp->h2 > 64)
-    return fail(STARNT_EINVAL, "starnt_infer: hidden widths must be in [1, 64]");
-  if (!mlp->W1 || !mlp->b1 || !mlp->W2 || !mlp->b2 || !mlp->W3 || !mlp->b3)
-    return fail(STARNT_EINVAL, "starnt_infer: NULL weight array");
-  if (mlp->dtype == STARNT_FP8 && !mlp->fp8_scales)
-    return fail(STARNT_EINVAL, "starnt_infer: FP8 needs fp8_scales");
-  if (mlp->fp8_scales)
-    for (int i = 0; i < 6; ++i)
-      if (!(mlp->fp8_scales[i] > 0.0f) || !std::isfinite(mlp->fp8_scales[i]))
-        return fail(STARNT_EINVAL, "starnt_infer: fp8 scales must be finite and positive");
+  if (!tail || !count || !tail_rgb) return fail(STARNT_EINVAL, "starnt_infer: NULL argument");
+  rc = check_mlp(mlp, "starnt_infer");
+  if (rc) return rc;
   return launch_infer(*mlp, tail, count, sched, width, height, tail_rgb, as_stream(stream));
+}
+
+int starnt_infer_composite(const starnt_mlp* mlp, const starnt_feats* feats, const starnt_sched* sched,
+                           const float* bg, float* rgb, void* stream) {
+  if (!feats) return fail(STARNT_EINVAL, "starnt_infer_composite: NULL feats");
+  int rc = check_frame(feats->width, feats->height, "starnt_infer_composite");
+  if (rc) return rc;
+  if (!bg || !rgb || !feats->layer1 || !feats->count || !feats->layer2 || !feats->tail)
+    return fail(STARNT_EINVAL, "starnt_infer_composite: NULL argument");
+  rc = check_mlp(mlp, "starnt_infer_composite");
+  if (rc) return rc;
+  return launch_infer_composite(*mlp, *feats, sched, bg, rgb, as_stream(stream));
 }
 
 int starnt_composite(const starnt_frags* frags, const starnt_feats* feats, const float* tail_rgb,

@@ -1,6 +1,8 @@
 // Tail-colour network f(x) of STAR-NT (Sec. 3.3) at full resolution, over the
 // bilinearly upscaled pass-3 features (Sec. 3.2). Three dense layers with ReLU
 // after each; x = (N, t_tail, Ct_rgb) plus zero padding to 16 inputs.
+// Optionally fused with the eq (3) composite (starnt_infer_composite), which
+// saves writing and re-reading the tail colour and the second feature fetch.
 //
 // Paths:
 //  * STARNT_F32  : one thread per pixel, FP32 FMAs, weights read with
@@ -10,11 +12,15 @@
 //                  is H^T = W H_prev^T. The hidden units of layer 1 are stored
 //                  in a permuted order chosen so that each lane's accumulator
 //                  registers of layer 1 are exactly its B-operand registers of
-//                  layer 2: no data moves between lanes. The 3-wide output
-//                  layer runs on the VALU from bf16-rounded operands.
-//  * STARNT_FP8  : the same structure with E4M3 operands and per-layer scales
-//                  (v_mfma_f32_32x32x64_f8f6f4 is not needed: K = 16 per step
-//                  uses v_mfma_f32_32x32x16_fp8_fp8).
+//                  layer 2 (and layer 2's of layer 3): no data moves between
+//                  lanes. The 3-wide output layer is a 32-row tile with
+//                  rows 0..2 live.
+//  * STARNT_FP8  : the same structure with OCP E4M3 operands and per-layer
+//                  scales on v_mfma_f32_32x32x16_fp8_fp8.
+// Weights are staged once per block in LDS; blocks are persistent and walk
+// 64-pixel steps.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace starnt {
@@ -24,6 +30,8 @@ struct InferArgs {
   int W, H;
   const float4* tail;
   const uint32_t* count;
+  const float4* layer1;
+  const float4* layer2;
   const starnt_sched* sched;
   const float* __restrict__ W1;
   const float* __restrict__ b1;
@@ -33,52 +41,131 @@ struct InferArgs {
   const float* __restrict__ b3;
   int in, h1, h2;
   float sa[3], sw[3];  // FP8 scales
-  float* out;
+  float bg0, bg1, bg2;
+  float* out;          // tail colour [P][3] or composite rgb [P][3]
 };
 
-// upscaled features x0..x4 of full-resolution pixel (x, y)
-__device__ __forceinline__ void fetch_x(const InferArgs& a, const Grids& g, int x, int y, float v[5]) {
+// inputs of one pixel for the network and the composite
+struct PixIn {
+  uint32_t n;
+  float x[5];          // upscaled features (n >= 3)
+  float4 l1;           // layer 1 (composite only)
+  float4 l2;           // upscaled layer 2 (composite only)
+};
+
+__device__ __forceinline__ float lerp1(float p, float q, float w) { return fmaf(w, q - p, p); }
+__device__ __forceinline__ float4 lerp4(float4 a, float4 b, float w) {
+  return make_float4(lerp1(a.x, b.x, w), lerp1(a.y, b.y, w), lerp1(a.z, b.z, w), lerp1(a.w, b.w, w));
+}
+
+// Raw inputs of one pixel: all loads are issued up front, independent of the
+// loaded values, so a prefetched group costs one memory round trip.
+struct PixRaw {
+  uint32_t n;
+  float4 t[4];   // x0..x3 of the four pass-3 taps
+  float t4[4];   // x4 of the four taps
+  float4 l1;
+  float4 l2[4];  // the four pass-2 taps
+  float wx3, wy3, wx2, wy2;
+};
+
+template <bool COMP>
+__device__ __forceinline__ void issue_loads(const InferArgs& a, const Grids& g, int p, PixRaw& r) {
+  r.n = a.count[p];
+  const int x = p % a.W, y = p / a.W;
   const Taps tx = axis_taps(x, a.W, g.w3), ty = axis_taps(y, a.H, g.h3);
-  const size_t i00 = (size_t)ty.i0 * g.w3 + tx.i0, i01 = (size_t)ty.i0 * g.w3 + tx.i1;
-  const size_t i10 = (size_t)ty.i1 * g.w3 + tx.i0, i11 = (size_t)ty.i1 * g.w3 + tx.i1;
-  const float4 a00 = a.tail[2 * i00], c00 = a.tail[2 * i00 + 1];
-  float4 r0 = a00;
-  float r4 = c00.x;
-  if (tx.w1 != 0.0f || ty.w1 != 0.0f) {
-    const float4 a01 = a.tail[2 * i01], c01 = a.tail[2 * i01 + 1];
-    const float4 a10 = a.tail[2 * i10], c10 = a.tail[2 * i10 + 1];
-    const float4 a11 = a.tail[2 * i11], c11 = a.tail[2 * i11 + 1];
-    const float wx = tx.w1, wy = ty.w1;
-    auto l = [](float p, float q, float w) { return fmaf(w, q - p, p); };
-    r0.x = l(l(a00.x, a01.x, wx), l(a10.x, a11.x, wx), wy);
-    r0.y = l(l(a00.y, a01.y, wx), l(a10.y, a11.y, wx), wy);
-    r0.z = l(l(a00.z, a01.z, wx), l(a10.z, a11.z, wx), wy);
-    r0.w = l(l(a00.w, a01.w, wx), l(a10.w, a11.w, wx), wy);
-    r4 = l(l(c00.x, c01.x, wx), l(c10.x, c11.x, wx), wy);
+  const size_t i3[4] = {(size_t)ty.i0 * g.w3 + tx.i0, (size_t)ty.i0 * g.w3 + tx.i1,
+                        (size_t)ty.i1 * g.w3 + tx.i0, (size_t)ty.i1 * g.w3 + tx.i1};
+  // a full-resolution grid needs only the pixel's own sample (weights 0);
+  // the test is uniform across the wave
+  const int taps3 = (g.w3 == a.W && g.h3 == a.H) ? 1 : 4;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const size_t i = i3[k < taps3 ? k : 0];
+    r.t[k] = a.tail[2 * i];
+    r.t4[k] = a.tail[2 * i + 1].x;
   }
-  v[0] = r0.x; v[1] = r0.y; v[2] = r0.z; v[3] = r0.w; v[4] = r4;
+  r.wx3 = tx.w1;
+  r.wy3 = ty.w1;
+  if constexpr (COMP) {
+    r.l1 = a.layer1[p];
+    const Taps ux = axis_taps(x, a.W, g.w2), uy = axis_taps(y, a.H, g.h2);
+    const size_t i2[4] = {(size_t)uy.i0 * g.w2 + ux.i0, (size_t)uy.i0 * g.w2 + ux.i1,
+                          (size_t)uy.i1 * g.w2 + ux.i0, (size_t)uy.i1 * g.w2 + ux.i1};
+    const int taps2 = (g.w2 == a.W && g.h2 == a.H) ? 1 : 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r.l2[k] = a.layer2[i2[k < taps2 ? k : 0]];
+    r.wx2 = ux.w1;
+    r.wy2 = uy.w1;
+  }
+}
+
+// bilinear blend of the raw taps; the full-resolution count gates the terms
+template <bool COMP>
+__device__ __forceinline__ PixIn blend(const PixRaw& r) {
+  PixIn in;
+  in.n = r.n;
+  if (r.n >= 3) {
+    const float4 v = lerp4(lerp4(r.t[0], r.t[1], r.wx3), lerp4(r.t[2], r.t[3], r.wx3), r.wy3);
+    in.x[0] = v.x; in.x[1] = v.y; in.x[2] = v.z; in.x[3] = v.w;
+    in.x[4] = lerp1(lerp1(r.t4[0], r.t4[1], r.wx3), lerp1(r.t4[2], r.t4[3], r.wx3), r.wy3);
+  } else {
+    in.x[0] = in.x[1] = in.x[2] = in.x[3] = in.x[4] = 0.0f;
+  }
+  if constexpr (COMP) {
+    in.l1 = r.l1;
+    in.l2 = r.n >= 2 ? lerp4(lerp4(r.l2[0], r.l2[1], r.wx2), lerp4(r.l2[2], r.l2[3], r.wx2), r.wy2)
+                     : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  return in;
+}
+
+template <bool COMP>
+__device__ __forceinline__ void load_pixel(const InferArgs& a, const Grids& g, int p, bool, PixIn& in) {
+  PixRaw r;
+  issue_loads<COMP>(a, g, p, r);
+  in = blend<COMP>(r);
+}
+
+// write the tail colour, or the eq (3) composite with it
+template <bool COMP>
+__device__ __forceinline__ void store_pixel(const InferArgs& a, int p, const PixIn& in, float f0, float f1, float f2) {
+  const bool on = in.n >= 3;
+  if (!on) { f0 = f1 = f2 = 0.0f; }
+  if constexpr (COMP) {
+    const float tt = on ? in.x[1] : 1.0f;
+    const float om1 = 1.0f - in.l1.w;
+    const float T2 = om1 * (1.0f - in.l2.w);
+    const float Tb = T2 * tt;
+    a.out[3 * (size_t)p + 0] = in.l1.x + om1 * in.l2.x + T2 * f0 + Tb * a.bg0;
+    a.out[3 * (size_t)p + 1] = in.l1.y + om1 * in.l2.y + T2 * f1 + Tb * a.bg1;
+    a.out[3 * (size_t)p + 2] = in.l1.z + om1 * in.l2.z + T2 * f2 + Tb * a.bg2;
+  } else {
+    a.out[3 * (size_t)p + 0] = f0;
+    a.out[3 * (size_t)p + 1] = f1;
+    a.out[3 * (size_t)p + 2] = f2;
+  }
 }
 
 // ---------------------------------------------------------------------------
 // FP32 VALU path
 
-template <int H1, int H2>
+template <int H1, int H2, bool COMP>
 __global__ __launch_bounds__(256) void infer_f32_kernel(InferArgs a) {
   const int P = a.W * a.H;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
-  const uint32_t n = a.count[p];
+  const Grids g = load_grids(a.sched, a.W, a.H);
+  PixIn in;
+  load_pixel<COMP>(a, g, p, true, in);
   float o0 = 0.f, o1 = 0.f, o2 = 0.f;
-  if (n >= 3) {
-    const Grids g = load_grids(a.sched, a.W, a.H);
-    float x[5];
-    fetch_x(a, g, p % a.W, p / a.W, x);
+  if (in.n >= 3) {
     float h1[H1];
 #pragma unroll
     for (int j = 0; j < H1; ++j) {
       float s = a.b1[j];
 #pragma unroll
-      for (int i = 0; i < 5; ++i) s = fmaf(a.W1[j * a.in + i], x[i], s);
+      for (int i = 0; i < 5; ++i) s = fmaf(a.W1[j * a.in + i], in.x[i], s);
       h1[j] = fmaxf(s, 0.0f);
     }
     float h2[H2];
@@ -100,19 +187,23 @@ __global__ __launch_bounds__(256) void infer_f32_kernel(InferArgs a) {
     o1 = fmaxf(s1, 0.0f);
     o2 = fmaxf(s2, 0.0f);
   }
-  a.out[3 * (size_t)p + 0] = o0;
-  a.out[3 * (size_t)p + 1] = o1;
-  a.out[3 * (size_t)p + 2] = o2;
+  store_pixel<COMP>(a, p, in, o0, o1, o2);
 }
 
 // ---------------------------------------------------------------------------
-// BF16 matrix-core path
+// matrix-core paths (BF16 and FP8)
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+typedef long fp8x8;  // 8 E4M3 bytes
 
-__device__ __forceinline__ __bf16 to_bf16(float v) { return static_cast<__bf16>(v); }
-__device__ __forceinline__ float bf16_round(float v) { return static_cast<float>(static_cast<__bf16>(v)); }
+// OCP E4M3 with round-to-nearest-even and saturation (hardware convert)
+__device__ __forceinline__ uint32_t e4m3_pack4(float a, float b, float c, float d) {
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+  w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+  return (uint32_t)w;
+}
+__device__ __forceinline__ float sat448(float v) { return fminf(fmaxf(v, -448.0f), 448.0f); }
 
 // Physical accumulator row r of a 32-row tile (lane half h = (r % 8) / 4,
 // block b = r / 8, element i = r % 4) holds logical hidden unit
@@ -124,10 +215,62 @@ __device__ __forceinline__ int perm_row(int r) {
   return 16 * (b >> 1) + 8 * h + 4 * (b & 1) + i;
 }
 
+template <bool FP8>
+struct Op {
+  using vec = typename std::conditional<FP8, fp8x8, bf16x8>::type;
+};
+
+template <bool FP8>
+__device__ __forceinline__ void set8(typename Op<FP8>::vec& v, const float* w, float scale_inv) {
+  if constexpr (FP8) {
+    const uint32_t lo = e4m3_pack4(sat448(w[0] * scale_inv), sat448(w[1] * scale_inv), sat448(w[2] * scale_inv),
+                                   sat448(w[3] * scale_inv));
+    const uint32_t hi = e4m3_pack4(sat448(w[4] * scale_inv), sat448(w[5] * scale_inv), sat448(w[6] * scale_inv),
+                                   sat448(w[7] * scale_inv));
+    v = (long)(((unsigned long)hi << 32) | lo);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = static_cast<__bf16>(w[e]);
+  }
+}
+
+template <bool FP8>
+__device__ __forceinline__ f32x16 mfma(const typename Op<FP8>::vec& A, const typename Op<FP8>::vec& B, f32x16 c) {
+  if constexpr (FP8) return __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(A, B, c, 0, 0, 0);
+  else return __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, c, 0, 0, 0);
+}
+
+constexpr int kMaxParams = 64 * 16 + 64 + 64 * 64 + 64 + 3 * 64 + 3;
+
 // T1, T2: number of 32-row tiles of the two hidden layers (h padded with zero
-// weights up to 32 * T).
-template <int T1, int T2>
-__global__ __launch_bounds__(256) void infer_bf16_kernel(InferArgs a) {
+// weights up to 32 * T). All three layers run on the matrix cores; the rows of
+// both hidden layers are stored permuted (perm_row) so each layer's
+// accumulators are the next layer's B operand in place. The 3-wide output
+// layer is a 32-row tile with rows 0..2 live: lane half 0 holds a pixel's
+// three outputs in accumulator registers 0..2.
+// A wave step covers 64 pixels: every lane loads its own pixel, the second
+// 32-pixel group's inputs cross to lane half 0 with one xor-32 shuffle, and
+// its outputs cross back the same way.
+template <int T1, int T2, bool FP8, bool COMP>
+__global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
+  __shared__ float s_w[kMaxParams];
+  using V = typename Op<FP8>::vec;
+  // stage weights: W1 [h1][16], b1, W2 [h2][h1], b2, W3 [3][h2], b3
+  const int nW1 = a.h1 * 16, nW2 = a.h2 * a.h1, nW3 = 3 * a.h2;
+  float* sW1 = s_w;
+  float* sb1 = sW1 + nW1;
+  float* sW2 = sb1 + a.h1;
+  float* sb2 = sW2 + nW2;
+  float* sW3 = sb2 + a.h2;
+  float* sb3 = sW3 + nW3;
+  for (int i = threadIdx.x; i < nW1; i += blockDim.x) sW1[i] = a.W1[i];
+  for (int i = threadIdx.x; i < a.h1; i += blockDim.x) sb1[i] = a.b1[i];
+  for (int i = threadIdx.x; i < nW2; i += blockDim.x) sW2[i] = a.W2[i];
+  for (int i = threadIdx.x; i < a.h2; i += blockDim.x) sb2[i] = a.b2[i];
+  for (int i = threadIdx.x; i < nW3; i += blockDim.x) sW3[i] = a.W3[i];
+  for (int i = threadIdx.x; i < 3; i += blockDim.x) sb3[i] = a.b3[i];
+  __syncthreads();
+
   const int lane = threadIdx.x & 63;
   const int half = lane >> 5;
   const int col = lane & 31;
@@ -135,143 +278,195 @@ __global__ __launch_bounds__(256) void infer_bf16_kernel(InferArgs a) {
   const int wave = blockIdx.x * waves_per_block + (threadIdx.x >> 6);
   const int nwaves = gridDim.x * waves_per_block;
   const int P = a.W * a.H;
-  const int ngroups = (P + 31) / 32;
+  const int nsteps = (P + 63) / 64;
   const Grids g = load_grids(a.sched, a.W, a.H);
+  // FP8: activation scale of each layer's input, inverse weight scale, and
+  // the dequantisation factor sa * sw of each layer's products
+  const float ia0 = FP8 ? 1.0f / a.sa[0] : 1.0f, ia1 = FP8 ? 1.0f / a.sa[1] : 1.0f;
+  const float ia2 = FP8 ? 1.0f / a.sa[2] : 1.0f;
+  const float iw0 = FP8 ? 1.0f / a.sw[0] : 1.0f, iw1 = FP8 ? 1.0f / a.sw[1] : 1.0f;
+  const float iw2 = FP8 ? 1.0f / a.sw[2] : 1.0f;
+  const float dq0 = FP8 ? a.sa[0] * a.sw[0] : 1.0f, dq1 = FP8 ? a.sa[1] * a.sw[1] : 1.0f;
+  const float dq2 = FP8 ? a.sa[2] * a.sw[2] : 1.0f;
 
   // ---- weights into registers, in operand layout ----
-  // layer 1 A operand: tile t, physical row `col`, inputs 8*half .. 8*half+7
-  bf16x8 A1[T1];
-  f32x16 B1v[T1];  // bias per accumulator register
+  // layer 1: tile t, physical row `col` = hidden unit 32 t + perm_row(col)
+  V A1[T1];
+  f32x16 B1v[T1];
 #pragma unroll
   for (int t = 0; t < T1; ++t) {
     const int u = 32 * t + perm_row(col);
+    float w[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int k = 8 * half + e;
-      const float w = (u < a.h1 && k < 5) ? a.W1[u * a.in + k] : 0.0f;
-      A1[t][e] = to_bf16(w);
+      w[e] = (u < a.h1 && k < 5) ? sW1[u * 16 + k] : 0.0f;
     }
+    set8<FP8>(A1[t], w, iw0);
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const int r = 8 * (v >> 2) + 4 * half + (v & 3);
-      const int uu = 32 * t + perm_row(r);
-      B1v[t][v] = uu < a.h1 ? a.b1[uu] : 0.0f;
+      const int uu = 32 * t + perm_row(8 * (v >> 2) + 4 * half + (v & 3));
+      B1v[t][v] = uu < a.h1 ? sb1[uu] : 0.0f;
     }
   }
-  // layer 2 A operand: tile t2 (rows = h2 units 32 t2 + col), K chunk c over
-  // logical h1 units 16 c + 8 half + e
+  // layer 2: tile t, physical row `col` = unit 32 t + perm_row(col); K chunk c
+  // runs over layer-1 units 16 c + 8 half + e
   constexpr int C2 = 2 * T1;
-  bf16x8 A2[T2][C2];
+  V A2[T2][C2];
   f32x16 B2v[T2];
 #pragma unroll
   for (int t = 0; t < T2; ++t) {
-    const int row = 32 * t + col;
+    const int u = 32 * t + perm_row(col);
 #pragma unroll
-    for (int c = 0; c < C2; ++c)
+    for (int c = 0; c < C2; ++c) {
+      float w[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int k = 16 * c + 8 * half + e;
-        const float w = (row < a.h2 && k < a.h1) ? a.W2[row * a.h1 + k] : 0.0f;
-        A2[t][c][e] = to_bf16(w);
+        w[e] = (u < a.h2 && k < a.h1) ? sW2[u * a.h1 + k] : 0.0f;
       }
+      set8<FP8>(A2[t][c], w, iw1);
+    }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const int r = 32 * t + 8 * (v >> 2) + 4 * half + (v & 3);
-      B2v[t][v] = r < a.h2 ? a.b2[r] : 0.0f;
+      const int uu = 32 * t + perm_row(8 * (v >> 2) + 4 * half + (v & 3));
+      B2v[t][v] = uu < a.h2 ? sb2[uu] : 0.0f;
     }
   }
-  // output layer (VALU) weights for this lane's h2 rows, bf16-rounded
-  float W3v[3][T2][16];
+  // layer 3: rows 0..2 live, K chunk c over layer-2 units 16 c + 8 half + e
+  constexpr int C3 = 2 * T2;
+  V A3[C3];
 #pragma unroll
-  for (int o = 0; o < 3; ++o)
+  for (int c = 0; c < C3; ++c) {
+    float w[8];
 #pragma unroll
-    for (int t = 0; t < T2; ++t)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int r = 32 * t + 8 * (v >> 2) + 4 * half + (v & 3);
-        W3v[o][t][v] = r < a.h2 ? bf16_round(a.W3[o * a.h2 + r]) : 0.0f;
-      }
-  const float b30 = a.b3[0], b31 = a.b3[1], b32 = a.b3[2];
-
-  for (int grp = wave; grp < ngroups; grp += nwaves) {
-    const int p = grp * 32 + col;
-    const bool live = p < P;
-    const uint32_t n = live ? a.count[p] : 0u;
-    // B operand of layer 1: inputs 8 half .. 8 half + 7 of pixel p
-    bf16x8 X;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) X[e] = to_bf16(0.0f);
-    if (half == 0 && n >= 3) {
-      float v[5];
-      fetch_x(a, g, p % a.W, p / a.W, v);
-#pragma unroll
-      for (int e = 0; e < 5; ++e) X[e] = to_bf16(v[e]);
+    for (int e = 0; e < 8; ++e) {
+      const int k = 16 * c + 8 * half + e;
+      w[e] = (col < 3 && k < a.h2) ? sW3[col * a.h2 + k] : 0.0f;
     }
-    // layer 1
-    bf16x8 Hb[C2];
+    set8<FP8>(A3[c], w, iw2);
+  }
+  const float b30 = sb3[0], b31 = sb3[1], b32 = sb3[2];
+
+  // the network on one 32-pixel group whose inputs sit in lane half 0
+  auto net = [&](const float xv[5], float& o0, float& o1, float& o2) {
+    V X;
+    {
+      float xx[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) xx[e] = (half == 0 && e < 5) ? xv[e] : 0.0f;
+      set8<FP8>(X, xx, ia0);
+    }
+    V Hb[C2];
 #pragma unroll
     for (int t = 0; t < T1; ++t) {
-      f32x16 acc = B1v[t];
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1[t], X, acc, 0, 0, 0);
+      f32x16 acc = {};
+      acc = mfma<FP8>(A1[t], X, acc);
 #pragma unroll
-      for (int v = 0; v < 16; ++v) Hb[2 * t + (v >> 3)][v & 7] = to_bf16(fmaxf(acc[v], 0.0f));
-    }
-    // layer 2 + output layer
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+      for (int c = 0; c < 2; ++c) {
+        float hv[8];
 #pragma unroll
-    for (int t = 0; t < T2; ++t) {
-      f32x16 acc = B2v[t];
-#pragma unroll
-      for (int c = 0; c < C2; ++c) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A2[t][c], Hb[c], acc, 0, 0, 0);
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const float h = bf16_round(fmaxf(acc[v], 0.0f));
-        s0 = fmaf(W3v[0][t][v], h, s0);
-        s1 = fmaf(W3v[1][t][v], h, s1);
-        s2 = fmaf(W3v[2][t][v], h, s2);
+        for (int e = 0; e < 8; ++e) hv[e] = fmaxf(fmaf(acc[8 * c + e], dq0, B1v[t][8 * c + e]), 0.0f);
+        set8<FP8>(Hb[2 * t + c], hv, ia1);
       }
     }
-    // the two lane halves hold the two halves of the h2 rows of pixel p
-    s0 += __shfl_xor(s0, 32);
-    s1 += __shfl_xor(s1, 32);
-    s2 += __shfl_xor(s2, 32);
-    if (half == 0 && live) {
-      const bool on = n >= 3;
-      a.out[3 * (size_t)p + 0] = on ? fmaxf(s0 + b30, 0.0f) : 0.0f;
-      a.out[3 * (size_t)p + 1] = on ? fmaxf(s1 + b31, 0.0f) : 0.0f;
-      a.out[3 * (size_t)p + 2] = on ? fmaxf(s2 + b32, 0.0f) : 0.0f;
+    V Hb2[C3];
+#pragma unroll
+    for (int t = 0; t < T2; ++t) {
+      f32x16 acc = {};
+#pragma unroll
+      for (int c = 0; c < C2; ++c) acc = mfma<FP8>(A2[t][c], Hb[c], acc);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        float hv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) hv[e] = fmaxf(fmaf(acc[8 * c + e], dq1, B2v[t][8 * c + e]), 0.0f);
+        set8<FP8>(Hb2[2 * t + c], hv, ia2);
+      }
+    }
+    f32x16 acc = {};
+#pragma unroll
+    for (int c = 0; c < C3; ++c) acc = mfma<FP8>(A3[c], Hb2[c], acc);
+    o0 = fmaxf(fmaf(acc[0], dq2, b30), 0.0f);
+    o1 = fmaxf(fmaf(acc[1], dq2, b31), 0.0f);
+    o2 = fmaxf(fmaf(acc[2], dq2, b32), 0.0f);
+  };
+
+  for (int st = wave; st < nsteps; st += nwaves) {
+    const int p = st * 64 + lane;
+    const bool live = p < P;
+    PixRaw r;
+    r.n = 0;
+    if (live) issue_loads<COMP>(a, g, p, r);
+    const PixIn in = blend<COMP>(r);
+    float xs[5], xo[5];
+#pragma unroll
+    for (int e = 0; e < 5; ++e) {
+      xs[e] = (live && in.n >= 3) ? in.x[e] : 0.0f;
+      xo[e] = __shfl_xor(xs[e], 32);  // half 0 receives the second group's inputs
+    }
+    float a0, a1, a2, b0, b1, b2;
+    net(xs, a0, a1, a2);   // first group (lanes 0..31)
+    net(xo, b0, b1, b2);   // second group (lanes 32..63), outputs in half 0
+    b0 = __shfl_xor(b0, 32);
+    b1 = __shfl_xor(b1, 32);
+    b2 = __shfl_xor(b2, 32);
+    if (live) {
+      if (half == 0) store_pixel<COMP>(a, p, in, a0, a1, a2);
+      else store_pixel<COMP>(a, p, in, b0, b1, b2);
     }
   }
 }
 
-template <int H1, int H2>
-int launch_f32(const InferArgs& a, hipStream_t s) {
+template <int H1, int H2, bool COMP>
+void launch_f32(const InferArgs& a, hipStream_t s) {
   const int P = a.W * a.H;
-  hipLaunchKernelGGL((infer_f32_kernel<H1, H2>), dim3((P + 255) / 256), dim3(256), 0, s, a);
-  return STARNT_OK;
+  hipLaunchKernelGGL((infer_f32_kernel<H1, H2, COMP>), dim3((P + 255) / 256), dim3(256), 0, s, a);
 }
 
-template <int T1, int T2>
-int launch_bf16(const InferArgs& a, hipStream_t s) {
+template <int T1, int T2, bool FP8, bool COMP>
+void launch_mfma(const InferArgs& a, hipStream_t s) {
   const int P = a.W * a.H;
-  const int groups = (P + 31) / 32;
-  // persistent waves: enough to fill the chip, each walking many 32-pixel groups
-  int blocks = (groups + 3) / 4;
-  if (blocks > 2048) blocks = 2048;
+  const int steps = (P + 63) / 64;
+  // persistent blocks: a few per CU, each wave walking many 64-pixel steps
+  int blocks = (steps + 3) / 4;
+  if (blocks > 1024) blocks = 1024;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL((infer_bf16_kernel<T1, T2>), dim3(blocks), dim3(256), 0, s, a);
-  return STARNT_OK;
+  hipLaunchKernelGGL((infer_mfma_kernel<T1, T2, FP8, COMP>), dim3(blocks), dim3(256), 0, s, a);
 }
 
-}  // namespace
+template <bool COMP>
+int dispatch(const starnt_mlp& m, const InferArgs& a, hipStream_t s) {
+  if (m.dtype == STARNT_F32) {
+#define F32CASE(A, B) \
+  if (m.h1 == A && m.h2 == B) { launch_f32<A, B, COMP>(a, s); return STARNT_OK; }
+    F32CASE(16, 16) F32CASE(16, 32) F32CASE(32, 16) F32CASE(32, 32) F32CASE(32, 64) F32CASE(64, 32)
+    F32CASE(64, 64) F32CASE(16, 64) F32CASE(64, 16)
+#undef F32CASE
+    return STARNT_EUNSUPPORTED;
+  }
+  if (m.dtype != STARNT_BF16 && m.dtype != STARNT_FP8) return STARNT_EUNSUPPORTED;
+  const bool f8 = m.dtype == STARNT_FP8;
+  const int t1 = (m.h1 + 31) / 32, t2 = (m.h2 + 31) / 32;
+#define MCASE(A, B)                                                              \
+  if (t1 == A && t2 == B) {                                                      \
+    if (f8) launch_mfma<A, B, true, COMP>(a, s); else launch_mfma<A, B, false, COMP>(a, s); \
+    return STARNT_OK;                                                            \
+  }
+  MCASE(1, 1) MCASE(1, 2) MCASE(2, 1) MCASE(2, 2)
+#undef MCASE
+  return STARNT_EUNSUPPORTED;
+}
 
-int launch_infer(const starnt_mlp& m, const float* tail, const uint32_t* count, const starnt_sched* sched,
-                 int W, int H, float* out, hipStream_t s) {
+InferArgs make_args(const starnt_mlp& m, const float* tail, const uint32_t* count, const float* layer1,
+                    const float* layer2, const starnt_sched* sched, int W, int H, const float* bg, float* out) {
   InferArgs a;
   a.W = W;
   a.H = H;
   a.tail = reinterpret_cast<const float4*>(tail);
   a.count = count;
+  a.layer1 = reinterpret_cast<const float4*>(layer1);
+  a.layer2 = reinterpret_cast<const float4*>(layer2);
   a.sched = sched;
   a.W1 = m.W1; a.b1 = m.b1; a.W2 = m.W2; a.b2 = m.b2; a.W3 = m.W3; a.b3 = m.b3;
   a.in = m.in; a.h1 = m.h1; a.h2 = m.h2;
@@ -279,24 +474,31 @@ int launch_infer(const starnt_mlp& m, const float* tail, const uint32_t* count, 
     a.sa[i] = m.fp8_scales ? m.fp8_scales[2 * i] : 1.0f;
     a.sw[i] = m.fp8_scales ? m.fp8_scales[2 * i + 1] : 1.0f;
   }
+  a.bg0 = bg ? bg[0] : 0.0f;
+  a.bg1 = bg ? bg[1] : 0.0f;
+  a.bg2 = bg ? bg[2] : 0.0f;
   a.out = out;
-  int rc = STARNT_EUNSUPPORTED;
-  if (m.dtype == STARNT_F32) {
-#define F32CASE(A, B) \
-  if (m.h1 == A && m.h2 == B) rc = launch_f32<A, B>(a, s);
-    F32CASE(16, 16) F32CASE(16, 32) F32CASE(32, 16) F32CASE(32, 32) F32CASE(32, 64) F32CASE(64, 32)
-    F32CASE(64, 64) F32CASE(16, 64) F32CASE(64, 16)
-#undef F32CASE
-  } else if (m.dtype == STARNT_BF16) {
-    const int t1 = (m.h1 + 31) / 32, t2 = (m.h2 + 31) / 32;
-    if (t1 == 1 && t2 == 1) rc = launch_bf16<1, 1>(a, s);
-    else if (t1 == 1 && t2 == 2) rc = launch_bf16<1, 2>(a, s);
-    else if (t1 == 2 && t2 == 1) rc = launch_bf16<2, 1>(a, s);
-    else if (t1 == 2 && t2 == 2) rc = launch_bf16<2, 2>(a, s);
-  }
-  if (rc == STARNT_EUNSUPPORTED) return fail(rc, "starnt_infer: unsupported dtype / hidden widths");
+  return a;
+}
+
+}  // namespace
+
+int launch_infer(const starnt_mlp& m, const float* tail, const uint32_t* count, const starnt_sched* sched,
+                 int W, int H, float* out, hipStream_t s) {
+  const InferArgs a = make_args(m, tail, count, nullptr, nullptr, sched, W, H, nullptr, out);
+  const int rc = dispatch<false>(m, a, s);
+  if (rc) return fail(rc, "starnt_infer: unsupported dtype / hidden widths");
   STARNT_LAUNCH_CHECK("starnt_infer launch");
-  return rc;
+  return STARNT_OK;
+}
+
+int launch_infer_composite(const starnt_mlp& m, const starnt_feats& f, const starnt_sched* sched,
+                           const float bg[3], float* rgb, hipStream_t s) {
+  const InferArgs a = make_args(m, f.tail, f.count, f.layer1, f.layer2, sched, f.width, f.height, bg, rgb);
+  const int rc = dispatch<true>(m, a, s);
+  if (rc) return fail(rc, "starnt_infer_composite: unsupported dtype / hidden widths");
+  STARNT_LAUNCH_CHECK("starnt_infer_composite launch");
+  return STARNT_OK;
 }
 
 }  // namespace starnt

@@ -25,15 +25,17 @@ int hip_status(hipError_t e, const char* what);
 
 // Grid index i of the W_s-sample grid that samples full-resolution coordinate
 // x (sample i sits at floor((2i+1) W / (2 W_s))), or -1 when x is not sampled.
+// Frame sides are at most 16384, so every product below is below 2^30 and
+// 32-bit integer arithmetic is exact.
 __device__ __forceinline__ int grid_index_of(int x, int W, int Ws) {
   if (Ws >= W) return x;
   // smallest i with (2i+1) W >= 2 Ws x
-  long long num = 2LL * Ws * x - W;
-  long long den = 2LL * W;
-  long long i = num <= 0 ? 0 : (num + den - 1) / den;
+  const int num = 2 * Ws * x - W;
+  const int den = 2 * W;
+  const int i = num <= 0 ? 0 : (int)(((unsigned)num + (unsigned)den - 1u) / (unsigned)den);
   if (i >= Ws) return -1;
-  long long pos = ((2 * i + 1) * (long long)W) / (2LL * Ws);
-  return pos == x ? (int)i : -1;
+  const int pos = (int)((unsigned)((2 * i + 1) * W) / (unsigned)(2 * Ws));
+  return pos == x ? i : -1;
 }
 
 // Bilinear taps along one axis for full-resolution coordinate x on a W_s grid:
@@ -45,15 +47,14 @@ struct Taps {
 };
 __device__ __forceinline__ Taps axis_taps(int x, int W, int Ws) {
   Taps t;
-  long long num = (2LL * x + 1) * Ws - W;
-  long long den = 2LL * W;
-  long long q = num >= 0 ? num / den : -((-num + den - 1) / den);
-  long long r = num - q * den;
+  const int num = (2 * x + 1) * Ws - W;  // >= -W
+  const int den = 2 * W;
+  // floor division for num >= -den
+  const int q = num >= 0 ? (int)((unsigned)num / (unsigned)den) : -1;
+  const int r = num - q * den;
   t.w1 = (float)r / (float)den;
-  long long a = q < 0 ? 0 : (q > Ws - 1 ? Ws - 1 : q);
-  long long b = q + 1 < 0 ? 0 : (q + 1 > Ws - 1 ? Ws - 1 : q + 1);
-  t.i0 = (int)a;
-  t.i1 = (int)b;
+  t.i0 = q < 0 ? 0 : (q > Ws - 1 ? Ws - 1 : q);
+  t.i1 = q + 1 < 0 ? 0 : (q + 1 > Ws - 1 ? Ws - 1 : q + 1);
   return t;
 }
 
@@ -96,6 +97,8 @@ int launch_composite(const starnt_feats& o, const float* tail_rgb, const starnt_
                      const float bg[3], int mode, float* rgb, hipStream_t s);
 int launch_infer(const starnt_mlp& m, const float* tail, const uint32_t* count, const starnt_sched* sched,
                  int W, int H, float* out, hipStream_t s);
+int launch_infer_composite(const starnt_mlp& m, const starnt_feats& f, const starnt_sched* sched,
+                           const float bg[3], float* rgb, hipStream_t s);
 int launch_quadtree(const float* rgb, const uint32_t* count, int W, int H, const starnt_qt_params& qp,
                     const uint32_t* prev_mask, uint32_t* mask, uint8_t* level, starnt_sched* sched, void* ws,
                     hipStream_t s);

@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from . import (MODE_EXACT, MODE_LEARNED, WS_QUADTREE, DeviceFrags, DeviceMlp, FeatBuffers, QtParams,
-               starnt_composite, starnt_features, starnt_infer, starnt_quadtree, starnt_reproject,
+               starnt_composite, starnt_features, starnt_infer_composite, starnt_quadtree, starnt_reproject,
                starnt_sched_init, starnt_workspace_size, workspace)
 
 
@@ -34,7 +34,6 @@ class Renderer:
         self.bg = tuple(float(v) for v in bg)
         self.qp = QtParams(int(base), float(tau_split), float(tau_merge), int(k_relax))
         self.feats = FeatBuffers(self.W, self.H, device)
-        self.tail_rgb = torch.zeros(P, 3, dtype=torch.float32, device=device)
         self.sched = torch.zeros(16, dtype=torch.int32, device=device)
         T = ((self.W + base - 1) // base) * ((self.H + base - 1) // base)
         cs = base // 8
@@ -61,10 +60,11 @@ class Renderer:
     def real_frame(self, frags: DeviceFrags, out, stream=None):
         self._call("features", lambda: starnt_features(frags, self.sched, self.feats, stream))
         if self.mode == MODE_LEARNED:
-            self._call("infer", lambda: starnt_infer(self.mlp, self.feats.tail, self.feats.count, self.sched, self.W,
-                                                     self.H, self.tail_rgb, stream))
-        self._call("composite", lambda: starnt_composite(frags, self.feats, self.tail_rgb, self.sched, self.bg,
-                                                         self.mode, out, None, stream))
+            self._call("infer_composite", lambda: starnt_infer_composite(self.mlp, self.feats, self.sched, self.bg,
+                                                                         out, stream))
+        else:
+            self._call("composite", lambda: starnt_composite(frags, self.feats, None, self.sched, self.bg,
+                                                             self.mode, out, None, stream))
         prev = None if self.n_real == 0 else self.masks[(self.n_real - 1) % 2]
         cur = self.masks[self.n_real % 2]
         self._call("quadtree", lambda: starnt_quadtree(out, self.feats.count, self.W, self.H, self.qp, prev, cur,

@@ -228,7 +228,8 @@ int starnt_quadtree(const float* rgb, const uint32_t* count, int32_t width, int3
  * 1) with x_ndc = (2px+1)/W - 1, y_ndc = 1 - (2py+1)/H; h = X + (M - I) X with
  * M = VP_prev VP_cur^-1; source q = (floor((u+1) W / 2), floor((1-v) H / 2)),
  * (u, v) = (h_x, h_y) / h_w. rgb_out[p] = rgb_prev[q], src[p] = q; outside the
- * frame or h_w <= 0: src[p] = -1 and rgb_out[p] = rgb_prev[p].
+ * frame the source is clamped to the nearest edge pixel and src[p] = -1; when
+ * h_w <= 0, src[p] = -1 and rgb_out[p] = rgb_prev[p].
  * m_minus_i is a host float[16], row-major, acting on column vectors.
  * src may be NULL. */
 int starnt_reproject(const float* rgb_prev, const float* d1_prev, int32_t width, int32_t height,

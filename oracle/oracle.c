@@ -689,9 +689,10 @@ int orc_quadtree(int32_t W, int32_t H, const float* rgb, const uint32_t* N, cons
  * X = ((2px+1)/W - 1, 1 - (2py+1)/H, d1_r(p), 1) with the first-fragment depth
  * of the last real frame r at the same pixel, mapped by M = VP_r VP_t^-1
  * (given as M - I, row-major, column vectors), divided by w, and rounded to the
- * nearest source pixel q = (floor((u+1) W / 2), floor((1-v) H / 2)).
- * Inside the frame: out[p] = rgb_r[q], src[p] = q. Otherwise (or w <= 0):
- * src[p] = -1 and out[p] = rgb_r[p].
+ * nearest source pixel (floor((u+1) W / 2), floor((1-v) H / 2)).
+ * Inside the frame: out[p] = rgb_r[q], src[p] = q. Outside the frame the
+ * source is clamped to the nearest edge pixel (edge extension) and src[p] = -1.
+ * When w <= 0 (behind the camera): src[p] = -1 and out[p] = rgb_r[p].
  * margin (optional) receives the distance, in pixels, of the source coordinate
  * to the nearest rounding boundary (either axis).
  */
@@ -707,6 +708,7 @@ int orc_reproject(int32_t W, int32_t H, const float* rgb_r, const float* d1_r, c
         for (int c = 0; c < 4; ++c) h[r] += mmi[4 * r + c] * X[c];
       }
       int32_t q = -1;
+      int64_t s = p;
       double mg = 1e30;
       if (h[3] > 0.0) {
         double u = h[0] / h[3], v = h[1] / h[3];
@@ -715,10 +717,12 @@ int orc_reproject(int32_t W, int32_t H, const float* rgb_r, const float* d1_r, c
         double mx = fmin(sx - qx, qx + 1.0 - sx), my = fmin(sy - qy, qy + 1.0 - sy);
         mg = fmin(mx, my);
         if (qx >= 0 && qx < W && qy >= 0 && qy < H) q = (int32_t)((int64_t)qy * W + (int64_t)qx);
+        double cx = qx < 0 ? 0 : (qx > W - 1 ? W - 1 : qx);
+        double cy = qy < 0 ? 0 : (qy > H - 1 ? H - 1 : qy);
+        s = (int64_t)cy * W + (int64_t)cx;
       }
       if (src) src[p] = q;
       if (margin) margin[p] = mg;
-      int64_t s = q >= 0 ? q : p;
       for (int c = 0; c < 3; ++c) out[3 * p + c] = rgb_r[3 * s + c];
     }
   return 0;

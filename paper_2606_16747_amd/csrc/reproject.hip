@@ -1,7 +1,8 @@
 // Interpolated frames by depth reprojection (Sec. 3.3): a gather from the last
 // real frame using its first-fragment depth at the same pixel and the matrix
 // M = VP_prev VP_cur^-1, given as M - I so the source offset is computed from
-// the (small) motion, not from the absolute coordinates.
+// the (small) motion, not from the absolute coordinates. A source outside the
+// frame is clamped to the nearest edge pixel (reported as src = -1).
 #include "internal.h"
 
 namespace starnt {
@@ -35,17 +36,21 @@ __global__ __launch_bounds__(256) void reproject_kernel(ReprojArgs a) {
   const float dw = fmaf(d[12], X0, fmaf(d[13], X1, fmaf(d[14], X2, d[15])));
   const float w = 1.0f + dw;
   int q = -1;
+  int s = p;
   if (w > 0.0f) {
     // u - x = (dx - x dw) / w, in pixels: (u - x) W / 2; same for v (y up)
     const float ox = (dx - X0 * dw) / w * (0.5f * a.W);
     const float oy = (dy - X1 * dw) / w * (0.5f * a.H);
-    const float fx = floorf(ox + 0.5f), fy = floorf(0.5f - oy);
-    if (fabsf(fx) < 1e7f && fabsf(fy) < 1e7f) {
-      const int qx = px + (int)fx, qy = py + (int)fy;
-      if (qx >= 0 && qx < a.W && qy >= 0 && qy < a.H) q = qy * a.W + qx;
-    }
+    // displacement in whole pixels, bounded so the integer conversion is safe
+    const float fx = fminf(fmaxf(floorf(ox + 0.5f), -1e8f), 1e8f);
+    const float fy = fminf(fmaxf(floorf(0.5f - oy), -1e8f), 1e8f);
+    const long long qx = px + (long long)fx, qy = py + (long long)fy;
+    if (qx >= 0 && qx < a.W && qy >= 0 && qy < a.H) q = (int)(qy * a.W + qx);
+    // outside the frame: edge extension (src stays -1)
+    const int cx = (int)(qx < 0 ? 0 : (qx > a.W - 1 ? a.W - 1 : qx));
+    const int cy = (int)(qy < 0 ? 0 : (qy > a.H - 1 ? a.H - 1 : qy));
+    s = cy * a.W + cx;
   }
-  const int s = q >= 0 ? q : p;
   a.out[3 * (size_t)p + 0] = a.rgb[3 * (size_t)s + 0];
   a.out[3 * (size_t)p + 1] = a.rgb[3 * (size_t)s + 1];
   a.out[3 * (size_t)p + 2] = a.rgb[3 * (size_t)s + 2];

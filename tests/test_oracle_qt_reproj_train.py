@@ -205,6 +205,18 @@ def test_quadtree_structural_invariants(oracle_mod):
 # ---------------------------------------------------------------------------
 # reprojection
 
+def test_reproject_behind_camera_keeps_own_pixel(oracle_mod):
+    """w <= 0 after the transform (a point behind the camera): hole, own colour."""
+    W, H = 6, 5
+    rgb = np.random.default_rng(4).random((W * H, 3)).astype(np.float32)
+    d1 = np.full(W * H, 0.5, np.float32)
+    mmi = np.zeros((4, 4))
+    mmi[3, 3] = -2.0  # w' = 1 - 2 = -1
+    out, src, _ = oracle_mod.reproject(rgb, d1, mmi, W, H)
+    assert np.all(src == -1)
+    np.testing.assert_array_equal(out, rgb)
+
+
 def test_reproject_identity(oracle_mod):
     W, H = 33, 17
     rng = np.random.default_rng(0)
@@ -218,7 +230,8 @@ def test_reproject_identity(oracle_mod):
 @pytest.mark.parametrize("k,m", [(3, 0), (-5, 2), (0, -4), (7, 7)])
 def test_reproject_screen_translation(oracle_mod, k, m):
     """M = translation by (2k/W, -2m/H) in NDC at any depth: the source of pixel
-    (x, y) is (x + k, y + m); outside the frame -> -1 and own colour kept."""
+    (x, y) is (x + k, y + m); outside the frame src = -1 and the colour comes
+    from the nearest edge pixel."""
     W, H = 40, 24
     rng = np.random.default_rng(1)
     rgb = rng.random((W * H, 3)).astype(np.float32)
@@ -236,7 +249,8 @@ def test_reproject_screen_translation(oracle_mod, k, m):
                 np.testing.assert_array_equal(out[p], rgb[sy * W + sx])
             else:
                 assert src[p] == -1
-                np.testing.assert_array_equal(out[p], rgb[p])
+                cx, cy = min(max(sx, 0), W - 1), min(max(sy, 0), H - 1)
+                np.testing.assert_array_equal(out[p], rgb[cy * W + cx])
 
 
 def test_reproject_matches_full_unproject_project(oracle_mod, sg):

@@ -4,9 +4,9 @@
 // Kernel 1: one block per slice of kSB samples. Forward and backward run with
 //   the slice's activations in LDS; the block writes its partial loss and its
 //   partial gradient (sum over its samples) for every parameter.
-// Kernel 2: one thread per parameter sums the partials in block order (a fixed
-//   order, so a step is bitwise reproducible), then applies bias-corrected
-//   Adam to the FP32 master weight.
+// Kernel 2: sums the partials of every parameter in a fixed order (so a step
+//   is bitwise reproducible), then applies bias-corrected Adam to the FP32
+//   master weight.
 // In BF16 mode every GEMM operand (weights, inputs, activations, output
 // gradients) is rounded to bf16 as the matrix cores would consume it; products
 // of two bf16 values are exact in FP32 and accumulation is FP32.
@@ -158,23 +158,44 @@ struct AdamArgs {
   float lr, b1, b2, eps, c1, c2;  // c1 = 1 - b1^t, c2 = 1 - b2^t
 };
 
-__global__ __launch_bounds__(256) void train_reduce_adam(AdamArgs a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < a.nparam) {
-    float g = 0.0f;
-    for (int b = 0; b < a.nblocks; ++b) g += a.partial[(size_t)b * a.nparam + i];
-    a.grad[i] = g;
-    const float m = fmaf(a.b1, a.m[i], (1.0f - a.b1) * g);
-    const float v = fmaf(a.b2, a.v[i], (1.0f - a.b2) * g * g);
+// 16 parameters x 16 row groups per block: thread (r, c) sums the partials
+// of rows r, r + 16, ... for parameter c; the 16 group sums are then added in
+// order. The order is fixed, so the gradient is bitwise reproducible.
+constexpr int kRP = 16;   // parameters per block
+constexpr int kRG = 16;   // row groups per block
+
+__global__ __launch_bounds__(kRP * kRG) void train_reduce_adam(AdamArgs a) {
+  __shared__ float s_part[kRG][kRP];
+  const int c = threadIdx.x % kRP, r = threadIdx.x / kRP;
+  const int i = blockIdx.x * kRP + c;
+  float g = 0.0f;
+  if (i < a.nparam)
+    for (int b = r; b < a.nblocks; b += kRG) g += a.partial[(size_t)b * a.nparam + i];
+  s_part[r][c] = g;
+  __syncthreads();
+  if (r == 0 && i < a.nparam) {
+    float t = 0.0f;
+    for (int k = 0; k < kRG; ++k) t += s_part[k][c];
+    a.grad[i] = t;
+    const float m = fmaf(a.b1, a.m[i], (1.0f - a.b1) * t);
+    const float v = fmaf(a.b2, a.v[i], (1.0f - a.b2) * t * t);
     a.m[i] = m;
     a.v[i] = v;
     const float mh = m / a.c1, vh = v / a.c2;
     a.params[i] -= a.lr * mh / (sqrtf(vh) + a.eps);
   }
-  if (i == 0) {
+  if (blockIdx.x == 0) {
+    // loss: per-thread strided sums, then a fixed-order tree
+    __shared__ float s_loss[kRP * kRG];
     float l = 0.0f;
-    for (int b = 0; b < a.nblocks; ++b) l += a.partial_loss[b];
-    a.loss[0] = l;
+    for (int b = threadIdx.x; b < a.nblocks; b += kRP * kRG) l += a.partial_loss[b];
+    s_loss[threadIdx.x] = l;
+    __syncthreads();
+    for (int w = kRP * kRG / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) s_loss[threadIdx.x] += s_loss[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) a.loss[0] = s_loss[0];
   }
 }
 
@@ -237,7 +258,7 @@ int launch_train(const starnt_train& tr, const float* x, const float* y, int bat
   ad.eps = hp.eps;
   ad.c1 = (float)(1.0 - std::pow((double)hp.beta1, hp.step));
   ad.c2 = (float)(1.0 - std::pow((double)hp.beta2, hp.step));
-  hipLaunchKernelGGL(train_reduce_adam, dim3((np + 255) / 256), dim3(256), 0, s, ad);
+  hipLaunchKernelGGL(train_reduce_adam, dim3((np + kRP - 1) / kRP), dim3(kRP * kRG), 0, s, ad);
   STARNT_LAUNCH_CHECK("starnt_train_step adam launch");
   (void)ws_bytes;
   return STARNT_OK;

@@ -114,7 +114,7 @@ class SceneParams:
     cam_trans: float = 0.02
     move_rot_deg: float = 0.0
     move_trans: float = 0.0
-    colour_mode: int = 0          # 0 iid colours, 1 colour correlated with depth
+    colour_mode: int = 0          # 0 iid colours, 1 correlated with depth, 2 per-object palette
     half_rgba: bool = False
 
     def _c(self) -> _Params:
@@ -132,25 +132,26 @@ PRESETS = {
     # 256x256, 64 screen-space triangles, planar depth U[0,1], mean ~4-5, max ~24
     "c1_256": SceneParams(kind=0, width=256, height=256, num_tris=64, max_per_pixel=24,
                           seed=BASE_SEED + 1),
-    # 1920x1080, 2000 world triangles, heavy-tailed (mean ~8, max 64), 8-frame camera path
+    # 1920x1080, 2000 world triangles, heavy-tailed (mean ~8, max 64), 8-frame
+    # smooth camera path (<= 0.25 deg and 0.01 units per frame), per-object materials
     "c2_1080p": SceneParams(kind=1, width=1920, height=1080, num_tris=2000, num_frames=8,
                             max_per_pixel=64, seed=BASE_SEED + 2, size_mu=-2.03, size_sigma=0.55,
                             clusters=5, cluster_frac=0.5, cluster_radius=0.012,
-                            cam_rot_deg=0.5, cam_trans=0.02),
-    # 512x512 training scenes, mean ~12, max 128
+                            cam_rot_deg=0.25, cam_trans=0.01, colour_mode=2),
+    # 512x512 training scenes, mean ~12, max 128, per-object materials
     "c3_512": SceneParams(kind=1, width=512, height=512, num_tris=1600, max_per_pixel=128,
                           seed=BASE_SEED + 3, size_mu=-2.0, size_sigma=0.6,
-                          clusters=2, cluster_frac=0.5, cluster_radius=0.002),
+                          clusters=2, cluster_frac=0.5, cluster_radius=0.002, colour_mode=2),
     # 3840x2160, 8000 triangles, mean ~16, max 256, fp16 RGBA
     "c4_4k": SceneParams(kind=1, width=3840, height=2160, num_tris=8000, max_per_pixel=256,
                          seed=BASE_SEED + 4, size_mu=-2.5, size_sigma=0.6, clusters=6,
-                         cluster_frac=0.5, cluster_radius=0.004, half_rgba=True),
+                         cluster_frac=0.5, cluster_radius=0.004, half_rgba=True, colour_mode=2),
     # 2560x1440, 4000 static + 500 moving triangles, 60 frames, mean ~10, max 160
     "c5_1440p": SceneParams(kind=1, width=2560, height=1440, num_tris=4000, num_moving=500,
                             num_frames=60, max_per_pixel=160, seed=BASE_SEED + 5,
                             size_mu=-2.45, size_sigma=0.6, clusters=4, cluster_frac=0.5,
                             cluster_radius=0.005, cam_rot_deg=0.3, cam_trans=0.01,
-                            move_rot_deg=0.5, move_trans=0.01),
+                            move_rot_deg=0.5, move_trans=0.01, colour_mode=2),
 }
 
 

@@ -78,7 +78,7 @@ typedef struct {
   double fov_y_deg, z_near, z_far;
   double cam_rot_deg, cam_trans;    // per-frame camera motion bounds
   double move_rot_deg, move_trans;  // per-frame rigid motion bounds of moving triangles
-  int32_t colour_mode;          // 0 iid U[0,1]; 1 colour correlated with depth
+  int32_t colour_mode;          // 0 iid U[0,1]; 1 colour correlated with depth; 2 object palette
   int32_t half_rgba;            // informational: caller stores RGBA as fp16
 } sg_params;
 
@@ -115,7 +115,23 @@ struct sg_scene {
 
 namespace {
 
-void colour_for(Rng& r, const sg_params& p, double depth01, float out[4]) {
+// per-object material: base colour and opacity of object (cluster) `obj`
+void object_material(const sg_params& p, int obj, double base[4]) {
+  Rng r(p.seed, ST_CLUSTER + 100, (uint64_t)obj);
+  for (int c = 0; c < 3; ++c) base[c] = r.uniform(0.05, 0.95);
+  base[3] = r.uniform(p.alpha_lo, p.alpha_hi);
+}
+
+void colour_for(Rng& r, const sg_params& p, double depth01, float out[4], int obj = -1) {
+  if (p.colour_mode == 2) {
+    // object palette: the object's material with a small per-triangle variation
+    double base[4];
+    object_material(p, obj < 0 ? 0 : obj, base);
+    for (int c = 0; c < 3; ++c)
+      out[c] = (float)std::min(1.0, std::max(0.0, base[c] + 0.04 * (2.0 * r.uniform() - 1.0)));
+    out[3] = (float)std::min(p.alpha_hi, std::max(p.alpha_lo, base[3] + 0.04 * (2.0 * r.uniform() - 1.0)));
+    return;
+  }
   if (p.colour_mode == 1) {
     // near fragments reddish, far fragments bluish, with noise
     double t = std::min(1.0, std::max(0.0, depth01));
@@ -145,7 +161,7 @@ void build_triangles(sg_scene* s) {
         t.v[k][2] = r.uniform();
         zsum += t.v[k][2];
       }
-      colour_for(r, p, zsum / 3.0, t.rgba);
+      colour_for(r, p, zsum / 3.0, t.rgba, i % 8);
     }
     return;
   }
@@ -164,8 +180,10 @@ void build_triangles(sg_scene* s) {
   for (int i = 0; i < total; ++i) {
     Rng r(p.seed, ST_TRI, (uint64_t)i);
     double cx, cy, cz, d;
+    int obj = nc;  // scattered triangles share one background material
     if (p.clusters > 0 && r.uniform() < p.cluster_frac) {
       int c = (int)(r.next() % (uint64_t)nc);
+      obj = c;
       d = -cc[3 * c + 2];
       cx = cc[3 * c + 0] + r.normal() * p.cluster_radius * d;
       cy = cc[3 * c + 1] + r.normal() * p.cluster_radius * d;
@@ -189,7 +207,7 @@ void build_triangles(sg_scene* s) {
       t.v[k][2] = cz + rad * z;
     }
     double dep01 = (d - p.depth_lo) / std::max(1e-9, p.depth_hi - p.depth_lo);
-    colour_for(r, p, dep01, t.rgba);
+    colour_for(r, p, dep01, t.rgba, obj);
   }
 }
 

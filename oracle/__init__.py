@@ -92,6 +92,10 @@ def _load():
             lib.orc_adam.restype = None
             lib.orc_adam.argtypes = [ctypes.c_int64, _P, _P, _P, _P, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_int32]
+            lib.orc_wboit_weight.restype = ctypes.c_double
+            lib.orc_wboit_weight.argtypes = [ctypes.c_double, ctypes.c_double]
+            lib.orc_baseline.restype = ctypes.c_int
+            lib.orc_baseline.argtypes = [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, ctypes.c_int32, _P, _P]
             _lib = lib
     return _lib
 
@@ -376,3 +380,31 @@ def psnr(a, b, mask=None):
         d = d[np.asarray(mask)]
     mse = float(d.mean()) if d.size else 0.0
     return float("inf") if mse == 0 else 10.0 * np.log10(1.0 / mse)
+
+
+# ---------------------------------------------------------------------------
+# approximate baselines of the evaluation (Sec. 4)
+
+BASE_WBOIT = 0
+BASE_OVER_LIST = 1
+
+
+def wboit_weight(z, a):
+    """McGuire-Bavoil weight on window-space depth: a * max(1e-2, 3e3 (1 - z)^3)."""
+    return float(_load().orc_wboit_weight(float(z), float(a)))
+
+
+def baseline(offsets, depth, rgba, width, height, method, bg=(1.0, 1.0, 1.0)):
+    """[P,3] composite of a cheap baseline: method BASE_WBOIT (weighted blended
+    OIT) or BASE_OVER_LIST (eq (1) in stored order, no sort)."""
+    lib = _load()
+    P = int(width) * int(height)
+    off = _c(offsets, np.uint32)
+    dep = _c(depth, np.float32)
+    col = _c(np.asarray(rgba).astype(np.float32), np.float32)
+    out = np.empty((P, 3), np.float64)
+    rc = lib.orc_baseline(int(width), int(height), _ptr(off), _ptr(dep), _ptr(col), int(method),
+                          _ptr(np.asarray(bg, np.float64)), _ptr(out))
+    if rc != 0:
+        raise ValueError("unknown baseline method %r" % (method,))
+    return out

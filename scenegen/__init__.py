@@ -127,7 +127,7 @@ class SceneParams:
 BASE_SEED = 0x57A20000
 
 # Synthetic workloads: sizes, depth-complexity targets and motion of the five
-# measured configurations (see the design doc for the recipe and tuning notes).
+# measured configurations; the comment of each preset gives its statistics.
 PRESETS = {
     # 256x256, 64 screen-space triangles, planar depth U[0,1], mean ~4-5, max ~24
     "c1_256": SceneParams(kind=0, width=256, height=256, num_tris=64, max_per_pixel=24,

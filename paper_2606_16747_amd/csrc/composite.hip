@@ -41,7 +41,8 @@ __global__ __launch_bounds__(256) void composite_kernel(CompArgs a) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
   const Grids g = load_grids(a.sched, a.W, a.H);
-  const int x = p % a.W, y = p / a.W;
+  int x, y;
+  pixel_xy(p, a.W, x, y);
   const uint32_t n = a.count[p];
   const float4 l1 = a.layer1[p];
   float4 l2 = make_float4(0.f, 0.f, 0.f, 0.f);

@@ -33,6 +33,29 @@ constexpr uint32_t kOne = 0x3F800000u;  // bits of 1.0f
 constexpr int kG = 4;                   // lanes per pixel
 constexpr uint32_t kFold = 128;         // lane steps between 32 -> 64-bit folds
 
+// Quad permutations (DPP quad_perm, lane i reads lane perm[i] of its quad).
+constexpr int kXor1 = 0xB1;  // [1,0,3,2]
+constexpr int kXor2 = 0x4E;  // [2,3,0,1]
+constexpr int kRot1 = 0x39;  // [1,2,3,0]
+constexpr int kBc0 = 0x00;   // [0,0,0,0]
+template <int CTRL>
+__device__ __forceinline__ uint32_t qperm(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float qperm(float v) {
+  return __uint_as_float(qperm<CTRL>(__float_as_uint(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t qperm(uint64_t v) {
+  return (uint64_t)qperm<CTRL>((uint32_t)v) | ((uint64_t)qperm<CTRL>((uint32_t)(v >> 32)) << 32);
+}
+// u64 -> FP32 as hi * 2^32 + lo (at most one rounding more than a direct
+// conversion; the sums here stay far below 2^53)
+__device__ __forceinline__ float u64_to_f32(uint64_t v) {
+  return __builtin_fmaf((float)(uint32_t)(v >> 32), 4294967296.0f, (float)(uint32_t)v);
+}
+
 struct FeatArgs {
   int W, H;
   const uint32_t* off;
@@ -58,16 +81,20 @@ struct Terms {
   uint32_t a, r, g, b;
   uint64_t lg;
 };
+__device__ __forceinline__ uint32_t q24_term(float a24, float m) { return (uint32_t)__builtin_rintf(a24 * m); }
+__device__ __forceinline__ uint64_t lg_term(float a) {
+  const float l = -__log2f(1.0f - a) * kQ27;  // <= 24 * 2^27 below a = 1
+  return a >= 1.0f ? kOpaque : (uint64_t)(uint32_t)__builtin_rintf(l);
+}
 __device__ __forceinline__ Terms frag_terms(float4 c) {
   Terms t;
   const float a = __builtin_amdgcn_fmed3f(c.w, 0.0f, 1.0f);
   const float a24 = a * kQ24;  // exact scaling: a24 * c = (a * c) * 2^24
-  t.a = (uint32_t)__builtin_rintf(a24);
-  t.r = (uint32_t)__builtin_rintf(a24 * c.x);
-  t.g = (uint32_t)__builtin_rintf(a24 * c.y);
-  t.b = (uint32_t)__builtin_rintf(a24 * c.z);
-  const float l = -__log2f(1.0f - a) * kQ27;  // <= 24 * 2^27 below a = 1
-  t.lg = a >= 1.0f ? kOpaque : (uint64_t)(uint32_t)__builtin_rintf(l);
+  t.a = q24_term(a24, 1.0f);
+  t.r = q24_term(a24, c.x);
+  t.g = q24_term(a24, c.y);
+  t.b = q24_term(a24, c.z);
+  t.lg = lg_term(a);
   return t;
 }
 
@@ -89,20 +116,22 @@ struct Top2 {
   uint32_t k1 = kNone, k2 = kNone;  // global fragment indices
 };
 
-__device__ __forceinline__ bool key_less(float z, uint32_t k, float zb, uint32_t kb, const uint32_t* prim) {
-  if (z < zb) return true;
-  if (z > zb || kb == kNone) return false;
-  if (z != zb) return false;  // NaN
-  return prim[k] < prim[kb];
-}
-
+// Insert key (z, k) into the top 2. Straight-line compares and selects; only
+// an exact depth tie with a held key loads primitive ids (the tie-break). A
+// NaN depth never enters (every compare is false), and neither does a key at
+// the empty slots' +inf depth.
 __device__ __forceinline__ void top2_push(Top2& t, float z, uint32_t k, const uint32_t* prim) {
-  if (key_less(z, k, t.z1, t.k1, prim)) {
-    t.z2 = t.z1; t.k2 = t.k1;
-    t.z1 = z; t.k1 = k;
-  } else if (key_less(z, k, t.z2, t.k2, prim)) {
-    t.z2 = z; t.k2 = k;
+  bool lt1 = z < t.z1, lt2 = z < t.z2;
+  const bool eq1 = z == t.z1 && t.k1 != kNone, eq2 = z == t.z2 && t.k2 != kNone;
+  if (eq1 || eq2) {
+    const uint32_t pk = prim[k];
+    if (eq1) lt1 = pk < prim[t.k1];
+    if (eq2) lt2 = pk < prim[t.k2];
   }
+  t.z2 = lt1 ? t.z1 : (lt2 ? z : t.z2);
+  t.k2 = lt1 ? t.k1 : (lt2 ? k : t.k2);
+  t.z1 = lt1 ? z : t.z1;
+  t.k1 = lt1 ? k : t.k1;
 }
 
 template <bool HALF, bool RGBA>
@@ -161,7 +190,8 @@ __global__ __launch_bounds__(256) void features_kernel(FeatArgs a) {
   const int p = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) / kG);
   if (p >= P) return;  // whole quads leave together
   const Grids g = load_grids(a.sched, a.W, a.H);
-  const int x = p % a.W, y = p / a.W;
+  int x, y;
+  pixel_xy(p, a.W, x, y);
   const int i2 = grid_index_of(x, a.W, g.w2), j2 = grid_index_of(y, a.H, g.h2);
   const int i3 = grid_index_of(x, a.W, g.w3), j3 = grid_index_of(y, a.H, g.h3);
   const bool pass2 = i2 >= 0 && j2 >= 0;
@@ -175,60 +205,71 @@ __global__ __launch_bounds__(256) void features_kernel(FeatArgs a) {
   if (pass3) stream<HALF, true>(a, b, e, q, t, s, zmax, amax);
   else stream<HALF, false>(a, b, e, q, t, s, zmax, amax);
 
-  // merge the quad: two xor-shuffle rounds
-#pragma unroll
-  for (int m = 1; m < kG; m <<= 1) {
-    const float oz1 = __shfl_xor(t.z1, m), oz2 = __shfl_xor(t.z2, m);
-    const uint32_t ok1 = __shfl_xor(t.k1, m), ok2 = __shfl_xor(t.k2, m);
+  // merge the quad's top-2 keys: two butterfly rounds
+  {
+    const float oz1 = qperm<kXor1>(t.z1), oz2 = qperm<kXor1>(t.z2);
+    const uint32_t ok1 = qperm<kXor1>(t.k1), ok2 = qperm<kXor1>(t.k2);
     top2_push(t, oz1, ok1, a.prim);
     top2_push(t, oz2, ok2, a.prim);
-    if (pass3) {
-      s.a += __shfl_xor(s.a, m);
-      s.r += __shfl_xor(s.r, m);
-      s.g += __shfl_xor(s.g, m);
-      s.b += __shfl_xor(s.b, m);
-      s.lg += __shfl_xor(s.lg, m);
+  }
+  {
+    const float oz1 = qperm<kXor2>(t.z1), oz2 = qperm<kXor2>(t.z2);
+    const uint32_t ok1 = qperm<kXor2>(t.k1), ok2 = qperm<kXor2>(t.k2);
+    top2_push(t, oz1, ok1, a.prim);
+    top2_push(t, oz2, ok2, a.prim);
+  }
+  // the two selected layers, fetched by every lane of the quad (one
+  // transaction per address)
+  const bool want2 = pass2 || pass3;
+  float4 c1 = make_float4(0.f, 0.f, 0.f, 0.f), c2 = c1;
+  if (t.k1 != kNone) c1 = load_rgba<HALF>(a.rgba, t.k1);
+  if (t.k2 != kNone && want2) c2 = load_rgba<HALF>(a.rgba, t.k2);
+
+  // layer outputs (premultiplied): lane 0 -> layer 1, lane 1 -> layer 2
+  {
+    const float4 c = q == 0 ? c1 : c2;
+    const float al = __builtin_amdgcn_fmed3f(c.w, 0.0f, 1.0f);
+    if (q == 0 || (q == 1 && pass2)) {
+      float4* dst = q == 0 ? a.layer1 + p : a.layer2 + (j2 * g.w2 + i2);
+      *dst = make_float4(al * c.x, al * c.y, al * c.z, al);
     }
   }
-  // the two selected layers: lane 0 fetches layer 1, lane 1 layer 2, and the
-  // quad shares them
-  const bool want2 = pass2 || pass3;
-  float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (q == 0 && t.k1 != kNone) c = load_rgba<HALF>(a.rgba, t.k1);
-  if (q == 1 && t.k2 != kNone && want2) c = load_rgba<HALF>(a.rgba, t.k2);
-  const int base = threadIdx.x & ~(kG - 1);
-  const float4 c1 = make_float4(__shfl(c.x, base), __shfl(c.y, base), __shfl(c.z, base), __shfl(c.w, base));
-  const float4 c2 = make_float4(__shfl(c.x, base + 1), __shfl(c.y, base + 1), __shfl(c.z, base + 1),
-                                __shfl(c.w, base + 1));
-  // outputs, spread over the quad
-  if (q == 0) {
-    const float a1 = __builtin_amdgcn_fmed3f(c1.w, 0.0f, 1.0f);
-    a.d1[p] = n ? t.z1 : 1.0f;
-    a.layer1[p] = make_float4(a1 * c1.x, a1 * c1.y, a1 * c1.z, a1);
-    a.count[p] = n;
-    if (a.sel) a.sel[p] = make_uint2(t.k1, t.k2);
-  } else if (q == 1 && pass2) {
-    const float a2 = __builtin_amdgcn_fmed3f(c2.w, 0.0f, 1.0f);
-    a.layer2[j2 * g.w2 + i2] = make_float4(a2 * c2.x, a2 * c2.y, a2 * c2.z, a2);
-  } else if (q >= 2 && pass3) {
-    // exact removal of the two selected layers leaves the tail
-    if (t.k1 != kNone) {
-      const Terms r = frag_terms(c1);
-      s.a -= r.a; s.r -= r.r; s.g -= r.g; s.b -= r.b; s.lg -= r.lg;
-    }
-    if (t.k2 != kNone) {
-      const Terms r = frag_terms(c2);
-      s.a -= r.a; s.r -= r.r; s.g -= r.g; s.b -= r.b; s.lg -= r.lg;
-    }
-    float4* o = a.tail + 2 * (size_t)(j3 * g.w3 + i3);
+  // lane 2 -> d1, lane 3 -> N
+  if (q >= 2) {
+    uint32_t* dst = q == 2 ? reinterpret_cast<uint32_t*>(a.d1) + p : a.count + p;
+    *dst = q == 2 ? __float_as_uint(n ? t.z1 : 1.0f) : n;
+  }
+  if (a.sel && q == 0) a.sel[p] = make_uint2(t.k1, t.k2);
+
+  if (pass3) {
+    // reduce-scatter of the channel sums (alpha, r, g, b): lane q ends with
+    // the quad total of channel q; the log-transmittance sum is all-reduced
+    const bool hi = q & 2, odd = q & 1;
+    const uint64_t y0 = (hi ? s.g : s.a) + qperm<kXor2>(hi ? s.a : s.g);
+    const uint64_t y1 = (hi ? s.b : s.r) + qperm<kXor2>(hi ? s.r : s.b);
+    uint64_t v = (odd ? y1 : y0) + qperm<kXor1>(odd ? y0 : y1);
+    uint64_t lg = s.lg + qperm<kXor1>(s.lg);
+    lg += qperm<kXor2>(lg);
+    // exact removal of the two selected layers leaves the tail (a missing
+    // layer is all zero, so its terms are zero)
+    const float m1 = q == 0 ? 1.0f : (q == 1 ? c1.x : (q == 2 ? c1.y : c1.z));
+    const float m2 = q == 0 ? 1.0f : (q == 1 ? c2.x : (q == 2 ? c2.y : c2.z));
+    const float a1 = __builtin_amdgcn_fmed3f(c1.w, 0.0f, 1.0f), a2 = __builtin_amdgcn_fmed3f(c2.w, 0.0f, 1.0f);
+    v -= (uint64_t)q24_term(a1 * kQ24, m1) + (uint64_t)q24_term(a2 * kQ24, m2);
+    lg -= lg_term(a1) + lg_term(a2);
+    // x = (N, t_tail, Ct = S / A) and A, one channel per lane
     const bool tail = n > 2;
-    const float inv = (tail && s.a) ? 1.0f / (float)s.a : 0.0f;
-    if (q == 2) {
-      const float tt = tail ? exp2f(-(float)s.lg * (1.0f / kQ27)) : 1.0f;
-      o[0] = make_float4((float)n, tt, (float)s.r * inv, (float)s.g * inv);
-    } else {
-      o[1] = make_float4((float)s.b * inv, tail ? (float)s.a * (1.0f / kQ24) : 0.0f, 0.0f, 0.0f);
-    }
+    const float tv = u64_to_f32(v);
+    const float A = qperm<kBc0>(tv);
+    const float inv = (tail && A > 0.0f) ? __builtin_amdgcn_rcpf(A) : 0.0f;
+    const float o = q == 0 ? (tail ? A * (1.0f / kQ24) : 0.0f) : tv * inv;
+    const float tt = tail ? __builtin_amdgcn_exp2f(-u64_to_f32(lg) * (1.0f / kQ27)) : 1.0f;
+    // record [N, t_tail, Cr, Cg | Cb, A, 0, 0] as one float2 per lane
+    const float nx = qperm<kRot1>(o), oa = qperm<kBc0>(o);
+    float2 rec;
+    rec.x = q == 0 ? (float)n : (q == 1 ? o : (q == 2 ? nx : 0.0f));
+    rec.y = q == 0 ? tt : (q == 1 ? nx : (q == 2 ? oa : 0.0f));
+    reinterpret_cast<float2*>(a.tail + 2 * (size_t)(j3 * g.w3 + i3))[q] = rec;
   }
   uint32_t errf = (q == 0 && n > a.max_n) ? STARNT_DERR_COUNT : 0u;
   errf |= zmax > kOne ? STARNT_DERR_DEPTH : 0u;

@@ -72,7 +72,8 @@ struct PixRaw {
 template <bool COMP>
 __device__ __forceinline__ void issue_loads(const InferArgs& a, const Grids& g, int p, PixRaw& r) {
   r.n = a.count[p];
-  const int x = p % a.W, y = p / a.W;
+  int x, y;
+  pixel_xy(p, a.W, x, y);
   const Taps tx = axis_taps(x, a.W, g.w3), ty = axis_taps(y, a.H, g.h3);
   const size_t i3[4] = {(size_t)ty.i0 * g.w3 + tx.i0, (size_t)ty.i0 * g.w3 + tx.i1,
                         (size_t)ty.i1 * g.w3 + tx.i0, (size_t)ty.i1 * g.w3 + tx.i1};

@@ -23,18 +23,38 @@ int hip_status(hipError_t e, const char* what);
 
 // ---- device helpers -------------------------------------------------------
 
+// floor(n / d) for n < 2^30, 1 <= d < 2^24 and a quotient below 2^15, exactly.
+// The FP32 estimate n * rcp(d) carries a relative error below 2^-22 (n rounded
+// once, the hardware reciprocal within 1 ulp, the product rounded once), so its
+// absolute error is below 2^-7 and its truncation is the true quotient or one
+// off; the remainder's sign and size fix that one step. About a third of the
+// instructions of the general 32-bit division.
+__device__ __forceinline__ uint32_t udiv_small(uint32_t n, uint32_t d) {
+  const float f = (float)n * __builtin_amdgcn_rcpf((float)d);
+  uint32_t q = (uint32_t)f;
+  const int32_t r = (int32_t)(n - q * d);
+  q = r < 0 ? q - 1u : (r >= (int32_t)d ? q + 1u : q);
+  return q;
+}
+
+// Pixel coordinates of linear pixel index p in a frame of width W.
+__device__ __forceinline__ void pixel_xy(int p, int W, int& x, int& y) {
+  y = (int)udiv_small((uint32_t)p, (uint32_t)W);
+  x = p - y * W;
+}
+
 // Grid index i of the W_s-sample grid that samples full-resolution coordinate
 // x (sample i sits at floor((2i+1) W / (2 W_s))), or -1 when x is not sampled.
-// Frame sides are at most 16384, so every product below is below 2^30 and
-// 32-bit integer arithmetic is exact.
+// Frame sides are at most 16384, so every product below is below 2^30, every
+// quotient at most 16384, and the 32-bit arithmetic is exact.
 __device__ __forceinline__ int grid_index_of(int x, int W, int Ws) {
   if (Ws >= W) return x;
   // smallest i with (2i+1) W >= 2 Ws x
   const int num = 2 * Ws * x - W;
   const int den = 2 * W;
-  const int i = num <= 0 ? 0 : (int)(((unsigned)num + (unsigned)den - 1u) / (unsigned)den);
+  const int i = num <= 0 ? 0 : (int)udiv_small((unsigned)num + (unsigned)den - 1u, (unsigned)den);
   if (i >= Ws) return -1;
-  const int pos = (int)((unsigned)((2 * i + 1) * W) / (unsigned)(2 * Ws));
+  const int pos = (int)udiv_small((unsigned)((2 * i + 1) * W), (unsigned)(2 * Ws));
   return pos == x ? i : -1;
 }
 
@@ -50,7 +70,7 @@ __device__ __forceinline__ Taps axis_taps(int x, int W, int Ws) {
   const int num = (2 * x + 1) * Ws - W;  // >= -W
   const int den = 2 * W;
   // floor division for num >= -den
-  const int q = num >= 0 ? (int)((unsigned)num / (unsigned)den) : -1;
+  const int q = num >= 0 ? (int)udiv_small((unsigned)num, (unsigned)den) : -1;
   const int r = num - q * den;
   t.w1 = (float)r / (float)den;
   t.i0 = q < 0 ? 0 : (q > Ws - 1 ? Ws - 1 : q);
@@ -93,6 +113,7 @@ __device__ __forceinline__ float4 load_rgba(const void* rgba, uint32_t k) {
 int launch_features(const starnt_frags& f, const starnt_sched* sched, const starnt_feats& o, hipStream_t s);
 int launch_exact(const starnt_frags& f, const float bg[3], float* rgb, float* fstar, uint32_t* err,
                  hipStream_t s);
+int launch_baseline(const starnt_frags& f, int32_t method, const float bg[3], float* rgb, hipStream_t s);
 int launch_composite(const starnt_feats& o, const float* tail_rgb, const starnt_sched* sched, int W, int H,
                      const float bg[3], int mode, float* rgb, hipStream_t s);
 int launch_infer(const starnt_mlp& m, const float* tail, const uint32_t* count, const starnt_sched* sched,

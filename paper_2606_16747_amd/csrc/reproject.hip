@@ -25,7 +25,8 @@ __global__ __launch_bounds__(256) void reproject_kernel(ReprojArgs a) {
   const int P = a.W * a.H;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
-  const int px = p % a.W, py = p / a.W;
+  int px, py;
+  pixel_xy(p, a.W, px, py);
   const float X0 = (2.0f * px + 1.0f) / (float)a.W - 1.0f;
   const float X1 = 1.0f - (2.0f * py + 1.0f) / (float)a.H;
   const float X2 = a.d1[p];

@@ -205,6 +205,21 @@ int starnt_composite(const starnt_frags* frags, const starnt_feats* feats, const
                      const starnt_sched* sched, const float* bg, int32_t mode, float* rgb, float* fstar,
                      void* stream);
 
+/* Cheap approximate baselines of the evaluation (Sec. 4), for quality per
+ * millisecond on the same fragment lists; rgb [P][3], bg a host float[3].
+ * STARNT_BASE_WBOIT: weighted blended OIT (McGuire and Bavoil 2013) with the
+ *   window-depth weight w(z, a) = a max(1e-2, 3e3 (1 - z)^3),
+ *   C = (sum w a c / sum w a)(1 - R) + R C_b, R = prod (1 - a) (the ratio is 0
+ *   when sum w a = 0). Order independent.
+ * STARNT_BASE_OVER_LIST: eq (1) applied to each list in stored order with no
+ *   sort (the naive blend whose error is the paper's E_random).
+ * Alpha is clamped to [0, 1]; no device error word (depth or alpha outside
+ *   the domain give meaningless colours, never a fault). Reads offsets, depth
+ *   and rgba; prim may be NULL. */
+#define STARNT_BASE_WBOIT 0
+#define STARNT_BASE_OVER_LIST 1
+int starnt_baseline(const starnt_frags* frags, int32_t method, const float* bg, float* rgb, void* stream);
+
 /* Quadtree update from a real frame's composite rgb [P][3] and counts [P]
  * (Sec. 3.1): per base tile, the corner-sample distance D of every internal
  * node (mean of the six pairwise Euclidean RGB distances of its corners),
@@ -258,6 +273,38 @@ double starnt_wbar(const uint32_t* hist4);
 void starnt_pass_scales(double wbar, double* s2, double* s3);
 /* grid size max(1, min(n, ceil(s n))) */
 int32_t starnt_grid_dim(int32_t n, double s);
+
+/* Adaptive interpolation interval (Sec. 3.3, interpolated frames): one real
+ * render is followed by interval - 1 interpolated frames, interval <= 4. The
+ * interval is chosen from the measured frame costs at the start of each
+ * interval: the smallest k in 1..max_interval whose mean frame time
+ * (real + (k - 1) interp) / k meets target_ms; k = 1 when a real frame alone
+ * meets it, and also (standard rendering, no interpolation) when even
+ * max_interval cannot meet it. Until an interpolated frame has been measured,
+ * a real frame that misses the target is followed by a probing interval of 2.
+ * Costs are running means: m <- m + smoothing (sample - m), the first sample
+ * taken as is. Host only; the caller owns the struct. */
+typedef struct {
+  double target_ms;     /* frame-time target, 1000 / target fps; > 0        */
+  double smoothing;     /* weight of a new sample in the running means, (0, 1] */
+  double real_ms;       /* running mean cost of a real frame (< 0: none yet)  */
+  double interp_ms;     /* running mean cost of an interpolated frame (< 0)   */
+  int32_t max_interval; /* 1..4                                             */
+  int32_t interval;     /* current interval (1 = every frame real)          */
+  int32_t pos;          /* frames of the current interval already issued    */
+  int32_t pad;
+} starnt_interval;
+
+/* Reset s; EINVAL for target_ms <= 0, smoothing outside (0, 1] or
+ * max_interval outside 1..4. */
+int starnt_interval_init(starnt_interval* s, double target_ms, int32_t max_interval, double smoothing);
+/* Kind of the next frame: 1 = real render, 0 = interpolated (from the last
+ * real frame). A new interval starts, and is re-chosen, at every real frame.
+ * Returns -1 for a NULL s. */
+int starnt_interval_next(starnt_interval* s);
+/* Record the measured cost of a finished frame of the given kind.
+ * EINVAL for a NULL s or a negative or non-finite time. */
+int starnt_interval_report(starnt_interval* s, int32_t was_real, double ms);
 
 /* bytes of workspace a call needs (a, b, c as listed at each call) */
 size_t starnt_workspace_size(int32_t kind, int64_t a, int64_t b, int64_t c);

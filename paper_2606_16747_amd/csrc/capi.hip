@@ -128,6 +128,22 @@ int starnt_composite(const starnt_frags* frags, const starnt_feats* feats, const
   return launch_composite(*feats, tail_rgb, sched, W, H, bg, mode, rgb, as_stream(stream));
 }
 
+int starnt_baseline(const starnt_frags* frags, int32_t method, const float* bg, float* rgb, void* stream) {
+  if (!frags) return fail(STARNT_EINVAL, "starnt_baseline: frags is NULL");
+  int rc = check_frame(frags->width, frags->height, "starnt_baseline");
+  if (rc) return rc;
+  if (!frags->offsets) return fail(STARNT_EINVAL, "starnt_baseline: offsets is NULL");
+  if (frags->num_frags > 0 && (!frags->depth || !frags->rgba))
+    return fail(STARNT_EINVAL, "starnt_baseline: NULL fragment array");
+  if (frags->rgba_dtype != STARNT_F32 && frags->rgba_dtype != STARNT_F16)
+    return fail(STARNT_EINVAL, "starnt_baseline: rgba_dtype must be STARNT_F32 or STARNT_F16");
+  if (frags->num_frags >= (1ull << 32)) return fail(STARNT_EINVAL, "starnt_baseline: num_frags must be below 2^32");
+  if (!bg || !rgb) return fail(STARNT_EINVAL, "starnt_baseline: NULL bg or rgb");
+  if (method != STARNT_BASE_WBOIT && method != STARNT_BASE_OVER_LIST)
+    return fail(STARNT_EINVAL, "starnt_baseline: unknown method");
+  return launch_baseline(*frags, method, bg, rgb, as_stream(stream));
+}
+
 int starnt_quadtree(const float* rgb, const uint32_t* count, int32_t width, int32_t height,
                     const starnt_qt_params* params, const uint32_t* prev_mask, uint32_t* mask, uint8_t* level,
                     starnt_sched* sched, void* workspace, size_t workspace_bytes, void* stream) {

@@ -91,6 +91,11 @@ def test_host_validation_rejects_bad_arguments(starnt):
     assert lib.starnt_train_step(ctypes.byref(tr), 16, 16, 64, ctypes.byref(ad), 16, 16, 8, None) == 3
     bg = (ctypes.c_float * 3)(1.0, 1.0, 1.0)
     assert lib.starnt_composite(None, None, None, None, bg, 9, 16, None, None) == 1
+    fr = starnt.Frags(8, 8, 16, 16, 16, 0, None, 10, 1)
+    assert lib.starnt_baseline(ctypes.byref(fr), 5, bg, 16, None) == 1  # unknown method
+    assert b"method" in lib.starnt_last_error()
+    assert lib.starnt_baseline(ctypes.byref(fr), 0, bg, None, None) == 1
+    assert lib.starnt_baseline(None, 0, bg, 16, None) == 1
 
 
 def test_product_package_has_no_cpu_fallback():

@@ -408,3 +408,48 @@ def baseline(offsets, depth, rgba, width, height, method, bg=(1.0, 1.0, 1.0)):
     if rc != 0:
         raise ValueError("unknown baseline method %r" % (method,))
     return out
+
+
+# ---------------------------------------------------------------------------
+# adaptive interpolation interval (Sec. 3.3)
+
+def interval_schedule(costs, target_ms, max_interval=4, smoothing=0.25):
+    """Kinds of a sequence of frames under the adaptive interval: frames
+    alternate one real render with (interval - 1) reprojected ones, the
+    interval (at most max_interval <= 4) being re-chosen at every real frame
+    from the running mean costs so the mean frame time meets target_ms with
+    the least interpolation; a real frame that meets the target alone, or a
+    target that even the longest interval misses, means every frame is real.
+    Before any interpolated frame is measured, a real frame over the target
+    is followed by one probing interval of two.
+
+    Reading (the paper states the behaviour, not a rule): "meets" is mean
+    time (real + (k-1) interp) / k <= target; running means move by
+    smoothing * (sample - mean), starting at the first sample.
+
+    costs[t] = (cost if frame t is real, cost if it is interpolated), in ms.
+    Returns (kinds, means): kinds a list of booleans (True = real), means the
+    final (real_ms, interp_ms), None where nothing was measured."""
+    mean = {True: None, False: None}
+    kinds = []
+    interval, pos = 1, 0
+    for t in range(len(costs)):
+        if pos == 0:
+            r, i = mean[True], mean[False]
+            if r is None or r <= target_ms or max_interval < 2:
+                interval = 1
+            elif i is None:
+                interval = 2
+            else:
+                interval = 1
+                for k in range(2, max_interval + 1):
+                    if (r + (k - 1) * i) / k <= target_ms:
+                        interval = k
+                        break
+        real = pos == 0
+        pos = (pos + 1) % interval
+        kinds.append(real)
+        c = costs[t][0 if real else 1]
+        m = mean[real]
+        mean[real] = c if m is None else m + smoothing * (c - m)
+    return kinds, (mean[True], mean[False])

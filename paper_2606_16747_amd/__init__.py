@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libstarnt.so")
 
 F32, F16, BF16, FP8 = 0, 1, 2, 3
 MODE_LEARNED, MODE_F0, MODE_FAVG, MODE_EXACT = 0, 1, 2, 3
+BASE_WBOIT, BASE_OVER_LIST = 0, 1
 WS_QUADTREE, WS_TRAIN = 1, 2
 DERR_DEPTH, DERR_ALPHA, DERR_COUNT = 1, 2, 4
 STATUS = {0: "OK", 1: "EINVAL", 2: "ERANGE", 3: "ENOMEM", 4: "EHIP", 5: "EUNSUPPORTED"}
@@ -72,9 +73,17 @@ class Adam(ctypes.Structure):
                 ("eps", ctypes.c_float), ("step", ctypes.c_int32)]
 
 
+class Interval(ctypes.Structure):
+    _fields_ = [("target_ms", ctypes.c_double), ("smoothing", ctypes.c_double), ("real_ms", ctypes.c_double),
+                ("interp_ms", ctypes.c_double), ("max_interval", ctypes.c_int32), ("interval", ctypes.c_int32),
+                ("pos", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
 assert ctypes.sizeof(Sched) == 64
 
-EXPORTS = ("starnt_features", "starnt_infer", "starnt_infer_composite", "starnt_composite", "starnt_quadtree", "starnt_reproject",
+EXPORTS = ("starnt_features", "starnt_infer", "starnt_infer_composite", "starnt_composite", "starnt_baseline",
+           "starnt_quadtree", "starnt_reproject", "starnt_interval_init", "starnt_interval_next",
+           "starnt_interval_report",
            "starnt_train_step", "starnt_sched_init", "starnt_wbar", "starnt_pass_scales", "starnt_grid_dim",
            "starnt_workspace_size", "starnt_check", "starnt_last_error", "starnt_version")
 
@@ -89,6 +98,10 @@ def _load():
                                            ctypes.POINTER(ctypes.c_float), _P, _P]
     lib.starnt_composite.argtypes = [ctypes.POINTER(Frags), ctypes.POINTER(Feats), _P, _P,
                                      ctypes.POINTER(ctypes.c_float), ctypes.c_int32, _P, _P, _P]
+    lib.starnt_baseline.argtypes = [ctypes.POINTER(Frags), ctypes.c_int32, ctypes.POINTER(ctypes.c_float), _P, _P]
+    lib.starnt_interval_init.argtypes = [ctypes.POINTER(Interval), ctypes.c_double, ctypes.c_int32, ctypes.c_double]
+    lib.starnt_interval_next.argtypes = [ctypes.POINTER(Interval)]
+    lib.starnt_interval_report.argtypes = [ctypes.POINTER(Interval), ctypes.c_int32, ctypes.c_double]
     lib.starnt_quadtree.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(QtParams), _P, _P, _P,
                                     _P, _P, ctypes.c_size_t, _P]
     lib.starnt_reproject.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), _P,
@@ -233,8 +246,15 @@ class DeviceMlp:
 # ---------------------------------------------------------------------------
 # the C calls
 
+# number of starnt_features launches issued by this process (lets a profiler's
+# per-dispatch records be matched to a caller's own launches)
+features_launches = 0
+
+
 def starnt_features(frags: DeviceFrags, sched, feats: FeatBuffers, stream=None):
+    global features_launches
     _check(lib.starnt_features(ctypes.byref(frags._c), _ptr(sched), ctypes.byref(feats._c), _stream(stream)))
+    features_launches += 1
 
 
 def starnt_infer(mlp: DeviceMlp, tail, count, sched, width, height, tail_rgb, stream=None):
@@ -253,6 +273,30 @@ def starnt_composite(frags, feats, tail_rgb, sched, bg, mode, rgb, fstar=None, s
     _check(lib.starnt_composite(ctypes.byref(frags._c) if frags is not None else None,
                                 ctypes.byref(feats._c) if feats is not None else None, _ptr(tail_rgb), _ptr(sched),
                                 bgc, int(mode), _ptr(rgb), _ptr(fstar), _stream(stream)))
+
+
+def starnt_baseline(frags, method, bg, rgb, stream=None):
+    bgc = (ctypes.c_float * 3)(*[float(v) for v in bg])
+    _check(lib.starnt_baseline(ctypes.byref(frags._c) if frags is not None else None, int(method), bgc, _ptr(rgb),
+                               _stream(stream)))
+
+
+def starnt_interval_init(target_ms, max_interval=4, smoothing=0.25) -> Interval:
+    s = Interval()
+    _check(lib.starnt_interval_init(ctypes.byref(s), float(target_ms), int(max_interval), float(smoothing)))
+    return s
+
+
+def starnt_interval_next(s: Interval) -> bool:
+    """True when the next frame is a real render, False for an interpolated one."""
+    r = lib.starnt_interval_next(ctypes.byref(s))
+    if r < 0:
+        raise StarntError(1, "starnt_interval_next: NULL state")
+    return bool(r)
+
+
+def starnt_interval_report(s: Interval, was_real, ms):
+    _check(lib.starnt_interval_report(ctypes.byref(s), int(bool(was_real)), float(ms)))
 
 
 def starnt_quadtree(rgb, count, width, height, params: QtParams, prev_mask, mask, level, sched, workspace,

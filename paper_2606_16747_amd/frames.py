@@ -12,8 +12,9 @@ import numpy as np
 import torch
 
 from . import (MODE_EXACT, MODE_LEARNED, WS_QUADTREE, DeviceFrags, DeviceMlp, FeatBuffers, QtParams,
-               starnt_composite, starnt_features, starnt_infer_composite, starnt_quadtree, starnt_reproject,
-               starnt_sched_init, starnt_workspace_size, workspace)
+               starnt_composite, starnt_features, starnt_infer_composite, starnt_interval_init,
+               starnt_interval_next, starnt_interval_report, starnt_quadtree, starnt_reproject, starnt_sched_init,
+               starnt_workspace_size, workspace)
 
 
 def m_minus_i(vp_real, vp_cur):
@@ -80,6 +81,65 @@ class Renderer:
         self._call("reproject", lambda: starnt_reproject(self.rgb_real, self.feats.d1, self.W, self.H, mmi, out, None,
                                                          stream))
         return out
+
+
+class AdaptiveSequence:
+    """Frames of a sequence, each a real render or a reprojection of the last
+    real frame, as the adaptive interval policy (starnt_interval_*) decides
+    from measured frame costs (Sec. 3.3: at most four frames per real render,
+    every frame real when the target is out of reach).
+
+    Costs are measured with events around each frame and reported when the
+    next frame is issued (one frame late, so the host never waits on the
+    frame it just queued). `cost` may instead be a callable (t, real) -> ms
+    that supplies them, which makes a sequence deterministic. The output of a
+    real frame is the source of the frames interpolated after it, so it must
+    stay untouched until the next real frame."""
+
+    def __init__(self, renderer: Renderer, target_ms, max_interval=4, smoothing=0.25, cost=None):
+        self.r = renderer
+        self.state = starnt_interval_init(target_ms, max_interval, smoothing)
+        self.cost = cost
+        self.vp_real = None
+        self.t = 0
+        self.kinds = []
+        self._pending = None
+
+    def _report(self):
+        if self._pending is None:
+            return
+        t, real, a, b = self._pending
+        if self.cost is not None:
+            ms = float(self.cost(t, real))
+        else:
+            b.synchronize()
+            ms = a.elapsed_time(b)
+        starnt_interval_report(self.state, real, ms)
+        self._pending = None
+
+    def frame(self, vp, frags_fn, out, stream=None):
+        """Render frame t into out; frags_fn() gives its fragment lists and is
+        called only for a real frame. Returns True for a real frame."""
+        self._report()
+        real = starnt_interval_next(self.state)
+        if self.t == 0 or self.r.n_real == 0:
+            assert real, "the first frame of a sequence is real"
+        a = b = None
+        if self.cost is None:
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream) if stream is not None else a.record()
+        if real:
+            self.r.real_frame(frags_fn(), out, stream)
+            self.vp_real = np.asarray(vp, np.float64)
+        else:
+            self.r.interpolated_frame(m_minus_i(self.vp_real, vp), out, stream)
+        if b is not None:
+            b.record(stream) if stream is not None else b.record()
+        self._pending = (self.t, real, a, b)
+        self.kinds.append(real)
+        self.t += 1
+        return real
 
 
 def exact_frame(frags: DeviceFrags, out, bg=(1.0, 1.0, 1.0), fstar=None, stream=None):

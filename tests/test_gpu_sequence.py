@@ -1,0 +1,54 @@
+"""A sequence under the adaptive interpolation interval (Sec. 3.3): with
+injected frame costs the library's policy picks the oracle's real and
+interpolated frames, each interpolated frame is the reprojection of the last
+real frame's output (oracle gather, same FP32 inputs), and each real frame is
+the renderer's full real-frame result."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import sync, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def test_adaptive_sequence_follows_policy_and_reprojects(starnt, gpu, sg, oracle_mod):
+    from paper_2606_16747_amd import frames as fm
+    sc = sg.Scene("c2_1080p", width=256, height=144, num_tris=300)
+    n = 10
+    frames = [sc.frame(t) for t in range(n)]
+    W, H = 256, 144
+    P = W * H
+    costs = [(50.0, 2.0)] * n  # target 16.7 ms: probe, then intervals of 4
+    want_kinds, _ = oracle_mod.interval_schedule(costs, 16.7, 4, 0.5)
+    assert want_kinds == [True, True, False, True, False, False, False, True, False, False]
+    Ws, bs = sg.init_mlp((16, 32, 32, 3), out_bias=0.05)
+    mlp = starnt.DeviceMlp(Ws, bs, starnt.F32)
+    rend = fm.Renderer(W, H, mlp)
+    rend.reset()
+    seq = fm.AdaptiveSequence(rend, 16.7, 4, 0.5, cost=lambda t, real: costs[t][0 if real else 1])
+    # a second renderer fed only the real frames gives their expected outputs
+    ref = fm.Renderer(W, H, mlp)
+    ref.reset()
+    outs = [torch.empty(P, 3, dtype=torch.float32, device="cuda") for _ in range(n)]
+    last_real = None
+    checked = 0
+    for t in range(n):
+        real = seq.frame(frames[t].vp, lambda: starnt.DeviceFrags.from_frame(frames[t], max_per_pixel=64), outs[t])
+        sync()
+        assert real == want_kinds[t], t
+        if real:
+            r_out = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+            ref.real_frame(starnt.DeviceFrags.from_frame(frames[t], max_per_pixel=64), r_out)
+            sync()
+            assert torch.equal(outs[t], r_out), t
+            last_real = t
+        else:
+            d1 = to_np(rend.feats.d1)
+            mmi = oracle_mod.m_minus_i(frames[last_real].vp, frames[t].vp).astype(np.float32)
+            want, _, margin = oracle_mod.reproject(to_np(outs[last_real]), d1, mmi.astype(np.float64), W, H)
+            ok = margin >= 1e-4
+            assert ok.mean() > 0.995
+            np.testing.assert_array_equal(to_np(outs[t])[ok], want[ok])
+            checked += 1
+    assert checked == 6

@@ -60,6 +60,27 @@ def feature_pass_bytes(fr, grids):
     return reads + writes, int(n[s3].sum())
 
 
+FEATURE_SOURCES = ("paper_2606_16747_amd/csrc/features.hip", "paper_2606_16747_amd/csrc/internal.h")
+COUNTERS_RECORD = "profiles/features_c2_1080p_counters.json"
+PROFILE_SUMMARY = "profiles/features_c2_1080p.md"
+PROFILE_COMMANDS = (
+    "rocprofv3 --kernel-trace --stats -d $PROF_DIR/trace -o trace -- "
+    "python3 $REPO/bench.py --no-cpu-baseline --calib-copy-mb 512 > $PROF_DIR/trace.json",
+    "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'features_kernel|copyBuffer' -d $PROF_DIR/fetch -o fetch "
+    "-- python3 $REPO/bench.py --no-cpu-baseline --calib-copy-mb 512 > $PROF_DIR/fetch.json",
+    "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex 'features_kernel|copyBuffer' -d $PROF_DIR/write -o write "
+    "-- python3 $REPO/bench.py --no-cpu-baseline --calib-copy-mb 512 > $PROF_DIR/write.json",
+    "python3 $REPO/bench.py --profile-summary $PROF_DIR --calib-copy-mb 512",
+)
+
+
+def feature_sources_sha256():
+    h = hashlib.sha256()
+    for rel in FEATURE_SOURCES:
+        h.update(open(os.path.join(ROOT, rel), "rb").read())
+    return h.hexdigest()
+
+
 def counters_traffic(path, src_hash):
     """HBM bytes per features launch measured by rocprofv3 counters, if the
     committed record was taken on the current kernel source."""
@@ -67,9 +88,98 @@ def counters_traffic(path, src_hash):
         rec = json.load(open(path))
     except Exception:
         return None
-    if rec.get("features_hip_sha256") != src_hash:
+    if rec.get("source_sha256") != src_hash:
         return None
     return rec.get("bytes_per_launch")
+
+
+def profile_summary(d, calib_mb):
+    """Summarise the three profiled runs of this bench (PROFILE_COMMANDS: kernel
+    trace, FETCH_SIZE pass, WRITE_SIZE pass; each run's JSON line saved as
+    <d>/<name>.json beside its database) into the committed summary and the
+    counters record. The features launches of the timed region are picked by
+    their order among the process's features dispatches."""
+    import glob
+    import sqlite3
+
+    def db(name):
+        return sqlite3.connect(glob.glob(os.path.join(d, name, "*_results.db"))[0])
+
+    def bench_line(path):
+        for line in reversed(open(path).read().splitlines()):
+            if line.startswith("{") and '"metric"' in line:
+                return json.loads(line)
+        raise SystemExit("no bench line in " + path)
+
+    bench = {n: bench_line(os.path.join(d, n + ".json")) for n in ("trace", "fetch", "write")}
+    i0, i1 = bench["trace"]["roofline"]["dispatch_range"]
+    for n in ("fetch", "write"):
+        if bench[n]["roofline"]["dispatch_range"] != [i0, i1]:
+            raise SystemExit("profiled runs launched different sequences")
+    con = db("trace")
+    feat = con.execute("select dispatch_id, duration from kernels where name like '%features_kernel%' "
+                       "order by dispatch_id").fetchall()
+    timed = [dur for _, dur in feat[i0:i1]]
+    top = con.execute("select name, total_calls, total_duration, average, percentage from top_kernels "
+                      "order by total_duration desc limit 12").fetchall()
+
+    def per_dispatch(name, counter):
+        c = db(name)
+        rows = c.execute("select dispatch_id, kernel_name, sum(value) from counters_collection where counter_name = ? "
+                         "group by dispatch_id order by dispatch_id", (counter,)).fetchall()
+        f = [v for _, k, v in rows if "features_kernel" in k]
+        cp = [v for _, k, v in rows if "copyBuffer" in k]
+        return f[i0:i1], max(cp)
+
+    fk, fcal = per_dispatch("fetch", "FETCH_SIZE")
+    wk, wcal = per_dispatch("write", "WRITE_SIZE")
+    ffac, wfac = calib_mb * 1024.0 / fcal, calib_mb * 1024.0 / wcal
+    fetch_b = float(np.mean(fk)) * 1024 * ffac
+    write_b = float(np.mean(wk)) * 1024 * wfac
+    alg = bench["trace"]["roofline"]["algorithmic_bytes_per_launch"]
+    rec = {
+        "kernel": "starnt_features (features_kernel<false>), 1080p sequence, timed region",
+        "sources": list(FEATURE_SOURCES),
+        "source_sha256": feature_sources_sha256(),
+        "launches": i1 - i0,
+        "fetch_kib_per_launch_raw": round(float(np.mean(fk)), 1),
+        "write_kib_per_launch_raw": round(float(np.mean(wk)), 1),
+        "copy_calibration_mib": calib_mb,
+        "fetch_factor": round(ffac, 4),
+        "write_factor": round(wfac, 4),
+        "fetch_bytes_per_launch": int(fetch_b),
+        "write_bytes_per_launch": int(write_b),
+        "bytes_per_launch": int(fetch_b + write_b),
+        "algorithmic_bytes_per_launch": alg,
+        "traffic_over_algorithmic": round((fetch_b + write_b) / alg, 4),
+        "commands": list(PROFILE_COMMANDS),
+    }
+    with open(os.path.join(ROOT, COUNTERS_RECORD), "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    lines = ["# starnt_features on the 1080p sequence: rocprofv3 summary", "",
+             "Commands (REPO = the repository root, PROF_DIR = an output folder; run from /tmp with "
+             "TMPDIR=/tmp):", ""]
+    lines += ["    " + c for c in PROFILE_COMMANDS]
+    lines += ["", "## Kernel trace (`--kernel-trace --stats`), top kernels of the whole run", "",
+              "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+    for name, calls, tot, avg, pct in top:
+        short = name.replace("(anonymous namespace)::", "").split("(")[0][:90]
+        lines.append("| %s | %d | %.2f | %.2f | %.1f |" % (short, calls, tot / 1e3, avg, pct))
+    lines += ["", "## Features launches of the timed region (dispatches %d..%d of the kernel)" % (i0, i1 - 1), "",
+              "* rocprofv3 average duration: %.2f us (min %.2f, max %.2f, %d launches)"
+              % (np.mean(timed) / 1e3, np.min(timed) / 1e3, np.max(timed) / 1e3, len(timed)),
+              "* HIP-event average inside bench.py (same run): %.2f us" % bench["trace"]["roofline"]["avg_launch_us"],
+              "* algorithmic bytes per launch: %d" % alg,
+              "* FETCH_SIZE %.1f KiB x %.3f (copy calibration) = %d B; WRITE_SIZE %.1f KiB x %.3f = %d B"
+              % (rec["fetch_kib_per_launch_raw"], ffac, rec["fetch_bytes_per_launch"], rec["write_kib_per_launch_raw"],
+                 wfac, rec["write_bytes_per_launch"]),
+              "* measured HBM traffic / algorithmic bytes: %.3f" % rec["traffic_over_algorithmic"],
+              "* calibration: one %d MiB device-to-device copy in each counter run; factor = copy size / counter"
+              % calib_mb, ""]
+    with open(os.path.join(ROOT, PROFILE_SUMMARY), "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
 
 
 def cpu_baseline(fr0, fr1, mlp_w, mlp_b, bg, budget_s):
@@ -104,7 +214,12 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--profile-summary", metavar="DIR", default=None,
+                    help="summarise the profiled runs under DIR (no GPU work) and exit")
     args = ap.parse_args()
+    if args.profile_summary:
+        profile_summary(args.profile_summary, args.calib_copy_mb or 512)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
               file=sys.stderr)
@@ -216,12 +331,14 @@ def main():
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
+    fl0 = st.features_launches
     e0.record()
     for _ in range(args.steps):
         star_step()
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
+    fl1 = st.features_launches
     rend.timer = None
     step_ms = e0.elapsed_time(e1) / args.steps
     feat_ms = [a.elapsed_time(b) for a, b in ev]
@@ -240,6 +357,33 @@ def main():
     torch.cuda.synchronize()
     exact_step_ms = x0.elapsed_time(x1) / args.steps
     log("exact step %.3f ms" % exact_step_ms)
+
+    # the evaluation's cheap baselines on the same lists (Sec. 4): WBOIT and
+    # stored-order over (the naive blend behind E_random), every frame
+    base_out = torch.empty(P, 3, dtype=torch.float32, device=dev)
+    base_ms, base_psnr = {}, {}
+    for name, method in (("wboit", st.BASE_WBOIT), ("over_stored_order", st.BASE_OVER_LIST)):
+        for _ in range(args.warmup):
+            for t in range(NF):
+                st.starnt_baseline(frags[t], method, bg, base_out)
+        torch.cuda.synchronize()
+        b0 = torch.cuda.Event(enable_timing=True)
+        b1 = torch.cuda.Event(enable_timing=True)
+        b0.record()
+        for _ in range(args.steps):
+            for t in range(NF):
+                st.starnt_baseline(frags[t], method, bg, base_out)
+        b1.record()
+        torch.cuda.synchronize()
+        base_ms[name] = b0.elapsed_time(b1) / args.steps / NF
+        vals = []
+        for t in range(NF):
+            st.starnt_baseline(frags[t], method, bg, base_out)
+            torch.cuda.synchronize()
+            d = (base_out - exact[t]).double()
+            vals.append(float((d * d).mean()))
+        base_psnr[name] = (float(np.mean([10 * np.log10(1.0 / v) for v in vals])), float(np.mean(vals)))
+    log("baselines ms/frame %s" % base_ms)
 
     # quality of the last timed step against the exact composite
     star_step()
@@ -362,9 +506,7 @@ def main():
     feat_total_s = sum(feat_ms) / 1e3
     achieved = alg_bytes / feat_total_s / 1e9
     frags_read = sum(host[t].num_frags for t in real_ts) * args.steps
-    src = open(os.path.join(ROOT, "paper_2606_16747_amd", "csrc", "features.hip"), "rb").read()
-    traffic = counters_traffic(os.path.join(ROOT, "profiles", "features_c2_1080p_counters.json"),
-                               hashlib.sha256(src).hexdigest())
+    traffic = counters_traffic(os.path.join(ROOT, COUNTERS_RECORD), feature_sources_sha256())
 
     total_frags = sum(f.num_frags for f in host)
     value = total_frags / (step_ms / 1e3) / 1e9
@@ -402,6 +544,9 @@ def main():
         "psnr_db_interpolated_frames": round(float(np.mean(psnr[1::2])), 2),
         "psnr_db_without_network": {"favg_real": round(float(np.mean(psnr_favg[0::2])), 2),
                                     "f0_real": round(float(np.mean(psnr_f0[0::2])), 2)},
+        "mse_mean": round(float(np.mean([10 ** (-v / 10) for v in psnr])), 8),
+        "baselines": {k: {"ms_per_frame": round(base_ms[k], 4), "psnr_db_mean": round(base_psnr[k][0], 2),
+                          "mse_mean": round(base_psnr[k][1], 8)} for k in base_ms},
         "kernel_gfrag_per_s": round(frags_read / feat_total_s / 1e9, 2),
         "kernels_us": breakdown,
         "grids": {str(k): v for k, v in grids.items()},
@@ -417,7 +562,8 @@ def main():
                      "traffic": traffic,
                      "kernel": "starnt_features (passes 1-3)",
                      "algorithmic_bytes_per_launch": int(alg_bytes / args.steps / len(real_ts)),
-                     "avg_launch_us": round(1e3 * float(np.mean(feat_ms)), 2)},
+                     "avg_launch_us": round(1e3 * float(np.mean(feat_ms)), 2),
+                     "dispatch_range": [fl0, fl1]},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

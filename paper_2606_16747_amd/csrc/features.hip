@@ -9,17 +9,26 @@
 //      A = sum a, S = sum a c (a c rounded once in FP32), Lg = sum -log2(1 - a),
 //    giving x = (N, t_tail = 2^-Lg, Ct = S / A) (Sec. 3.3).
 // Integer sums make every output independent of the order of a list.
-// Scales: A and S in Q24 (lane-local 32-bit partial sums, folded into 64 bits
-// every 128 steps so they cannot overflow), Lg in Q27 in 64 bits; an opaque
-// fragment (a = 1) adds 2^36 to Lg, so 2^-Lg is exactly 0 while it is in the
-// tail and the exact subtraction removes it when it is a selected layer.
+// Scales: A and S in Q24, Lg in Q27 in 64 bits; an opaque fragment (a = 1)
+// adds 2^36 to Lg, so 2^-Lg is exactly 0 while it is in the tail and the
+// exact subtraction removes it when it is a selected layer. Lists of up to
+// 255 fragments keep A and S in 32 bits end to end; a wave holding a longer
+// list takes a 64-bit variant (lane-local 32-bit partials folded into 64 bits
+// every 128 steps), chosen once per wave.
 //
 // Memory layout of the work: four lanes own a pixel and stride through its
 // list together, so every load instruction of a quad covers a contiguous run
 // of the CSR arrays (16 B of depth, 64 B of RGBA) that is consumed at once;
 // a wave streams 16 neighbouring pixels, whose lists are adjacent in memory.
-// No LDS and no barriers: the per-lane partial state (top-2 keys, 64-bit
-// fixed-point sums) is merged across the quad with register shuffles.
+// Pixels outside the pass-3 grid skip the RGBA loads inside the same loop
+// (their terms are zero), so a wave never runs two loop variants.
+// No LDS and no barriers: the per-lane partial state (top-2 keys, fixed-point
+// sums) is merged across the quad with DPP quad permutations; after the
+// merge each lane of the quad finishes one colour channel.
+//
+// The kernel is bound by VALU issue rather than by HBM (64-wide waves, a few
+// dozen instructions per fragment), so the code keeps per-fragment work to
+// straight-line compares, selects and one-instruction roundings.
 #include "internal.h"
 
 namespace starnt {
@@ -31,6 +40,7 @@ constexpr uint64_t kOpaque = 1ull << 36;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kOne = 0x3F800000u;  // bits of 1.0f
 constexpr int kG = 4;                   // lanes per pixel
+constexpr uint32_t kNarrow = 255;       // longest list with 32-bit channel sums
 constexpr uint32_t kFold = 128;         // lane steps between 32 -> 64-bit folds
 
 // Quad permutations (DPP quad_perm, lane i reads lane perm[i] of its quad).
@@ -50,11 +60,6 @@ template <int CTRL>
 __device__ __forceinline__ uint64_t qperm(uint64_t v) {
   return (uint64_t)qperm<CTRL>((uint32_t)v) | ((uint64_t)qperm<CTRL>((uint32_t)(v >> 32)) << 32);
 }
-// u64 -> FP32 as hi * 2^32 + lo (at most one rounding more than a direct
-// conversion; the sums here stay far below 2^53)
-__device__ __forceinline__ float u64_to_f32(uint64_t v) {
-  return __builtin_fmaf((float)(uint32_t)(v >> 32), 4294967296.0f, (float)(uint32_t)v);
-}
 
 struct FeatArgs {
   int W, H;
@@ -73,39 +78,48 @@ struct FeatArgs {
   uint32_t* err;
 };
 
-// Fixed-point terms of one fragment, rounded to nearest even (unbiased, so
-// the error of a sum grows with the square root of its length). Each term is
-// an exact integer function of its fragment, so the sums stay order
-// independent.
-struct Terms {
-  uint32_t a, r, g, b;
-  uint64_t lg;
-};
-__device__ __forceinline__ uint32_t q24_term(float a24, float m) { return (uint32_t)__builtin_rintf(a24 * m); }
+// Fixed-point terms of one fragment. Each is an exact integer function of
+// its fragment, so the sums stay order independent. Q24 terms round half up
+// (floor(x + 1/2), one instruction; unbiased but for exact halves, so the
+// error of a sum grows with the square root of its length); they are at
+// most 2^24 for colours in [0, 1].
+__device__ __forceinline__ uint32_t round_q(float x) {
+  int r;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return (uint32_t)r;
+}
 __device__ __forceinline__ uint64_t lg_term(float a) {
   const float l = -__log2f(1.0f - a) * kQ27;  // <= 24 * 2^27 below a = 1
   return a >= 1.0f ? kOpaque : (uint64_t)(uint32_t)__builtin_rintf(l);
 }
+struct Terms {
+  uint32_t a, r, g, b;
+  uint64_t lg;
+};
 __device__ __forceinline__ Terms frag_terms(float4 c) {
   Terms t;
   const float a = __builtin_amdgcn_fmed3f(c.w, 0.0f, 1.0f);
   const float a24 = a * kQ24;  // exact scaling: a24 * c = (a * c) * 2^24
-  t.a = q24_term(a24, 1.0f);
-  t.r = q24_term(a24, c.x);
-  t.g = q24_term(a24, c.y);
-  t.b = q24_term(a24, c.z);
+  t.a = round_q(a24);
+  t.r = round_q(a24 * c.x);
+  t.g = round_q(a24 * c.y);
+  t.b = round_q(a24 * c.z);
   t.lg = lg_term(a);
   return t;
 }
 
-// pixel totals (64-bit) and the lane-local 32-bit partials
+// channel sums: V is uint32_t for lists of at most kNarrow fragments, else
+// uint64_t (then fed from 32-bit lane partials folded every kFold steps)
+template <typename V>
 struct Sums {
-  uint64_t a = 0, r = 0, g = 0, b = 0, lg = 0;
+  V a = 0, r = 0, g = 0, b = 0;
+  uint64_t lg = 0;
 };
 struct Part {
   uint32_t a = 0, r = 0, g = 0, b = 0;
 };
-__device__ __forceinline__ void fold(Sums& s, Part& p) {
+template <typename V>
+__device__ __forceinline__ void fold(Sums<V>& s, Part& p) {
   s.a += p.a; s.r += p.r; s.g += p.g; s.b += p.b;
   p = Part();
 }
@@ -116,17 +130,20 @@ struct Top2 {
   uint32_t k1 = kNone, k2 = kNone;  // global fragment indices
 };
 
-// Insert key (z, k) into the top 2. Straight-line compares and selects; only
-// an exact depth tie with a held key loads primitive ids (the tie-break). A
-// NaN depth never enters (every compare is false), and neither does a key at
-// the empty slots' +inf depth.
+// Insert key (z, k) into the top 2. The common case is two compares and four
+// selects; an exact depth tie with a held key (rare) loads primitive ids for
+// the tie-break. A NaN depth never enters (every compare is false), and
+// neither does a key at the empty slots' +inf depth.
 __device__ __forceinline__ void top2_push(Top2& t, float z, uint32_t k, const uint32_t* prim) {
   bool lt1 = z < t.z1, lt2 = z < t.z2;
-  const bool eq1 = z == t.z1 && t.k1 != kNone, eq2 = z == t.z2 && t.k2 != kNone;
-  if (eq1 || eq2) {
-    const uint32_t pk = prim[k];
-    if (eq1) lt1 = pk < prim[t.k1];
-    if (eq2) lt2 = pk < prim[t.k2];
+  if (z == t.z1 || z == t.z2) {
+    const bool eq1 = z == t.z1 && t.k1 != kNone && k != kNone;
+    const bool eq2 = z == t.z2 && t.k2 != kNone && k != kNone;
+    if (eq1 || eq2) {
+      const uint32_t pk = prim[k];
+      if (eq1) lt1 = pk < prim[t.k1];
+      if (eq2) lt2 = pk < prim[t.k2];
+    }
   }
   t.z2 = lt1 ? t.z1 : (lt2 ? z : t.z2);
   t.k2 = lt1 ? t.k1 : (lt2 ? k : t.k2);
@@ -134,76 +151,73 @@ __device__ __forceinline__ void top2_push(Top2& t, float z, uint32_t k, const ui
   t.k1 = lt1 ? k : t.k1;
 }
 
-template <bool HALF, bool RGBA>
-__device__ __forceinline__ void step(const FeatArgs& a, uint32_t k, Top2& t, Part& p, Sums& s, uint32_t& zmax,
-                                     uint32_t& amax) {
-  const float z = a.depth[k];
-  zmax = max(zmax, __float_as_uint(z));  // -0, negatives and NaN exceed 1.0's bits
-  top2_push(t, z, k, a.prim);
-  if constexpr (RGBA) {
-    const float4 c = load_rgba<HALF>(a.rgba, k);
-    amax = max(amax, __float_as_uint(c.w));
-    const Terms q = frag_terms(c);
-    p.a += q.a; p.r += q.r; p.g += q.g; p.b += q.b;
-    s.lg += q.lg;
-  }
+__device__ __forceinline__ void add_terms(Part& p, uint64_t& lg, const Terms& q) {
+  p.a += q.a; p.r += q.r; p.g += q.g; p.b += q.b;
+  lg += q.lg;
 }
 
-// one lane's share of a list: fragments b+q, b+q+4, ... two per step so both
-// loads are in flight together; 32-bit partials folded every kFold steps
-template <bool HALF, bool RGBA>
-__device__ __forceinline__ void stream(const FeatArgs& a, uint32_t b, uint32_t e, int q, Top2& t, Sums& s,
-                                       uint32_t& zmax, uint32_t& amax) {
+// One lane's share of a list: fragments b+q, b+q+4, ..., two per step so both
+// loads are in flight together. RGBA is loaded only when `rgba` (pass-3
+// pixels); otherwise the colour is zero and so are its terms.
+template <bool HALF, bool WIDE, typename V>
+__device__ __forceinline__ void stream(const FeatArgs& a, uint32_t b, uint32_t e, int q, bool rgba, Top2& t,
+                                       Sums<V>& s, uint32_t& zmax, uint32_t& amax) {
   Part p;
   uint32_t k = b + q;
-  while (k < e) {
-    const uint32_t kend = min(e, k + kFold * kG);
+  do {
+    const uint32_t kend = WIDE ? min(e, k + kFold * kG) : e;
     for (; k + kG < kend; k += 2 * kG) {
       const float z0 = a.depth[k], z1 = a.depth[k + kG];
       float4 c0 = make_float4(0.f, 0.f, 0.f, 0.f), c1 = c0;
-      if constexpr (RGBA) {
+      if (rgba) {
         c0 = load_rgba<HALF>(a.rgba, k);
         c1 = load_rgba<HALF>(a.rgba, k + kG);
       }
-      zmax = max(zmax, max(__float_as_uint(z0), __float_as_uint(z1)));
+      zmax = max(zmax, max(__float_as_uint(z0), __float_as_uint(z1)));  // -0, negatives, NaN exceed 1.0's bits
       top2_push(t, z0, k, a.prim);
       top2_push(t, z1, k + kG, a.prim);
-      if constexpr (RGBA) {
-        amax = max(amax, max(__float_as_uint(c0.w), __float_as_uint(c1.w)));
-        const Terms q0 = frag_terms(c0), q1 = frag_terms(c1);
-        p.a += q0.a + q1.a; p.r += q0.r + q1.r; p.g += q0.g + q1.g; p.b += q0.b + q1.b;
-        s.lg += q0.lg + q1.lg;
-      }
+      amax = max(amax, max(__float_as_uint(c0.w), __float_as_uint(c1.w)));
+      add_terms(p, s.lg, frag_terms(c0));
+      add_terms(p, s.lg, frag_terms(c1));
     }
     if (k < kend) {
-      step<HALF, RGBA>(a, k, t, p, s, zmax, amax);
+      const float z = a.depth[k];
+      float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (rgba) c = load_rgba<HALF>(a.rgba, k);
+      zmax = max(zmax, __float_as_uint(z));
+      top2_push(t, z, k, a.prim);
+      amax = max(amax, __float_as_uint(c.w));
+      add_terms(p, s.lg, frag_terms(c));
       k += kG;
     }
     fold(s, p);
-  }
+  } while (WIDE && k < e);
 }
 
-template <bool HALF>
-__global__ __launch_bounds__(256) void features_kernel(FeatArgs a) {
-  const int P = a.W * a.H;
-  const int q = threadIdx.x & (kG - 1);
-  const int p = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) / kG);
-  if (p >= P) return;  // whole quads leave together
-  const Grids g = load_grids(a.sched, a.W, a.H);
-  int x, y;
-  pixel_xy(p, a.W, x, y);
-  const int i2 = grid_index_of(x, a.W, g.w2), j2 = grid_index_of(y, a.H, g.h2);
-  const int i3 = grid_index_of(x, a.W, g.w3), j3 = grid_index_of(y, a.H, g.h3);
+// channel sum -> FP32
+__device__ __forceinline__ float to_f32(uint32_t v) { return (float)v; }
+__device__ __forceinline__ float to_f32(uint64_t v) {
+  return __builtin_fmaf((float)(uint32_t)(v >> 32), 4294967296.0f, (float)(uint32_t)v);
+}
+// 2^(-Lg / 2^27): an opaque fragment (2^36) or any Lg of 2^36 and above gives
+// exactly 0; below that Lg / 2^27 = 32 hi + lo / 2^27
+__device__ __forceinline__ float tail_transmittance(uint64_t lg) {
+  const uint32_t hi = (uint32_t)(lg >> 32), lo = (uint32_t)lg;
+  const float e = __builtin_fmaf((float)hi, 32.0f, (float)lo * (1.0f / kQ27));
+  return hi >= 16u ? 0.0f : __builtin_amdgcn_exp2f(-e);
+}
+
+template <bool HALF, bool WIDE>
+__device__ __forceinline__ void pixel(const FeatArgs& a, const Grids& g, int p, int q, uint32_t b, uint32_t e,
+                                      int i2, int j2, int i3, int j3) {
+  using V = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
   const bool pass2 = i2 >= 0 && j2 >= 0;
   const bool pass3 = i3 >= 0 && j3 >= 0;
-
-  const uint32_t b = a.off[p], e = a.off[p + 1];
   const uint32_t n = e - b;
   Top2 t;
-  Sums s;
+  Sums<V> s;
   uint32_t zmax = 0, amax = 0;
-  if (pass3) stream<HALF, true>(a, b, e, q, t, s, zmax, amax);
-  else stream<HALF, false>(a, b, e, q, t, s, zmax, amax);
+  stream<HALF, WIDE>(a, b, e, q, pass3, t, s, zmax, amax);
 
   // merge the quad's top-2 keys: two butterfly rounds
   {
@@ -245,9 +259,9 @@ __global__ __launch_bounds__(256) void features_kernel(FeatArgs a) {
     // reduce-scatter of the channel sums (alpha, r, g, b): lane q ends with
     // the quad total of channel q; the log-transmittance sum is all-reduced
     const bool hi = q & 2, odd = q & 1;
-    const uint64_t y0 = (hi ? s.g : s.a) + qperm<kXor2>(hi ? s.a : s.g);
-    const uint64_t y1 = (hi ? s.b : s.r) + qperm<kXor2>(hi ? s.r : s.b);
-    uint64_t v = (odd ? y1 : y0) + qperm<kXor1>(odd ? y0 : y1);
+    const V y0 = (hi ? s.g : s.a) + qperm<kXor2>(hi ? s.a : s.g);
+    const V y1 = (hi ? s.b : s.r) + qperm<kXor2>(hi ? s.r : s.b);
+    V v = (odd ? y1 : y0) + qperm<kXor1>(odd ? y0 : y1);
     uint64_t lg = s.lg + qperm<kXor1>(s.lg);
     lg += qperm<kXor2>(lg);
     // exact removal of the two selected layers leaves the tail (a missing
@@ -255,15 +269,16 @@ __global__ __launch_bounds__(256) void features_kernel(FeatArgs a) {
     const float m1 = q == 0 ? 1.0f : (q == 1 ? c1.x : (q == 2 ? c1.y : c1.z));
     const float m2 = q == 0 ? 1.0f : (q == 1 ? c2.x : (q == 2 ? c2.y : c2.z));
     const float a1 = __builtin_amdgcn_fmed3f(c1.w, 0.0f, 1.0f), a2 = __builtin_amdgcn_fmed3f(c2.w, 0.0f, 1.0f);
-    v -= (uint64_t)q24_term(a1 * kQ24, m1) + (uint64_t)q24_term(a2 * kQ24, m2);
+    v -= (V)round_q(a1 * kQ24 * m1);
+    v -= (V)round_q(a2 * kQ24 * m2);
     lg -= lg_term(a1) + lg_term(a2);
     // x = (N, t_tail, Ct = S / A) and A, one channel per lane
     const bool tail = n > 2;
-    const float tv = u64_to_f32(v);
+    const float tv = to_f32(v);
     const float A = qperm<kBc0>(tv);
     const float inv = (tail && A > 0.0f) ? __builtin_amdgcn_rcpf(A) : 0.0f;
     const float o = q == 0 ? (tail ? A * (1.0f / kQ24) : 0.0f) : tv * inv;
-    const float tt = tail ? __builtin_amdgcn_exp2f(-u64_to_f32(lg) * (1.0f / kQ27)) : 1.0f;
+    const float tt = tail ? tail_transmittance(lg) : 1.0f;
     // record [N, t_tail, Cr, Cg | Cb, A, 0, 0] as one float2 per lane
     const float nx = qperm<kRot1>(o), oa = qperm<kBc0>(o);
     float2 rec;
@@ -275,6 +290,25 @@ __global__ __launch_bounds__(256) void features_kernel(FeatArgs a) {
   errf |= zmax > kOne ? STARNT_DERR_DEPTH : 0u;
   errf |= amax > kOne ? STARNT_DERR_ALPHA : 0u;
   if (errf) atomicOr(a.err, errf);
+}
+
+template <bool HALF>
+__global__ __launch_bounds__(256) void features_kernel(FeatArgs a) {
+  const int P = a.W * a.H;
+  const int q = threadIdx.x & (kG - 1);
+  const int p = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) / kG);
+  if (p >= P) return;  // whole quads leave together
+  const Grids g = load_grids(a.sched, a.W, a.H);
+  int x, y;
+  pixel_xy(p, a.W, x, y);
+  const int i2 = grid_index_of(x, a.W, g.w2), j2 = grid_index_of(y, a.H, g.h2);
+  const int i3 = grid_index_of(x, a.W, g.w3), j3 = grid_index_of(y, a.H, g.h3);
+  const uint32_t b = a.off[p], e = a.off[p + 1];
+  // the 64-bit variant only where the wave holds a list longer than kNarrow
+  if (__builtin_amdgcn_ballot_w64(e - b > kNarrow) != 0)
+    pixel<HALF, true>(a, g, p, q, b, e, i2, j2, i3, j3);
+  else
+    pixel<HALF, false>(a, g, p, q, b, e, i2, j2, i3, j3);
 }
 
 }  // namespace

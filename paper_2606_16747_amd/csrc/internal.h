@@ -45,17 +45,16 @@ __device__ __forceinline__ void pixel_xy(int p, int W, int& x, int& y) {
 
 // Grid index i of the W_s-sample grid that samples full-resolution coordinate
 // x (sample i sits at floor((2i+1) W / (2 W_s))), or -1 when x is not sampled.
-// Frame sides are at most 16384, so every product below is below 2^30, every
-// quotient at most 16384, and the 32-bit arithmetic is exact.
+// The candidate is the smallest i with (2i+1) W >= 2 W_s x; it samples x iff
+// (2i+1) W < 2 W_s (x+1) as well. Frame sides are at most 16384, so every
+// product is below 2^30, every quotient at most 16384, and the 32-bit
+// arithmetic is exact.
 __device__ __forceinline__ int grid_index_of(int x, int W, int Ws) {
   if (Ws >= W) return x;
-  // smallest i with (2i+1) W >= 2 Ws x
   const int num = 2 * Ws * x - W;
   const int den = 2 * W;
   const int i = num <= 0 ? 0 : (int)udiv_small((unsigned)num + (unsigned)den - 1u, (unsigned)den);
-  if (i >= Ws) return -1;
-  const int pos = (int)udiv_small((unsigned)((2 * i + 1) * W), (unsigned)(2 * Ws));
-  return pos == x ? i : -1;
+  return (i < Ws && (2 * i + 1) * W < 2 * Ws * (x + 1)) ? i : -1;
 }
 
 // Bilinear taps along one axis for full-resolution coordinate x on a W_s grid:

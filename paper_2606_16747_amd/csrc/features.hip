@@ -164,11 +164,12 @@ __device__ __forceinline__ void stream(const FeatArgs& a, uint32_t b, uint32_t e
                                        Sums<V>& s, uint32_t& zmax, uint32_t& amax) {
   Part p;
   uint32_t k = b + q;
+  // colours stay zero in lanes that never load them (rgba is per pixel)
+  float4 c0 = make_float4(0.f, 0.f, 0.f, 0.f), c1 = c0;
   do {
     const uint32_t kend = WIDE ? min(e, k + kFold * kG) : e;
     for (; k + kG < kend; k += 2 * kG) {
       const float z0 = a.depth[k], z1 = a.depth[k + kG];
-      float4 c0 = make_float4(0.f, 0.f, 0.f, 0.f), c1 = c0;
       if (rgba) {
         c0 = load_rgba<HALF>(a.rgba, k);
         c1 = load_rgba<HALF>(a.rgba, k + kG);
@@ -182,12 +183,11 @@ __device__ __forceinline__ void stream(const FeatArgs& a, uint32_t b, uint32_t e
     }
     if (k < kend) {
       const float z = a.depth[k];
-      float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (rgba) c = load_rgba<HALF>(a.rgba, k);
+      if (rgba) c0 = load_rgba<HALF>(a.rgba, k);
       zmax = max(zmax, __float_as_uint(z));
       top2_push(t, z, k, a.prim);
-      amax = max(amax, __float_as_uint(c.w));
-      add_terms(p, s.lg, frag_terms(c));
+      amax = max(amax, __float_as_uint(c0.w));
+      add_terms(p, s.lg, frag_terms(c0));
       k += kG;
     }
     fold(s, p);

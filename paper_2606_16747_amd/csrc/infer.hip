@@ -75,24 +75,25 @@ __device__ __forceinline__ void issue_loads(const InferArgs& a, const Grids& g, 
   int x, y;
   pixel_xy(p, a.W, x, y);
   const Taps tx = axis_taps(x, a.W, g.w3), ty = axis_taps(y, a.H, g.h3);
-  const size_t i3[4] = {(size_t)ty.i0 * g.w3 + tx.i0, (size_t)ty.i0 * g.w3 + tx.i1,
-                        (size_t)ty.i1 * g.w3 + tx.i0, (size_t)ty.i1 * g.w3 + tx.i1};
+  // grid sides are at most 16384, so sample indices fit 32 bits
+  const uint32_t i3[4] = {(uint32_t)(ty.i0 * g.w3 + tx.i0), (uint32_t)(ty.i0 * g.w3 + tx.i1),
+                          (uint32_t)(ty.i1 * g.w3 + tx.i0), (uint32_t)(ty.i1 * g.w3 + tx.i1)};
   // a full-resolution grid needs only the pixel's own sample (weights 0);
   // the test is uniform across the wave
   const int taps3 = (g.w3 == a.W && g.h3 == a.H) ? 1 : 4;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const size_t i = i3[k < taps3 ? k : 0];
-    r.t[k] = a.tail[2 * i];
-    r.t4[k] = a.tail[2 * i + 1].x;
+    const uint32_t i = i3[k < taps3 ? k : 0];
+    r.t[k] = a.tail[2u * i];
+    r.t4[k] = a.tail[2u * i + 1u].x;
   }
   r.wx3 = tx.w1;
   r.wy3 = ty.w1;
   if constexpr (COMP) {
     r.l1 = a.layer1[p];
     const Taps ux = axis_taps(x, a.W, g.w2), uy = axis_taps(y, a.H, g.h2);
-    const size_t i2[4] = {(size_t)uy.i0 * g.w2 + ux.i0, (size_t)uy.i0 * g.w2 + ux.i1,
-                          (size_t)uy.i1 * g.w2 + ux.i0, (size_t)uy.i1 * g.w2 + ux.i1};
+    const uint32_t i2[4] = {(uint32_t)(uy.i0 * g.w2 + ux.i0), (uint32_t)(uy.i0 * g.w2 + ux.i1),
+                            (uint32_t)(uy.i1 * g.w2 + ux.i0), (uint32_t)(uy.i1 * g.w2 + ux.i1)};
     const int taps2 = (g.w2 == a.W && g.h2 == a.H) ? 1 : 4;
 #pragma unroll
     for (int k = 0; k < 4; ++k) r.l2[k] = a.layer2[i2[k < taps2 ? k : 0]];
@@ -393,13 +394,20 @@ __global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
     o2 = fmaxf(fmaf(acc[2], dq2, b32), 0.0f);
   };
 
+  // software pipeline: the loads of the wave's next step are in flight while
+  // the network runs on the current one
+  PixRaw r;
+  r.n = 0;
+  int pn = wave * 64 + lane;
+  if (wave < nsteps && pn < P) issue_loads<COMP>(a, g, pn, r);
   for (int st = wave; st < nsteps; st += nwaves) {
-    const int p = st * 64 + lane;
+    const int p = pn;
     const bool live = p < P;
-    PixRaw r;
-    r.n = 0;
-    if (live) issue_loads<COMP>(a, g, p, r);
     const PixIn in = blend<COMP>(r);
+    const int sn = st + nwaves;
+    pn = sn * 64 + lane;
+    r.n = 0;
+    if (sn < nsteps && pn < P) issue_loads<COMP>(a, g, pn, r);
     float xs[5], xo[5];
 #pragma unroll
     for (int e = 0; e < 5; ++e) {

@@ -59,7 +59,8 @@ __device__ __forceinline__ int grid_index_of(int x, int W, int Ws) {
 
 // Bilinear taps along one axis for full-resolution coordinate x on a W_s grid:
 // grid coordinate u = ((2x+1) W_s - W) / (2W), taps floor(u) and floor(u)+1
-// clamped to [0, W_s-1], weight of the upper tap = frac(u).
+// clamped to [0, W_s-1], weight of the upper tap = frac(u) (the exact integer
+// remainder times the hardware reciprocal of 2W, within 2 ulp).
 struct Taps {
   int i0, i1;
   float w1;
@@ -71,7 +72,7 @@ __device__ __forceinline__ Taps axis_taps(int x, int W, int Ws) {
   // floor division for num >= -den
   const int q = num >= 0 ? (int)udiv_small((unsigned)num, (unsigned)den) : -1;
   const int r = num - q * den;
-  t.w1 = (float)r / (float)den;
+  t.w1 = (float)r * __builtin_amdgcn_rcpf((float)den);  // 0 exactly when r = 0
   t.i0 = q < 0 ? 0 : (q > Ws - 1 ? Ws - 1 : q);
   t.i1 = q + 1 < 0 ? 0 : (q + 1 > Ws - 1 ? Ws - 1 : q + 1);
   return t;

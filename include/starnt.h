@@ -234,7 +234,8 @@ int starnt_baseline(const starnt_frags* frags, int32_t method, const float* bg, 
  * sched->hist (occupied leaves per level), sched->wbar = sum l N_l / sum N_l,
  * sched->s2, s3 by eq (4) and the next frame's grids. The update reads and
  * writes `sched` on the device, so frames chain without host round trips.
- * Workspace: starnt_workspace_size(STARNT_WS_QUADTREE, W, H, base). */
+ * Workspace: starnt_workspace_size(STARNT_WS_QUADTREE, W, H, base) bytes,
+ * 256-byte aligned (EINVAL otherwise). */
 int starnt_quadtree(const float* rgb, const uint32_t* count, int32_t width, int32_t height,
                     const starnt_qt_params* params, const uint32_t* prev_mask, uint32_t* mask, uint8_t* level,
                     starnt_sched* sched, void* workspace, size_t workspace_bytes, void* stream);

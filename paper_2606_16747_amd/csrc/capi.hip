@@ -160,6 +160,8 @@ int starnt_quadtree(const float* rgb, const uint32_t* count, int32_t width, int3
   if (prev_mask && prev_mask == mask) return fail(STARNT_EINVAL, "starnt_quadtree: prev_mask aliases mask");
   const size_t need = quadtree_ws_bytes(width, height, params->base);
   if (!workspace || workspace_bytes < need) return fail(STARNT_ENOMEM, "starnt_quadtree: workspace too small");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256)
+    return fail(STARNT_EINVAL, "starnt_quadtree: workspace must be 256-byte aligned");
   return launch_quadtree(rgb, count, width, height, *params, prev_mask, mask, level, sched, workspace,
                          as_stream(stream));
 }

@@ -14,8 +14,8 @@
 //    masks re-derived (node at level l split iff a cell under it has r > l,
 //    via wave ballots), leaf levels re-read.
 //  The last pass writes masks, levels and per-tile occupied-leaf counts; a
-//  one-block kernel sums them in a fixed order and computes wbar, s2, s3 and
-//  the next grids on the device.
+//  one-block kernel sums them and computes wbar, s2, s3 and the next grids on
+//  the device.
 #include "internal.h"
 
 namespace starnt {
@@ -32,9 +32,51 @@ struct QtArgs {
   uint32_t* mask;
   uint8_t* level;
   uint32_t* tile_hist;  // [T][4]
+  uint64_t* tile_occ;   // [T] occupied cells, from the top-down pass
   int mode;             // 0 top-down, 1 relaxation
   int final_pass;
 };
+
+// Sum of the per-tile leaf counts and the schedule they imply (eq (4)), by
+// the 64 threads of one block. Integer sums: exact in any order.
+__device__ void finish_schedule(const uint32_t* tile_hist, int T, int W, int H, starnt_sched* s, int t) {
+  uint32_t h[4] = {0, 0, 0, 0};
+  const uint4* th = reinterpret_cast<const uint4*>(tile_hist);  // 256-byte aligned
+  for (int i0 = 0; i0 < T; i0 += 64 * 8) {
+    uint4 v[8];  // eight loads in flight per thread
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + 64 * u + t;
+      v[u] = i < T ? th[i] : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      h[0] += v[u].x; h[1] += v[u].y; h[2] += v[u].z; h[3] += v[u].w;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1)
+    for (int l = 0; l < 4; ++l) h[l] += __shfl_down(h[l], off);
+  if (t == 0) {
+    const double den = (double)h[0] + h[1] + h[2] + h[3];
+    const double wb = den > 0 ? ((double)h[1] + 2.0 * h[2] + 3.0 * h[3]) / den : 0.0;
+    const double s2 = fmin(1.0, fmax(0.25, exp2(wb - 2.2)));
+    const double s3 = fmin(1.0, fmax(0.25, exp2(wb - 3.0)));
+    auto dim = [](int n, double sc) {
+      double v = ceil(sc * (double)n);
+      v = fmax(1.0, fmin((double)n, v));
+      return (int)v;
+    };
+    for (int l = 0; l < 4; ++l) s->hist[l] = h[l];
+    s->wbar = (float)wb;
+    s->s2 = (float)s2;
+    s->s3 = (float)s3;
+    s->w2 = dim(W, s2);
+    s->h2 = dim(H, s2);
+    s->w3 = dim(W, s3);
+    s->h3 = dim(H, s3);
+    s->frames = s->frames + 1;
+  }
+}
 
 __device__ __forceinline__ int leaf_of(uint32_t m, int cx, int cy) {
   if (!(m & 1u)) return 0;
@@ -71,10 +113,62 @@ __device__ __forceinline__ uint32_t derive_mask(int r, bool live) {
   return m;
 }
 
+// Occupied cells of a tile as a 64-bit mask (bit 8 cy + cx): a cell is
+// occupied when some pixel inside it (and the frame) has at least one
+// fragment. Called by all 64 threads of the tile's block.
+__device__ __forceinline__ uint64_t tile_occupancy(const QtArgs& a, int tx, int ty, int t, int gx, int gy,
+                                                   bool live) {
+  uint64_t om;
+  if (a.B == 64) {
+    // lane = pixel column of the tile; each row is one coalesced 256-byte
+    // load, OR-ed per 8-row band; a cell's 8 columns are 8 bits of a ballot
+    // (addresses are clamped into the frame and values outside it dropped,
+    // so the 64 loads carry no branches and are all in flight together)
+    const int px = tx * 64 + t;
+    const bool col_in = px < a.W;
+    const uint32_t* col = a.count + min(px, a.W - 1);
+    const int rows = min(64, a.H - ty * 64);  // rows of the tile inside the frame
+    uint32_t v[64];
+#pragma unroll
+    for (int r = 0; r < 64; ++r) v[r] = col[(size_t)(ty * 64 + min(r, rows - 1)) * a.W];
+    uint32_t band = 0;  // bit cy: this column has a fragment in cell row cy
+#pragma unroll
+    for (int cy8 = 0; cy8 < 8; ++cy8) {
+      uint32_t any = 0;
+#pragma unroll
+      for (int dy = 0; dy < 8; ++dy) any |= v[8 * cy8 + dy];  // rows past the frame repeat the last
+      band |= (any != 0 ? 1u : 0u) << cy8;
+    }
+    // cell rows past the frame are empty; so are columns past it
+    band &= rows >= 64 ? 0xFFu : ((1u << ((rows + 7) >> 3)) - 1u);
+    band = col_in ? band : 0u;
+    om = 0;
+#pragma unroll
+    for (int cy8 = 0; cy8 < 8; ++cy8) {
+      const uint64_t cols = __ballot((band >> cy8) & 1u);
+#pragma unroll
+      for (int cx8 = 0; cx8 < 8; ++cx8)
+        if ((cols >> (8 * cx8)) & 0xFFull) om |= 1ull << (8 * cy8 + cx8);
+    }
+  } else {
+    bool occ = false;
+    if (live) {
+      const int cs = a.B >> 3;
+      const int x0 = gx * cs, y0 = gy * cs;
+      const int x1 = min(x0 + cs, a.W), y1 = min(y0 + cs, a.H);
+      uint32_t any = 0;
+      for (int y = y0; y < y1; ++y)
+#pragma unroll 8
+        for (int x = x0; x < x1; ++x) any |= a.count[(size_t)y * a.W + x];
+      occ = any != 0;
+    }
+    om = __ballot(occ);
+  }
+  return om;
+}
+
 __global__ __launch_bounds__(64) void qt_pass_kernel(QtArgs a) {
   __shared__ float s_rgb[64][3];
-  __shared__ float s_D[21];
-  __shared__ uint32_t s_m;
   const int tile = blockIdx.x;
   const int tx = tile % a.Tw, ty = tile / a.Tw;
   const int t = threadIdx.x;
@@ -86,7 +180,8 @@ __global__ __launch_bounds__(64) void qt_pass_kernel(QtArgs a) {
   int L;
   if (a.mode == 0) {
     // corner samples: x index 0..3 = left corners k B/4, 4..7 = right corners
-    // (k+1) B/4 - 1, clamped to the frame
+    // (k+1) B/4 - 1, clamped to the frame; lane t loads sample t
+    float cr, cg, cb;
     {
       const int ix = t & 7, iy = t >> 3;
       const int q = a.B >> 2;
@@ -94,16 +189,31 @@ __global__ __launch_bounds__(64) void qt_pass_kernel(QtArgs a) {
       const int oy = iy < 4 ? iy * q : (iy - 3) * q - 1;
       const int sx = min(tx * a.B + ox, a.W - 1), sy = min(ty * a.B + oy, a.H - 1);
       const size_t pix = (size_t)sy * a.W + sx;
-      s_rgb[t][0] = a.rgb[3 * pix + 0];
-      s_rgb[t][1] = a.rgb[3 * pix + 1];
-      s_rgb[t][2] = a.rgb[3 * pix + 2];
+      cr = a.rgb[3 * pix + 0];
+      cg = a.rgb[3 * pix + 1];
+      cb = a.rgb[3 * pix + 2];
     }
+    // cell occupancy for the histogram of the last pass (its loads are in
+    // flight together with the corner sample's)
+    const uint64_t om = tile_occupancy(a, tx, ty, t, gx, gy, live);
+    if (t == 0) a.tile_occ[tile] = om;
+    s_rgb[t][0] = cr;
+    s_rgb[t][1] = cg;
+    s_rgb[t][2] = cb;
     __syncthreads();
+    // lane t < 21 evaluates node bit t (0 root; 1..4 level 1; 5..20 level 2,
+    // quadrant-major): its D and its own split/merge decision with
+    // hysteresis; the decisions are gathered with a ballot and gated top-down
+    // (a node counts only under a split parent)
+    bool own_split = false;
     if (t < 21) {
       int lvl, nx, ny;
       if (t == 0) { lvl = 0; nx = 0; ny = 0; }
       else if (t < 5) { lvl = 1; nx = (t - 1) & 1; ny = (t - 1) >> 1; }
-      else { lvl = 2; nx = (t - 5) & 3; ny = (t - 5) >> 2; }
+      else {
+        const int q = (t - 5) >> 2, r = (t - 5) & 3;
+        lvl = 2; nx = 2 * (q & 1) + (r & 1); ny = 2 * (q >> 1) + (r >> 1);
+      }
       const int span = 4 >> lvl;               // node side in units of B/4
       const int xl = nx * span, yl = ny * span;  // left / top corner index
       const int xr = 3 + xl + span, yr = 3 + yl + span;
@@ -122,42 +232,33 @@ __global__ __launch_bounds__(64) void qt_pass_kernel(QtArgs a) {
           }
         D = sum / 6.0f;
       }
-      s_D[bit_of(lvl, nx, ny)] = D;
+      own_split = (a.prev_mask && (pm & (1u << t))) ? !(D < a.tau_merge) : (D > a.tau_split);
     }
-    __syncthreads();
-    if (t == 0) {
-      uint32_t m = 0;
-      for (int lvl = 0; lvl <= 2; ++lvl) {
-        const int n = 1 << lvl;
-        for (int ny = 0; ny < n; ++ny)
-          for (int nx = 0; nx < n; ++nx) {
-            if (lvl > 0 && !(m & (1u << bit_of(lvl - 1, nx >> 1, ny >> 1)))) continue;
-            const int bit = bit_of(lvl, nx, ny);
-            const float D = s_D[bit];
-            const bool split = (a.prev_mask && (pm & (1u << bit))) ? !(D < a.tau_merge) : (D > a.tau_split);
-            if (split) m |= 1u << bit;
-          }
-      }
-      s_m = m;
-    }
-    __syncthreads();
-    L = leaf_of(s_m, cx, cy);
+    const uint32_t own = (uint32_t)__ballot(own_split);
+    const uint32_t m0 = own & 1u;
+    const uint32_t m1 = m0 ? (own & 0x1Eu) : 0u;
+    uint32_t m2 = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if ((m1 >> (1 + q)) & 1u) m2 |= own & (0xFu << (5 + 4 * q));
+    const uint32_t mtd = m0 | m1 | m2;
+    L = leaf_of(mtd, cx, cy);
     if (a.prev_mask) {
       const int pl = leaf_of(pm, cx, cy);
       L = min(max(L, pl - 1), pl + 1);
     }
   } else {
-    L = 0;
-    if (live) {
-      const size_t c = (size_t)gy * a.Cw + gx;
-      const int own = a.Lin[c];
-      int r = own;
-      if (gx > 0) r = max(r, (int)a.Lin[c - 1] - 1);
-      if (gx < a.Cw - 1) r = max(r, (int)a.Lin[c + 1] - 1);
-      if (gy > 0) r = max(r, (int)a.Lin[c - a.Cw] - 1);
-      if (gy < a.Ch - 1) r = max(r, (int)a.Lin[c + a.Cw] - 1);
-      L = r;
-    }
+    // own level and the 4 neighbours' (clamped to the grid: a clamped
+    // neighbour is the cell itself, which cannot raise it), loads issued
+    // together
+    const int cxl = min(gx, a.Cw - 1), cyl = min(gy, a.Ch - 1);
+    const size_t c = (size_t)cyl * a.Cw + cxl;
+    const int own = a.Lin[c];
+    const int l = a.Lin[(size_t)cyl * a.Cw + max(cxl - 1, 0)];
+    const int rr = a.Lin[(size_t)cyl * a.Cw + min(cxl + 1, a.Cw - 1)];
+    const int u = a.Lin[(size_t)max(cyl - 1, 0) * a.Cw + cxl];
+    const int d = a.Lin[(size_t)min(cyl + 1, a.Ch - 1) * a.Cw + cxl];
+    L = live ? max(max(own, max(l, rr) - 1), max(u, d) - 1) : 0;
   }
   const uint32_t m = derive_mask(L, live);
   const int Lf = leaf_of(m, cx, cy);
@@ -168,18 +269,7 @@ __global__ __launch_bounds__(64) void qt_pass_kernel(QtArgs a) {
   }
   if (!a.final_pass) return;
   if (t == 0) a.mask[tile] = m;
-  // occupancy: a cell is occupied when some pixel inside it (and the frame)
-  // has at least one fragment
-  bool occ = false;
-  if (live) {
-    const int cs = a.B >> 3;
-    const int x0 = gx * cs, y0 = gy * cs;
-    const int x1 = min(x0 + cs, a.W), y1 = min(y0 + cs, a.H);
-    for (int y = y0; y < y1 && !occ; ++y)
-      for (int x = x0; x < x1; ++x)
-        if (a.count[(size_t)y * a.W + x]) { occ = true; break; }
-  }
-  const uint64_t om = __ballot(occ);
+  const uint64_t om = a.tile_occ[tile];
   if (t == 0) {
     uint32_t h[4] = {0, 0, 0, 0};
     if (!(m & 1u)) {
@@ -200,40 +290,10 @@ __global__ __launch_bounds__(64) void qt_pass_kernel(QtArgs a) {
   }
 }
 
-struct FinishArgs {
-  int W, H, T;
-  const uint32_t* tile_hist;
-  starnt_sched* sched;
-};
-
-__global__ __launch_bounds__(64) void qt_finish_kernel(FinishArgs a) {
-  const int t = threadIdx.x;
-  uint32_t h[4] = {0, 0, 0, 0};
-  for (int i = t; i < a.T; i += 64)
-    for (int l = 0; l < 4; ++l) h[l] += a.tile_hist[4 * (size_t)i + l];
-  for (int off = 32; off > 0; off >>= 1)
-    for (int l = 0; l < 4; ++l) h[l] += __shfl_down(h[l], off);
-  if (t == 0) {
-    starnt_sched* s = a.sched;
-    const double den = (double)h[0] + h[1] + h[2] + h[3];
-    const double wb = den > 0 ? ((double)h[1] + 2.0 * h[2] + 3.0 * h[3]) / den : 0.0;
-    const double s2 = fmin(1.0, fmax(0.25, exp2(wb - 2.2)));
-    const double s3 = fmin(1.0, fmax(0.25, exp2(wb - 3.0)));
-    auto dim = [](int n, double sc) {
-      double v = ceil(sc * (double)n);
-      v = fmax(1.0, fmin((double)n, v));
-      return (int)v;
-    };
-    for (int l = 0; l < 4; ++l) s->hist[l] = h[l];
-    s->wbar = (float)wb;
-    s->s2 = (float)s2;
-    s->s3 = (float)s3;
-    s->w2 = dim(a.W, s2);
-    s->h2 = dim(a.H, s2);
-    s->w3 = dim(a.W, s3);
-    s->h3 = dim(a.H, s3);
-    s->frames = s->frames + 1;
-  }
+// one block: the schedule of the next frame from all tiles' counts
+__global__ __launch_bounds__(64) void qt_finish_kernel(const uint32_t* tile_hist, int T, int W, int H,
+                                                       starnt_sched* sched) {
+  finish_schedule(tile_hist, T, W, H, sched, threadIdx.x);
 }
 
 struct InitArgs {
@@ -259,7 +319,7 @@ size_t quadtree_ws_bytes(int64_t W, int64_t H, int64_t B) {
   const int64_t cs = B / 8;
   const int64_t Cw = (W + cs - 1) / cs, Ch = (H + cs - 1) / cs;
   const int64_t T = ((W + B - 1) / B) * ((H + B - 1) / B);
-  return 2 * align256((size_t)(Cw * Ch)) + align256((size_t)T * 16);
+  return 2 * align256((size_t)(Cw * Ch)) + align256((size_t)T * 16) + align256((size_t)T * 8);
 }
 
 int launch_quadtree(const float* rgb, const uint32_t* count, int W, int H, const starnt_qt_params& qp,
@@ -283,6 +343,7 @@ int launch_quadtree(const float* rgb, const uint32_t* count, int W, int H, const
   uint8_t* L1 = L0 + align256((size_t)a.Cw * a.Ch);
   a.tile_hist = reinterpret_cast<uint32_t*>(L1 + align256((size_t)a.Cw * a.Ch));
   const int T = a.Tw * a.Th;
+  a.tile_occ = reinterpret_cast<uint64_t*>(reinterpret_cast<uint8_t*>(a.tile_hist) + align256((size_t)T * 16));
   uint8_t* bufs[2] = {L0, L1};
   for (int it = 0; it <= qp.k_relax; ++it) {
     a.mode = it == 0 ? 0 : 1;
@@ -292,11 +353,7 @@ int launch_quadtree(const float* rgb, const uint32_t* count, int W, int H, const
     hipLaunchKernelGGL(qt_pass_kernel, dim3(T), dim3(64), 0, s, a);
     STARNT_LAUNCH_CHECK("starnt_quadtree pass launch");
   }
-  FinishArgs f;
-  f.W = W; f.H = H; f.T = T;
-  f.tile_hist = a.tile_hist;
-  f.sched = sched;
-  hipLaunchKernelGGL(qt_finish_kernel, dim3(1), dim3(64), 0, s, f);
+  hipLaunchKernelGGL(qt_finish_kernel, dim3(1), dim3(64), 0, s, a.tile_hist, T, W, H, sched);
   STARNT_LAUNCH_CHECK("starnt_quadtree finish launch");
   return STARNT_OK;
 }

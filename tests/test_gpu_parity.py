@@ -203,10 +203,11 @@ def test_learned_equals_exact_when_f_is_the_exact_tail(starnt, gpu, sg, oracle_m
 
 @pytest.mark.parametrize("dims", [(16, 32, 32, 3), (16, 64, 64, 3), (16, 32, 16, 3)])
 def test_infer_bf16_against_same_operands(starnt, gpu, sg, oracle_mod, dims):
-    """BF16 matrix-core inference against the FP64 evaluation of the same
-    network with bf16-rounded weights and activations. Rounding of an
-    activation can flip between FP32 and FP64 accumulation, so the bar is:
-    99.5% of pixels within 2e-4, every pixel within 2e-2."""
+    """BF16 matrix-core inference (on the GPU's features) against the FP64
+    evaluation of the same network with bf16-rounded weights and activations
+    (on the oracle's features). Rounding of an input or an activation can
+    flip between the two, so the bar is: 99.5% of pixels within 2e-4, every
+    pixel within 2e-2."""
     fr = _frame(sg)
     df, fb = run_features(starnt, fr, max_per_pixel=24)
     Ws, bs = sg.init_mlp(dims, seed=123, out_bias=0.1)
@@ -216,9 +217,10 @@ def test_infer_bf16_against_same_operands(starnt, gpu, sg, oracle_mod, dims):
     starnt.starnt_infer(mlp, fb.tail, fb.count, None, fr.width, fr.height, out)
     sync()
     y = to_np(out)
-    x = np.zeros((P, 16))
-    x[:, :5] = to_np(fb.tail)[:, :5]
-    N = to_np(fb.count)
+    o = oracle_mod.frame_of(fr, want=("lay", "tail"))
+    x = oracle_mod.features(o["lay"], o["tail"])
+    N = o["lay"][:, 0]
+    np.testing.assert_array_equal(to_np(fb.count), N.astype(np.int32))
     om = oracle_mod.Mlp(Ws, bs)
     want = np.where(N[:, None] >= 3, om.forward_q(x, 1), 0.0)
     err = np.abs(y - want).max(axis=1)
@@ -230,10 +232,11 @@ def test_infer_bf16_against_same_operands(starnt, gpu, sg, oracle_mod, dims):
 
 
 def test_quadtree_matches_oracle_over_frames(starnt, gpu, sg, oracle_mod):
-    """Quadtree decisions on the GPU's FP32 composites of three frames of a
-    moving scene, chained through prev masks, against the oracle given the
-    same image, counts and prev mask. Tiles near a node whose FP64 distance is
-    within 1e-6 of a threshold are excluded (none expected)."""
+    """Quadtree decisions over three frames of a moving scene, chained through
+    prev masks: the GPU and the oracle each take the oracle's exact composite
+    (rounded to FP32) and counts, and each chains its own masks. Tiles near a
+    node whose FP64 distance is within 1e-6 of a threshold are excluded (none
+    expected)."""
     sc = sg.Scene("c2_1080p", width=480, height=270, num_tris=300)
     W, H = 480, 270
     qp = starnt.QtParams(64, 0.10, 0.05, 2)
@@ -243,18 +246,18 @@ def test_quadtree_matches_oracle_over_frames(starnt, gpu, sg, oracle_mod):
     masks = [torch.zeros(T, dtype=torch.int32, device="cuda") for _ in range(2)]
     level = torch.zeros(Cw * Ch, dtype=torch.uint8, device="cuda")
     sched = starnt.new_sched(W, H)
-    prev = None
+    prev, prev_o = None, None
     for t in range(3):
         fr = sc.frame(t)
-        df, fb = run_features(starnt, fr, max_per_pixel=64)
-        rgb, _ = run_exact(starnt, df)
-        rgb_t = torch.from_numpy(rgb).cuda()
+        o = oracle_mod.frame_of(fr, want=("rgb", "lay"))
+        rgb = o["rgb"].astype(np.float32)
+        N = o["lay"][:, 0].astype(np.uint32)
         cur = masks[t % 2]
-        starnt.starnt_quadtree(rgb_t, fb.count, W, H, qp, prev, cur, level, sched, ws)
+        starnt.starnt_quadtree(torch.from_numpy(rgb).cuda(), torch.from_numpy(N.view(np.int32)).cuda(), W, H, qp,
+                               prev, cur, level, sched, ws)
         sync()
-        pm = None if prev is None else to_np(prev).view(np.uint32)
-        m, lv, hist, D = oracle_mod.quadtree(rgb, to_np(fb.count).view(np.uint32), W, H, base=64,
-                                             tau_split=0.10, tau_merge=0.05, k_relax=2, prev_mask=pm)
+        m, lv, hist, D = oracle_mod.quadtree(rgb, N, W, H, base=64, tau_split=0.10, tau_merge=0.05, k_relax=2,
+                                             prev_mask=prev_o)
         border = (np.abs(D - 0.10) < 1e-6) | (np.abs(D - 0.05) < 1e-6)
         assert not border.any()
         np.testing.assert_array_equal(to_np(cur).view(np.uint32), m)
@@ -266,7 +269,7 @@ def test_quadtree_matches_oracle_over_frames(starnt, gpu, sg, oracle_mod):
         s2, s3 = oracle_mod.pass_scales(wb)
         assert (s["w2"], s["h2"], s["w3"], s["h3"]) == _grids_for(oracle_mod, W, H, s2, s3)
         assert s["frames"] == t + 1
-        prev = cur
+        prev, prev_o = cur, m
     assert sum(s["hist"][1:]) > 0  # something split
 
 
@@ -298,20 +301,21 @@ def test_quadtree_ragged_edges(starnt, gpu, oracle_mod, base):
 
 
 def test_reproject_matches_oracle(starnt, gpu, sg, oracle_mod):
-    """Reprojection indices bit-exact against FP64 given the same FP32 depth
-    and M - I, except where the FP64 source coordinate lies within 1e-4 px of
-    a rounding boundary (counted, must be rare)."""
+    """Reprojection indices bit-exact against FP64 given the same FP32 inputs
+    (the oracle's exact composite and first-fragment depth of frame 2, and
+    M - I to frame 3), except where the FP64 source coordinate lies within
+    1e-4 px of a rounding boundary (counted, must be rare)."""
     sc = sg.Scene("c2_1080p", width=640, height=360, num_tris=400)
     fr = sc.frame(2)
     W, H = 640, 360
-    df, fb = run_features(starnt, fr, max_per_pixel=64)
-    rgb, _ = run_exact(starnt, df)
+    o = oracle_mod.frame_of(fr, want=("rgb", "lay"))
+    rgb = o["rgb"].astype(np.float32)
+    d1 = o["lay"][:, 1].astype(np.float32)
     mmi = oracle_mod.m_minus_i(sc.camera(2), sc.camera(3)).astype(np.float32)
     out = torch.empty(W * H, 3, dtype=torch.float32, device="cuda")
     src = torch.empty(W * H, dtype=torch.int32, device="cuda")
-    starnt.starnt_reproject(torch.from_numpy(rgb).cuda(), fb.d1, W, H, mmi, out, src)
+    starnt.starnt_reproject(torch.from_numpy(rgb).cuda(), torch.from_numpy(d1).cuda(), W, H, mmi, out, src)
     sync()
-    d1 = to_np(fb.d1)
     want_rgb, want_src, margin = oracle_mod.reproject(rgb, d1, mmi.astype(np.float64), W, H)
     ok = margin >= 1e-4
     assert ok.mean() > 0.999
@@ -329,7 +333,7 @@ def _train_setup(sg, oracle_mod, dims, batch, seed=0):
     rng = np.random.default_rng(seed)
     idx = rng.choice(len(x), batch, replace=len(x) < batch)
     Ws, bs = sg.init_mlp(dims, seed=77, out_bias=0.1)
-    params = oracle_mod.Mlp(Ws, bs).params().astype(np.float32)
+    params = np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in zip(Ws, bs)]).astype(np.float32)
     return x[idx].astype(np.float32), y[idx].astype(np.float32), params
 
 
@@ -421,9 +425,10 @@ def test_infer_fp8_against_same_operands(starnt, gpu, sg, oracle_mod, dims):
     df, fb = run_features(starnt, fr, max_per_pixel=24)
     Ws, bs = sg.init_mlp(dims, seed=321, out_bias=0.1)
     P = fr.num_pixels
-    x = np.zeros((P, 16))
-    x[:, :5] = to_np(fb.tail)[:, :5]
-    N = to_np(fb.count)
+    o = oracle_mod.frame_of(fr, want=("lay", "tail"))
+    x = oracle_mod.features(o["lay"], o["tail"])
+    N = o["lay"][:, 0]
+    np.testing.assert_array_equal(to_np(fb.count), N.astype(np.int32))
     live = N >= 3
     sa, sw = _fp8_scales(oracle_mod, Ws, bs, x[live])
     mlp = starnt.DeviceMlp(Ws, bs, starnt.FP8, fp8_scales=[v for pair in zip(sa, sw) for v in pair])

@@ -74,7 +74,7 @@ def test_training_resume_from_checkpoint_is_bitwise(starnt, gpu, sg, oracle_mod)
     assert len(x) >= 8192
     x, y = x[:8192], y[:8192]
     Ws, bs = sg.init_mlp((16, 32, 32, 3), seed=5, out_bias=0.05)
-    flat = oracle_mod.Mlp(Ws, bs).params().astype(np.float32)
+    flat = np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in zip(Ws, bs)]).astype(np.float32)
     n = flat.size
     ws = starnt.workspace(starnt.starnt_workspace_size(starnt.WS_TRAIN, 4096, 32, 32))
     xd = torch.from_numpy(x).cuda()

@@ -41,3 +41,17 @@ def random_lists(rng, width, height, max_n, ties=False):
             l.append((float(z), int(pr), float(r), float(g), float(b), a))
         lists.append(l)
     return lists
+
+
+def sub_csr(offsets, depth, rgba, prim, pixels):
+    """The lists of the given pixels, in that order, as the CSR arrays of a
+    1 x len(pixels) frame (plain slicing; rgba keeps its dtype)."""
+    offsets = np.asarray(offsets, np.int64)
+    pixels = np.asarray(pixels, np.int64)
+    b, e = offsets[pixels], offsets[pixels + 1]
+    counts = e - b
+    sub_off = np.zeros(len(pixels) + 1, np.uint32)
+    sub_off[1:] = np.cumsum(counts)
+    idx = np.concatenate([np.arange(x, y) for x, y in zip(b, e)]) if len(pixels) else np.zeros(0, np.int64)
+    idx = idx.astype(np.int64)
+    return sub_off, depth[idx], rgba[idx], prim[idx], idx

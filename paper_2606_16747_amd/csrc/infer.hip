@@ -236,6 +236,32 @@ __device__ __forceinline__ void set8(typename Op<FP8>::vec& v, const float* w, f
   }
 }
 
+// ReLU then pack: FP8 clamps in FP32 before the convert; BF16 converts first
+// and zeroes negative values on the packed bits (a bf16 value is negative,
+// -0 included, exactly when its 16-bit pattern is a negative integer), two
+// values per instruction
+template <bool FP8>
+__device__ __forceinline__ void set8_relu(typename Op<FP8>::vec& v, float* w, float scale_inv) {
+  if constexpr (FP8) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) w[e] = fmaxf(w[e], 0.0f);
+    set8<FP8>(v, w, scale_inv);
+  } else {
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    typedef short s16x2 __attribute__((ext_vector_type(2)));
+    typedef int i32x4 __attribute__((ext_vector_type(4)));
+    i32x4 packed;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const bf16x2 b = __builtin_convertvector((f32x2){w[2 * e], w[2 * e + 1]}, bf16x2);
+      const s16x2 r = __builtin_elementwise_max(__builtin_bit_cast(s16x2, b), (s16x2)0);
+      packed[e] = __builtin_bit_cast(int, r);
+    }
+    v = __builtin_bit_cast(bf16x8, packed);
+  }
+}
+
 template <bool FP8>
 __device__ __forceinline__ f32x16 mfma(const typename Op<FP8>::vec& A, const typename Op<FP8>::vec& B, f32x16 c) {
   if constexpr (FP8) return __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(A, B, c, 0, 0, 0);
@@ -368,8 +394,8 @@ __global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
       for (int c = 0; c < 2; ++c) {
         float hv[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) hv[e] = fmaxf(fmaf(acc[8 * c + e], dq0, B1v[t][8 * c + e]), 0.0f);
-        set8<FP8>(Hb[2 * t + c], hv, ia1);
+        for (int e = 0; e < 8; ++e) hv[e] = fmaf(acc[8 * c + e], dq0, B1v[t][8 * c + e]);
+        set8_relu<FP8>(Hb[2 * t + c], hv, ia1);
       }
     }
     V Hb2[C3];
@@ -382,8 +408,8 @@ __global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
       for (int c = 0; c < 2; ++c) {
         float hv[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) hv[e] = fmaxf(fmaf(acc[8 * c + e], dq1, B2v[t][8 * c + e]), 0.0f);
-        set8<FP8>(Hb2[2 * t + c], hv, ia2);
+        for (int e = 0; e < 8; ++e) hv[e] = fmaf(acc[8 * c + e], dq1, B2v[t][8 * c + e]);
+        set8_relu<FP8>(Hb2[2 * t + c], hv, ia2);
       }
     }
     f32x16 acc = {};

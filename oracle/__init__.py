@@ -56,9 +56,16 @@ def _load():
                 build(force=True)
             lib = ctypes.CDLL(_LIB)
             lib.orc_frame.restype = ctypes.c_int
-            lib.orc_frame.argtypes = [ctypes.c_int32, ctypes.c_int32] + [_P] * 10 + [ctypes.c_int32]
+            lib.orc_frame.argtypes = [ctypes.c_int32, ctypes.c_int32] + [_P] * 11 + [ctypes.c_int32]
             lib.orc_mlp_forward.restype = ctypes.c_int
             lib.orc_mlp_forward.argtypes = [ctypes.POINTER(_Mlp), _P, ctypes.c_int64, _P]
+            lib.orc_mlp_forward_act.restype = ctypes.c_int
+            lib.orc_mlp_forward_act.argtypes = [ctypes.POINTER(_Mlp), _P, ctypes.c_int64, ctypes.c_int32, _P]
+            lib.orc_mlp_forward_q_act.restype = ctypes.c_int
+            lib.orc_mlp_forward_q_act.argtypes = [ctypes.POINTER(_Mlp), _P, ctypes.c_int64, ctypes.c_int32, _P, _P,
+                                                  ctypes.c_int32, _P]
+            lib.orc_mlp_loss_grad_act.restype = ctypes.c_double
+            lib.orc_mlp_loss_grad_act.argtypes = [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32, _P]
             lib.orc_mlp_forward_q.restype = ctypes.c_int
             lib.orc_mlp_forward_q.argtypes = [ctypes.POINTER(_Mlp), _P, ctypes.c_int64, ctypes.c_int32, _P, _P, _P]
             lib.orc_round_bf16.restype = ctypes.c_double
@@ -121,6 +128,7 @@ def frame(offsets, depth, rgba, prim, width, height, bg=(1.0, 1.0, 1.0), nthread
       lay   [P,10] N, d1, a1, c1(3), a2, c2(3)
       tail  [P,6] A, S(3), t_tail, 0
       sel   [P,2] global fragment index of layers 1 and 2 (0xFFFFFFFF if none)
+      tavg  [P,4] tail means: colour sum c / (N-2) and opacity sum a / (N-2)
     """
     lib = _load()
     P = int(width) * int(height)
@@ -136,10 +144,11 @@ def frame(offsets, depth, rgba, prim, width, height, bg=(1.0, 1.0, 1.0), nthread
         "lay": np.empty((P, 10), np.float64) if "lay" in want else None,
         "tail": np.empty((P, 6), np.float64) if "tail" in want else None,
         "sel": np.empty((P, 2), np.uint32) if "sel" in want else None,
+        "tavg": np.empty((P, 4), np.float64) if "tavg" in want else None,
     }
     rc = lib.orc_frame(int(width), int(height), _ptr(off), _ptr(dep), _ptr(col), _ptr(pr), _ptr(bgv),
                        _ptr(bufs["rgb"]), _ptr(bufs["fstar"]), _ptr(bufs["lay"]), _ptr(bufs["tail"]),
-                       _ptr(bufs["sel"]), int(nthreads))
+                       _ptr(bufs["sel"]), _ptr(bufs["tavg"]), int(nthreads))
     if rc != 0:
         raise RuntimeError("orc_frame failed")
     for k, v in bufs.items():
@@ -169,9 +178,12 @@ def features(lay, tail):
 # network
 
 class Mlp:
-    """Three dense layers W_l[out][in] (float32 data), ReLU after each."""
+    """Three dense layers W_l[out][in] (float32 data), ReLU after the hidden
+    layers; the output activation is ReLU (act 0, STAR-NT) or the logistic
+    sigmoid (act 1, the DFAOIT network)."""
 
-    def __init__(self, Ws, bs):
+    def __init__(self, Ws, bs, act=0):
+        self.act = int(act)
         self.Ws = [np.ascontiguousarray(w, np.float32) for w in Ws]
         self.bs = [np.ascontiguousarray(b, np.float32) for b in bs]
         self.dims = (self.Ws[0].shape[1], self.Ws[0].shape[0], self.Ws[1].shape[0], self.Ws[2].shape[0])
@@ -182,7 +194,7 @@ class Mlp:
         x = _c(x, np.float64)
         n = x.shape[0]
         y = np.empty((n, self.dims[3]), np.float64)
-        if _load().orc_mlp_forward(ctypes.byref(self._s), _ptr(x), n, _ptr(y)) != 0:
+        if _load().orc_mlp_forward_act(ctypes.byref(self._s), _ptr(x), n, self.act, _ptr(y)) != 0:
             raise RuntimeError("orc_mlp_forward failed")
         return y
 
@@ -193,8 +205,8 @@ class Mlp:
         y = np.empty((n, self.dims[3]), np.float64)
         sa_ = _c(sa if sa is not None else np.ones(3), np.float64)
         sw_ = _c(sw if sw is not None else np.ones(3), np.float64)
-        if _load().orc_mlp_forward_q(ctypes.byref(self._s), _ptr(x), n, int(qmode), _ptr(sa_), _ptr(sw_),
-                                     _ptr(y)) != 0:
+        if _load().orc_mlp_forward_q_act(ctypes.byref(self._s), _ptr(x), n, int(qmode), _ptr(sa_), _ptr(sw_),
+                                         self.act, _ptr(y)) != 0:
             raise RuntimeError("orc_mlp_forward_q failed")
         return y
 
@@ -337,14 +349,15 @@ def reproject_full(d1_r, vp_r, vp_t, width, height):
 # ---------------------------------------------------------------------------
 # training
 
-def loss_grad(dims, params, x, y):
-    """MSE loss and its gradient for the flat parameter vector (FP64)."""
+def loss_grad(dims, params, x, y, act=0):
+    """MSE loss and its gradient for the flat parameter vector (FP64); act
+    selects the output activation (0 ReLU, 1 sigmoid)."""
     d = np.asarray(dims, np.int32)
     w = _c(params, np.float64)
     x = _c(x, np.float64)
     y = _c(y, np.float64)
     g = np.empty_like(w)
-    loss = _load().orc_mlp_loss_grad(_ptr(d), _ptr(w), _ptr(x), _ptr(y), x.shape[0], _ptr(g))
+    loss = _load().orc_mlp_loss_grad_act(_ptr(d), _ptr(w), _ptr(x), _ptr(y), x.shape[0], int(act), _ptr(g))
     return loss, g
 
 
@@ -453,3 +466,35 @@ def interval_schedule(costs, target_ms, max_interval=4, smoothing=0.25):
         m = mean[real]
         mean[real] = c if m is None else m + smoothing * (c - m)
     return kinds, (mean[True], mean[False])
+
+
+# ---------------------------------------------------------------------------
+# the DFAOIT network's inputs and composite (Sec. 3.3, eq (2))
+
+def dfa_features(lay, tail, tavg):
+    """[P,16] DFAOIT input: the exact two-layer colour a1 c1 + (1-a1) a2 c2,
+    the tail's mean colour and mean opacity, the tail's accumulated
+    premultiplied colour C_acc = sum a c, and N; then zeros.
+    Reading: the paper counts ten features for these items (eleven values);
+    all listed items are used."""
+    P = lay.shape[0]
+    x = np.zeros((P, 16), np.float64)
+    a1, c1, a2, c2 = lay[:, 2:3], lay[:, 3:6], lay[:, 6:7], lay[:, 7:10]
+    x[:, 0:3] = a1 * c1 + (1.0 - a1) * a2 * c2
+    x[:, 3:6] = tavg[:, 0:3]
+    x[:, 6] = tavg[:, 3]
+    x[:, 7:10] = tail[:, 1:4]
+    x[:, 10] = lay[:, 0]
+    return x
+
+
+def dfa_composite(lay, tail, f, bg=(1.0, 1.0, 1.0)):
+    """eq (2): C = C_t + C_b prod_i (1 - a_i) with C_t the network output where
+    N >= 3 and the exact two-layer colour where N <= 2 (reading: both methods
+    leave the tail-free pixels exact, so the ablation differs only where
+    there is a tail)."""
+    a1, c1, a2, c2 = lay[:, 2:3], lay[:, 3:6], lay[:, 6:7], lay[:, 7:10]
+    exact2 = a1 * c1 + (1.0 - a1) * a2 * c2
+    T = (1.0 - a1) * (1.0 - a2) * tail[:, 4:5]
+    Ct = np.where(lay[:, 0:1] >= 3, f, exact2)
+    return Ct + T * np.asarray(bg, np.float64)[None, :]

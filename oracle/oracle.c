@@ -94,11 +94,14 @@ static uint32_t find_index(const uint32_t* off, const float* depth, const uint32
  * tail  [P][6]  A = sum a, S = sum a*c (3), t_tail = prod (1-a), Ctilde
  *               is not stored (S/A); tail = sorted positions 3..N
  * sel   [P][2]  global fragment index of layer 1 and layer 2 (0xFFFFFFFF if none)
+ * tavg  [P][4]  plain means over the tail (sorted positions 3..N): colour
+ *               sum c / (N-2) and opacity sum a / (N-2); 0 when N <= 2
+ *               (inputs of the DFAOIT network, Sec. 3.3)
  * Any output pointer may be NULL.
  */
 int orc_frame(int32_t W, int32_t H, const uint32_t* off, const float* depth, const float* rgba,
               const uint32_t* prim, const double* bg, double* rgb, double* fstar, double* lay, double* tail,
-              uint32_t* sel, int32_t nthreads) {
+              uint32_t* sel, double* tavg, int32_t nthreads) {
   int64_t P = (int64_t)W * H;
   uint32_t maxn = 0;
   for (int64_t p = 0; p < P; ++p) {
@@ -173,6 +176,18 @@ int orc_frame(int32_t W, int32_t H, const uint32_t* off, const float* depth, con
         Q[4] = t;
         Q[5] = 0.0;
       }
+      if (tavg) {
+        double sc[3] = {0, 0, 0}, sa = 0;
+        for (int j = 2; j < n; ++j) {
+          sc[0] += f[j].r;
+          sc[1] += f[j].g;
+          sc[2] += f[j].b;
+          sa += f[j].a;
+        }
+        double* Q = tavg + 4 * p;
+        for (int c = 0; c < 3; ++c) Q[c] = n > 2 ? sc[c] / (n - 2) : 0.0;
+        Q[3] = n > 2 ? sa / (n - 2) : 0.0;
+      }
       if (sel) {
         sel[2 * p + 0] = n > 0 ? find_index(off, depth, prim, p, &f[0]) : 0xFFFFFFFFu;
         sel[2 * p + 1] = n > 1 ? find_index(off, depth, prim, p, &f[1]) : 0xFFFFFFFFu;
@@ -214,16 +229,29 @@ static void dense_relu(int nin, int nout, const float* W, const float* b, const 
   }
 }
 
+/* Output activation: act 0 ReLU (STAR-NT, Sec. 3.3), act 1 logistic sigmoid
+ * (the DFAOIT network the paper starts from, Sec. 3.3). Hidden layers are
+ * ReLU in both. */
+static double out_act(double z, int32_t act) { return act ? 1.0 / (1.0 + exp(-z)) : (z > 0.0 ? z : 0.0); }
+
 /* y[n][out] = f(x[n][in]) in FP64 */
-int orc_mlp_forward(const orc_mlp* m, const double* x, int64_t n, double* y) {
+int orc_mlp_forward_act(const orc_mlp* m, const double* x, int64_t n, int32_t act, double* y) {
   if (m->h1 > 1024 || m->h2 > 1024 || m->out > 64 || m->in > 64) return -1;
   for (int64_t k = 0; k < n; ++k) {
     double h1[1024], h2[1024];
     dense_relu(m->in, m->h1, m->W1, m->b1, x + (size_t)k * m->in, h1);
     dense_relu(m->h1, m->h2, m->W2, m->b2, h1, h2);
-    dense_relu(m->h2, m->out, m->W3, m->b3, h2, y + (size_t)k * m->out);
+    for (int o = 0; o < m->out; ++o) {
+      double s = m->b3[o];
+      for (int i = 0; i < m->h2; ++i) s += (double)m->W3[(size_t)o * m->h2 + i] * h2[i];
+      y[(size_t)k * m->out + o] = out_act(s, act);
+    }
   }
   return 0;
+}
+
+int orc_mlp_forward(const orc_mlp* m, const double* x, int64_t n, double* y) {
+  return orc_mlp_forward_act(m, x, n, 0, y);
 }
 
 /* ---- reduced-precision operands (used only to state per-layer error) ---- */
@@ -280,8 +308,8 @@ double orc_round_e4m3(double v) { return round_e4m3(v); }
  * For e4m3, layer l uses activation scale sa[l] and weight scale sw[l]:
  *   y = (sum_i q(x_i / sa) q(W_oi / sw)) * sa * sw + b.
  */
-int orc_mlp_forward_q(const orc_mlp* m, const double* x, int64_t n, int32_t qmode, const double* sa,
-                      const double* sw, double* y) {
+int orc_mlp_forward_q_act(const orc_mlp* m, const double* x, int64_t n, int32_t qmode, const double* sa,
+                          const double* sw, int32_t act, double* y) {
   if (m->h1 > 1024 || m->h2 > 1024 || m->out > 64 || m->in > 64) return -1;
   const int dims[4] = {m->in, m->h1, m->h2, m->out};
   const float* Ws[3] = {m->W1, m->W2, m->W3};
@@ -306,13 +334,18 @@ int orc_mlp_forward_q(const orc_mlp* m, const double* x, int64_t n, int32_t qmod
         }
         if (qmode == 2) s *= sa[l] * sw[l];
         s += bs[l][j];
-        o[j] = s > 0.0 ? s : 0.0;
+        o[j] = l == 2 ? out_act(s, act) : (s > 0.0 ? s : 0.0);
       }
       for (int j = 0; j < nout; ++j) a[j] = o[j];
     }
     for (int j = 0; j < m->out; ++j) y[(size_t)k * m->out + j] = a[j];
   }
   return 0;
+}
+
+int orc_mlp_forward_q(const orc_mlp* m, const double* x, int64_t n, int32_t qmode, const double* sa,
+                      const double* sw, double* y) {
+  return orc_mlp_forward_q_act(m, x, n, qmode, sa, sw, 0, y);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -789,8 +822,8 @@ int orc_reproject_full(int32_t W, int32_t H, const float* d1_r, const double* vp
  * Loss = mean over B*out of (f(x) - y)^2. grad receives dLoss/dparams.
  * ReLU derivative at 0 is taken as 0.
  */
-double orc_mlp_loss_grad(const int32_t* dims, const double* w, const double* x, const double* y, int64_t B,
-                         double* grad) {
+double orc_mlp_loss_grad_act(const int32_t* dims, const double* w, const double* x, const double* y, int64_t B,
+                             int32_t act, double* grad) {
   const int in = dims[0], h1 = dims[1], h2 = dims[2], out = dims[3];
   const double* W1 = w;
   const double* b1 = W1 + (size_t)h1 * in;
@@ -833,10 +866,11 @@ double orc_mlp_loss_grad(const int32_t* dims, const double* w, const double* x, 
       z3[o] = s;
     }
     for (int o = 0; o < out; ++o) {
-      double f = z3[o] > 0 ? z3[o] : 0.0;
+      double f = out_act(z3[o], act);
       double e = f - yk[o];
       loss += e * e * scale;
-      d3[o] = z3[o] > 0 ? 2.0 * e * scale : 0.0;
+      double df = act ? f * (1.0 - f) : (z3[o] > 0 ? 1.0 : 0.0);
+      d3[o] = 2.0 * e * scale * df;
     }
     if (!grad) continue;
     for (int i = 0; i < h2; ++i) {
@@ -864,6 +898,11 @@ double orc_mlp_loss_grad(const int32_t* dims, const double* w, const double* x, 
   }
   free(z1);
   return loss;
+}
+
+double orc_mlp_loss_grad(const int32_t* dims, const double* w, const double* x, const double* y, int64_t B,
+                         double* grad) {
+  return orc_mlp_loss_grad_act(dims, w, x, y, B, 0, grad);
 }
 
 /*

@@ -113,6 +113,10 @@ typedef struct {
   uint32_t* sel;      /* optional [P][2]: global index of layers 1 and 2
                          (0xFFFFFFFF when absent); NULL to skip                 */
   uint32_t* err;      /* device error word (flags OR-ed in; caller zeroes it)   */
+  float* tail_avg;    /* optional [P][4] capacity; per pass-3 grid sample the
+                         plain tail means (sum c / (N-2), sum a / (N-2)), 0
+                         when N <= 2: inputs of the DFAOIT network (Sec. 3.3);
+                         NULL to skip (then no extra work)                      */
 } starnt_feats;
 
 /* ---- tail-colour network ----------------------------------------------------
@@ -128,7 +132,14 @@ typedef struct {
   const float *W1, *b1, *W2, *b2, *W3, *b3;
   const float* fp8_scales;  /* host [6]: sa1, sw1, sa2, sw2, sa3, sw3 (FP8 only):
                                layer l computes (sum q(a/sa) q(W/sw)) sa sw + b  */
+  int32_t variant;          /* STARNT_NET_STARNT (5 inputs, ReLU output, the
+                               tail colour; default 0) or STARNT_NET_DFAOIT (the
+                               ten-feature network STAR-NT builds on, Sec. 3.3:
+                               11 inputs, sigmoid output, the whole transparent
+                               colour C_t of eq (2))                            */
 } starnt_mlp;
+#define STARNT_NET_STARNT 0
+#define STARNT_NET_DFAOIT 1
 
 /* ---- composite modes ---------------------------------------------------- */
 #define STARNT_MODE_LEARNED 0 /* f = tail_rgb from starnt_infer                 */
@@ -153,6 +164,8 @@ typedef struct {
   float* m;                 /* [n] Adam first moment                            */
   float* v;                 /* [n] Adam second moment                           */
   float* grad;              /* [n] written: gradient of this step's loss        */
+  int32_t out_act;          /* output activation: 0 ReLU (STAR-NT), 1 logistic
+                               sigmoid (DFAOIT); hidden layers are ReLU         */
 } starnt_train;
 
 typedef struct {
@@ -178,16 +191,29 @@ int starnt_features(const starnt_frags* frags, const starnt_sched* sched, const 
 /* Tail colour at full resolution (Sec. 3.3): for each pixel with count >= 3,
  * x is the bilinear upscale (half-pixel centres, clamp to edge) of the tail
  * records on the pass-3 grid of `sched` (NULL = full resolution) and
- * tail_rgb[p] = f(x); tail_rgb[p] = 0 where count < 3. tail_rgb is [P][3]. */
+ * tail_rgb[p] = f(x); tail_rgb[p] = 0 where count < 3. tail_rgb is [P][3].
+ * STARNT_NET_STARNT networks only (EINVAL for DFAOIT: it needs the layers). */
 int starnt_infer(const starnt_mlp* mlp, const float* tail, const uint32_t* count, const starnt_sched* sched,
                  int32_t width, int32_t height, float* tail_rgb, void* stream);
 
 /* starnt_infer followed by starnt_composite(STARNT_MODE_LEARNED) in one pass
  * (same results): per pixel the upscaled features feed the network and its
  * output goes straight into eq (3), so the tail colour is never stored.
- * Frame size from feats; rgb is [P][3]; bg is a host float[3]. */
+ * Frame size from feats; rgb is [P][3]; bg is a host float[3].
+ * With a STARNT_NET_DFAOIT network (needs feats->tail_avg) the input is the
+ * upscaled DFAOIT vector of starnt_dfa_inputs and the result is eq (2):
+ * C = C_t + C_b (1 - a1)(1 - a2) t_tail, with C_t the network output where
+ * count >= 3 and the exact two-layer colour a1 c1 + (1 - a1) a2 c2 elsewhere. */
 int starnt_infer_composite(const starnt_mlp* mlp, const starnt_feats* feats, const starnt_sched* sched,
                            const float* bg, float* rgb, void* stream);
+
+/* The DFAOIT network input of every pixel (Sec. 3.3), x [P][16] float, zero
+ * where count < 3: (exact two-layer colour a1 c1 + (1 - a1) a2 c2, tail mean
+ * colour, tail mean opacity, tail accumulated colour S = Ct A, N, 0 x 5), with
+ * layer 2 and the pass-3 quantities upscaled from their grids as in eq (3)
+ * (S per grid sample, then upscaled). Needs feats->tail_avg. Used to build
+ * training pairs for STARNT_NET_DFAOIT networks. */
+int starnt_dfa_inputs(const starnt_feats* feats, const starnt_sched* sched, float* x, void* stream);
 
 /* Final colour rgb [P][3].
  * MODE_LEARNED / F0 / FAVG (eq (3), Sec. 3.3): with layer 2 and x upscaled

@@ -498,3 +498,51 @@ def dfa_composite(lay, tail, f, bg=(1.0, 1.0, 1.0)):
     T = (1.0 - a1) * (1.0 - a2) * tail[:, 4:5]
     Ct = np.where(lay[:, 0:1] >= 3, f, exact2)
     return Ct + T * np.asarray(bg, np.float64)[None, :]
+
+
+def dfa_learned(lay, tail, tavg, width, height, grids, mlp, bg=(1.0, 1.0, 1.0)):
+    """The DFAOIT path with passes 2/3 on the given grids (W2, H2, W3, H3):
+    layer 2 (a2, a2 c2) sampled on the pass-2 grid and the per-sample tail
+    quantities (N, t_tail, S = sum a c, tail means) on the pass-3 grid are
+    upscaled bilinearly (upsample), the full-resolution N gates them (no
+    layer 2 where N < 2, no tail where N < 3), the input is dfa_features of
+    the upscaled values, and eq (2) composites. mlp is None for the inputs
+    alone. Returns (rgb [P,3], x [P,16], f [P,3])."""
+    W, H = int(width), int(height)
+    P = W * H
+    W2, H2, W3, H3 = [int(v) for v in grids]
+    lay = np.asarray(lay, np.float64)
+    tail = np.asarray(tail, np.float64)
+    tavg = np.asarray(tavg, np.float64)
+    g2 = np.zeros((H2, W2, 4))
+    for j in range(H2):
+        for i in range(W2):
+            L = lay[sample_pos(H, H2, j) * W + sample_pos(W, W2, i)]
+            g2[j, i] = (L[6], L[6] * L[7], L[6] * L[8], L[6] * L[9])
+    g3 = np.zeros((H3, W3, 9))
+    for j in range(H3):
+        for i in range(W3):
+            p = sample_pos(H, H3, j) * W + sample_pos(W, W3, i)
+            g3[j, i] = (lay[p, 0], tail[p, 4], *tail[p, 1:4], *tavg[p])
+    u2 = upsample(g2, W, H).reshape(P, 4)
+    u3 = upsample(g3, W, H).reshape(P, 9)
+    N = lay[:, 0]
+    u2[N < 2] = 0.0
+    a1, c1 = lay[:, 2:3], lay[:, 3:6]
+    a2, pc2 = u2[:, 0:1], u2[:, 1:4]
+    exact2 = a1 * c1 + (1.0 - a1) * pc2
+    tailed = N >= 3
+    x = np.zeros((P, 16))
+    x[:, 0:3] = exact2
+    x[:, 3:6] = u3[:, 5:8]
+    x[:, 6] = u3[:, 8]
+    x[:, 7:10] = u3[:, 2:5]
+    x[:, 10] = u3[:, 0]
+    x[~tailed] = 0.0
+    f = np.zeros((P, 3))
+    if mlp is not None and tailed.any():
+        f[tailed] = mlp.forward(x[tailed])
+    tt = np.where(tailed, u3[:, 1], 1.0)[:, None]
+    Ct = np.where(tailed[:, None], f, exact2)
+    rgb = Ct + (1.0 - a1) * (1.0 - a2) * tt * np.asarray(bg, np.float64)[None, :]
+    return rgb, x, f

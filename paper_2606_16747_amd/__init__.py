@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libstarnt.so")
 
 F32, F16, BF16, FP8 = 0, 1, 2, 3
 MODE_LEARNED, MODE_F0, MODE_FAVG, MODE_EXACT = 0, 1, 2, 3
+NET_STARNT, NET_DFAOIT = 0, 1
 BASE_WBOIT, BASE_OVER_LIST = 0, 1
 WS_QUADTREE, WS_TRAIN = 1, 2
 DERR_DEPTH, DERR_ALPHA, DERR_COUNT = 1, 2, 4
@@ -49,13 +50,13 @@ class Sched(ctypes.Structure):
 
 class Feats(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("d1", _P), ("layer1", _P),
-                ("count", _P), ("layer2", _P), ("tail", _P), ("sel", _P), ("err", _P)]
+                ("count", _P), ("layer2", _P), ("tail", _P), ("sel", _P), ("err", _P), ("tail_avg", _P)]
 
 
 class Mlp(ctypes.Structure):
     _fields_ = [("in_", ctypes.c_int32), ("h1", ctypes.c_int32), ("h2", ctypes.c_int32), ("out", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("W1", _P), ("b1", _P), ("W2", _P), ("b2", _P), ("W3", _P), ("b3", _P),
-                ("fp8_scales", ctypes.POINTER(ctypes.c_float))]
+                ("fp8_scales", ctypes.POINTER(ctypes.c_float)), ("variant", ctypes.c_int32)]
 
 
 class QtParams(ctypes.Structure):
@@ -65,7 +66,8 @@ class QtParams(ctypes.Structure):
 
 class Train(ctypes.Structure):
     _fields_ = [("in_", ctypes.c_int32), ("h1", ctypes.c_int32), ("h2", ctypes.c_int32), ("out", ctypes.c_int32),
-                ("dtype", ctypes.c_int32), ("params", _P), ("m", _P), ("v", _P), ("grad", _P)]
+                ("dtype", ctypes.c_int32), ("params", _P), ("m", _P), ("v", _P), ("grad", _P),
+                ("out_act", ctypes.c_int32)]
 
 
 class Adam(ctypes.Structure):
@@ -82,6 +84,7 @@ class Interval(ctypes.Structure):
 assert ctypes.sizeof(Sched) == 64
 
 EXPORTS = ("starnt_features", "starnt_infer", "starnt_infer_composite", "starnt_composite", "starnt_baseline",
+           "starnt_dfa_inputs",
            "starnt_quadtree", "starnt_reproject", "starnt_interval_init", "starnt_interval_next",
            "starnt_interval_report",
            "starnt_train_step", "starnt_sched_init", "starnt_wbar", "starnt_pass_scales", "starnt_grid_dim",
@@ -98,6 +101,7 @@ def _load():
                                            ctypes.POINTER(ctypes.c_float), _P, _P]
     lib.starnt_composite.argtypes = [ctypes.POINTER(Frags), ctypes.POINTER(Feats), _P, _P,
                                      ctypes.POINTER(ctypes.c_float), ctypes.c_int32, _P, _P, _P]
+    lib.starnt_dfa_inputs.argtypes = [ctypes.POINTER(Feats), _P, _P, _P]
     lib.starnt_baseline.argtypes = [ctypes.POINTER(Frags), ctypes.c_int32, ctypes.POINTER(ctypes.c_float), _P, _P]
     lib.starnt_interval_init.argtypes = [ctypes.POINTER(Interval), ctypes.c_double, ctypes.c_int32, ctypes.c_double]
     lib.starnt_interval_next.argtypes = [ctypes.POINTER(Interval)]
@@ -191,7 +195,7 @@ class DeviceFrags:
 class FeatBuffers:
     """Outputs of starnt_features (full-resolution capacity)."""
 
-    def __init__(self, width, height, device="cuda", with_sel=False):
+    def __init__(self, width, height, device="cuda", with_sel=False, with_avg=False):
         P = int(width) * int(height)
         self.width, self.height = int(width), int(height)
         self.d1 = torch.empty(P, dtype=torch.float32, device=device)
@@ -201,12 +205,14 @@ class FeatBuffers:
         self.tail = torch.zeros(P, 8, dtype=torch.float32, device=device)
         self.sel = torch.empty(P, 2, dtype=torch.int32, device=device) if with_sel else None
         self.err = torch.zeros(1, dtype=torch.int32, device=device)
+        self.tail_avg = torch.zeros(P, 4, dtype=torch.float32, device=device) if with_avg else None
         self._c = self.c()
 
     def c(self):
         return Feats(self.width, self.height, self.d1.data_ptr(), self.layer1.data_ptr(), self.count.data_ptr(),
                      self.layer2.data_ptr(), self.tail.data_ptr(),
-                     self.sel.data_ptr() if self.sel is not None else None, self.err.data_ptr())
+                     self.sel.data_ptr() if self.sel is not None else None, self.err.data_ptr(),
+                     self.tail_avg.data_ptr() if self.tail_avg is not None else None)
 
 
 def new_sched(width, height, s2=1.0, s3=1.0, device="cuda", stream=None):
@@ -227,10 +233,11 @@ def read_sched(t):
 class DeviceMlp:
     """FP32 master weights of the tail network on the device."""
 
-    def __init__(self, Ws, bs, dtype=F32, fp8_scales=None, device="cuda"):
+    def __init__(self, Ws, bs, dtype=F32, fp8_scales=None, device="cuda", variant=NET_STARNT):
         self.Ws = [_dev(w, torch.float32, device) for w in Ws]
         self.bs = [_dev(b, torch.float32, device) for b in bs]
         self.dims = (self.Ws[0].shape[1], self.Ws[0].shape[0], self.Ws[1].shape[0], self.Ws[2].shape[0])
+        self.variant = int(variant)
         self.set_dtype(dtype, fp8_scales)
 
     def set_dtype(self, dtype, fp8_scales=None):
@@ -239,7 +246,7 @@ class DeviceMlp:
         W, b = self.Ws, self.bs
         self._c = Mlp(self.dims[0], self.dims[1], self.dims[2], self.dims[3], dtype, W[0].data_ptr(),
                       b[0].data_ptr(), W[1].data_ptr(), b[1].data_ptr(), W[2].data_ptr(), b[2].data_ptr(),
-                      self._scales)
+                      self._scales, self.variant)
         return self
 
 
@@ -273,6 +280,10 @@ def starnt_composite(frags, feats, tail_rgb, sched, bg, mode, rgb, fstar=None, s
     _check(lib.starnt_composite(ctypes.byref(frags._c) if frags is not None else None,
                                 ctypes.byref(feats._c) if feats is not None else None, _ptr(tail_rgb), _ptr(sched),
                                 bgc, int(mode), _ptr(rgb), _ptr(fstar), _stream(stream)))
+
+
+def starnt_dfa_inputs(feats: FeatBuffers, sched, x, stream=None):
+    _check(lib.starnt_dfa_inputs(ctypes.byref(feats._c), _ptr(sched), _ptr(x), _stream(stream)))
 
 
 def starnt_baseline(frags, method, bg, rgb, stream=None):

@@ -64,6 +64,8 @@ int check_mlp(const starnt_mlp* mlp, const char* who) {
     for (int i = 0; i < 6; ++i)
       if (!(mlp->fp8_scales[i] > 0.0f) || !std::isfinite(mlp->fp8_scales[i]))
         return fail(STARNT_EINVAL, w + ": fp8 scales must be finite and positive");
+  if (mlp->variant != STARNT_NET_STARNT && mlp->variant != STARNT_NET_DFAOIT)
+    return fail(STARNT_EINVAL, w + ": variant must be STARNT_NET_STARNT or STARNT_NET_DFAOIT");
   return STARNT_OK;
 }
 
@@ -91,6 +93,8 @@ int starnt_infer(const starnt_mlp* mlp, const float* tail, const uint32_t* count
   if (!tail || !count || !tail_rgb) return fail(STARNT_EINVAL, "starnt_infer: NULL argument");
   rc = check_mlp(mlp, "starnt_infer");
   if (rc) return rc;
+  if (mlp->variant != STARNT_NET_STARNT)
+    return fail(STARNT_EINVAL, "starnt_infer: a DFAOIT network needs the layers (starnt_infer_composite)");
   return launch_infer(*mlp, tail, count, sched, width, height, tail_rgb, as_stream(stream));
 }
 
@@ -103,7 +107,18 @@ int starnt_infer_composite(const starnt_mlp* mlp, const starnt_feats* feats, con
     return fail(STARNT_EINVAL, "starnt_infer_composite: NULL argument");
   rc = check_mlp(mlp, "starnt_infer_composite");
   if (rc) return rc;
+  if (mlp->variant == STARNT_NET_DFAOIT && !feats->tail_avg)
+    return fail(STARNT_EINVAL, "starnt_infer_composite: a DFAOIT network needs feats->tail_avg");
   return launch_infer_composite(*mlp, *feats, sched, bg, rgb, as_stream(stream));
+}
+
+int starnt_dfa_inputs(const starnt_feats* feats, const starnt_sched* sched, float* x, void* stream) {
+  if (!feats) return fail(STARNT_EINVAL, "starnt_dfa_inputs: NULL feats");
+  int rc = check_frame(feats->width, feats->height, "starnt_dfa_inputs");
+  if (rc) return rc;
+  if (!x || !feats->layer1 || !feats->count || !feats->layer2 || !feats->tail || !feats->tail_avg)
+    return fail(STARNT_EINVAL, "starnt_dfa_inputs: NULL argument (x, layer1, count, layer2, tail, tail_avg)");
+  return launch_dfa_inputs(*feats, sched, x, as_stream(stream));
 }
 
 int starnt_composite(const starnt_frags* frags, const starnt_feats* feats, const float* tail_rgb,
@@ -187,6 +202,7 @@ int starnt_train_step(const starnt_train* t, const float* x, const float* y, int
     return fail(STARNT_EINVAL, "starnt_train_step: dtype must be STARNT_F32 or STARNT_BF16");
   if (batch < 1 || batch > (1 << 24)) return fail(STARNT_EINVAL, "starnt_train_step: batch must be in [1, 2^24]");
   if (hp->step < 1) return fail(STARNT_EINVAL, "starnt_train_step: Adam step is 1-based");
+  if (t->out_act != 0 && t->out_act != 1) return fail(STARNT_EINVAL, "starnt_train_step: out_act must be 0 or 1");
   if (!(hp->beta1 >= 0.0f && hp->beta1 < 1.0f && hp->beta2 >= 0.0f && hp->beta2 < 1.0f))
     return fail(STARNT_EINVAL, "starnt_train_step: betas must be in [0, 1)");
   const size_t need = train_ws_bytes(batch, t->h1, t->h2);

@@ -76,6 +76,7 @@ struct FeatArgs {
   float4* tail;
   uint2* sel;
   uint32_t* err;
+  float4* tail_avg;  // optional tail means (DFAOIT inputs)
 };
 
 // Fixed-point terms of one fragment. Each is an exact integer function of
@@ -113,14 +114,17 @@ __device__ __forceinline__ Terms frag_terms(float4 c) {
 template <typename V>
 struct Sums {
   V a = 0, r = 0, g = 0, b = 0;
+  V cr = 0, cg = 0, cb = 0;  // plain colour sums (tail means only)
   uint64_t lg = 0;
 };
 struct Part {
   uint32_t a = 0, r = 0, g = 0, b = 0;
+  uint32_t cr = 0, cg = 0, cb = 0;
 };
-template <typename V>
+template <bool AVG, typename V>
 __device__ __forceinline__ void fold(Sums<V>& s, Part& p) {
   s.a += p.a; s.r += p.r; s.g += p.g; s.b += p.b;
+  if (AVG) { s.cr += p.cr; s.cg += p.cg; s.cb += p.cb; }
   p = Part();
 }
 
@@ -151,15 +155,21 @@ __device__ __forceinline__ void top2_push(Top2& t, float z, uint32_t k, const ui
   t.k1 = lt1 ? k : t.k1;
 }
 
-__device__ __forceinline__ void add_terms(Part& p, uint64_t& lg, const Terms& q) {
+template <bool AVG>
+__device__ __forceinline__ void add_terms(Part& p, uint64_t& lg, const Terms& q, float4 c) {
   p.a += q.a; p.r += q.r; p.g += q.g; p.b += q.b;
   lg += q.lg;
+  if (AVG) {  // plain colour in Q24 (a colour is zero when its fragment is absent)
+    p.cr += round_q(c.x * kQ24);
+    p.cg += round_q(c.y * kQ24);
+    p.cb += round_q(c.z * kQ24);
+  }
 }
 
 // One lane's share of a list: fragments b+q, b+q+4, ..., two per step so both
 // loads are in flight together. RGBA is loaded only when `rgba` (pass-3
 // pixels); otherwise the colour is zero and so are its terms.
-template <bool HALF, bool WIDE, typename V>
+template <bool HALF, bool WIDE, bool AVG, typename V>
 __device__ __forceinline__ void stream(const FeatArgs& a, uint32_t b, uint32_t e, int q, bool rgba, Top2& t,
                                        Sums<V>& s, uint32_t& zmax, uint32_t& amax) {
   Part p;
@@ -178,8 +188,8 @@ __device__ __forceinline__ void stream(const FeatArgs& a, uint32_t b, uint32_t e
       top2_push(t, z0, k, a.prim);
       top2_push(t, z1, k + kG, a.prim);
       amax = max(amax, max(__float_as_uint(c0.w), __float_as_uint(c1.w)));
-      add_terms(p, s.lg, frag_terms(c0));
-      add_terms(p, s.lg, frag_terms(c1));
+      add_terms<AVG>(p, s.lg, frag_terms(c0), c0);
+      add_terms<AVG>(p, s.lg, frag_terms(c1), c1);
     }
     if (k < kend) {
       const float z = a.depth[k];
@@ -187,10 +197,10 @@ __device__ __forceinline__ void stream(const FeatArgs& a, uint32_t b, uint32_t e
       zmax = max(zmax, __float_as_uint(z));
       top2_push(t, z, k, a.prim);
       amax = max(amax, __float_as_uint(c0.w));
-      add_terms(p, s.lg, frag_terms(c0));
+      add_terms<AVG>(p, s.lg, frag_terms(c0), c0);
       k += kG;
     }
-    fold(s, p);
+    fold<AVG>(s, p);
   } while (WIDE && k < e);
 }
 
@@ -207,7 +217,7 @@ __device__ __forceinline__ float tail_transmittance(uint64_t lg) {
   return hi >= 16u ? 0.0f : __builtin_amdgcn_exp2f(-e);
 }
 
-template <bool HALF, bool WIDE>
+template <bool HALF, bool WIDE, bool AVG>
 __device__ __forceinline__ void pixel(const FeatArgs& a, const Grids& g, int p, int q, uint32_t b, uint32_t e,
                                       int i2, int j2, int i3, int j3) {
   using V = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
@@ -217,7 +227,7 @@ __device__ __forceinline__ void pixel(const FeatArgs& a, const Grids& g, int p, 
   Top2 t;
   Sums<V> s;
   uint32_t zmax = 0, amax = 0;
-  stream<HALF, WIDE>(a, b, e, q, pass3, t, s, zmax, amax);
+  stream<HALF, WIDE, AVG>(a, b, e, q, pass3, t, s, zmax, amax);
 
   // merge the quad's top-2 keys: two butterfly rounds
   {
@@ -285,6 +295,23 @@ __device__ __forceinline__ void pixel(const FeatArgs& a, const Grids& g, int p, 
     rec.x = q == 0 ? (float)n : (q == 1 ? o : (q == 2 ? nx : 0.0f));
     rec.y = q == 0 ? tt : (q == 1 ? nx : (q == 2 ? oa : 0.0f));
     reinterpret_cast<float2*>(a.tail + 2 * (size_t)(j3 * g.w3 + i3))[q] = rec;
+    if (AVG) {
+      // tail means: the colour sums all-reduced, the selected layers removed
+      // exactly; lane q < 3 writes colour channel q, lane 3 the mean opacity
+      V cr = s.cr + qperm<kXor1>(s.cr), cg = s.cg + qperm<kXor1>(s.cg), cb = s.cb + qperm<kXor1>(s.cb);
+      cr += qperm<kXor2>(cr);
+      cg += qperm<kXor2>(cg);
+      cb += qperm<kXor2>(cb);
+      const float inv_t = tail ? 1.0f / (float)(n - 2) : 0.0f;
+      // channel q's plain colour of the selected layers (q = 3: unused)
+      const float s1 = q == 0 ? c1.x : (q == 1 ? c1.y : c1.z);
+      const float s2 = q == 0 ? c2.x : (q == 1 ? c2.y : c2.z);
+      V cq = q == 0 ? cr : (q == 1 ? cg : cb);
+      cq -= (V)round_q(s1 * kQ24);
+      cq -= (V)round_q(s2 * kQ24);
+      const float av = q == 3 ? A * (1.0f / kQ24) : to_f32(cq) * (1.0f / kQ24);
+      reinterpret_cast<float*>(a.tail_avg + (j3 * g.w3 + i3))[q] = av * inv_t;
+    }
   }
   uint32_t errf = (q == 0 && n > a.max_n) ? STARNT_DERR_COUNT : 0u;
   errf |= zmax > kOne ? STARNT_DERR_DEPTH : 0u;
@@ -292,7 +319,7 @@ __device__ __forceinline__ void pixel(const FeatArgs& a, const Grids& g, int p, 
   if (errf) atomicOr(a.err, errf);
 }
 
-template <bool HALF>
+template <bool HALF, bool AVG>
 __global__ __launch_bounds__(256) void features_kernel(FeatArgs a) {
   const int P = a.W * a.H;
   const int q = threadIdx.x & (kG - 1);
@@ -306,9 +333,9 @@ __global__ __launch_bounds__(256) void features_kernel(FeatArgs a) {
   const uint32_t b = a.off[p], e = a.off[p + 1];
   // the 64-bit variant only where the wave holds a list longer than kNarrow
   if (__builtin_amdgcn_ballot_w64(e - b > kNarrow) != 0)
-    pixel<HALF, true>(a, g, p, q, b, e, i2, j2, i3, j3);
+    pixel<HALF, true, AVG>(a, g, p, q, b, e, i2, j2, i3, j3);
   else
-    pixel<HALF, false>(a, g, p, q, b, e, i2, j2, i3, j3);
+    pixel<HALF, false, AVG>(a, g, p, q, b, e, i2, j2, i3, j3);
 }
 
 }  // namespace
@@ -332,10 +359,15 @@ int launch_features(const starnt_frags& f, const starnt_sched* sched, const star
   a.err = o.err;
   const int P = f.width * f.height;
   const dim3 block(256), grid((unsigned)(((int64_t)P * kG + 255) / 256));
-  if (f.rgba_dtype == STARNT_F16)
-    hipLaunchKernelGGL(features_kernel<true>, grid, block, 0, s, a);
-  else
-    hipLaunchKernelGGL(features_kernel<false>, grid, block, 0, s, a);
+  a.tail_avg = reinterpret_cast<float4*>(o.tail_avg);
+  const bool half = f.rgba_dtype == STARNT_F16;
+  if (o.tail_avg) {
+    if (half) hipLaunchKernelGGL((features_kernel<true, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((features_kernel<false, true>), grid, block, 0, s, a);
+  } else {
+    if (half) hipLaunchKernelGGL((features_kernel<true, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((features_kernel<false, false>), grid, block, 0, s, a);
+  }
   STARNT_LAUNCH_CHECK("starnt_features launch");
   return STARNT_OK;
 }

@@ -26,9 +26,14 @@
 namespace starnt {
 namespace {
 
+// what a kernel produces: the tail colour (starnt_infer), the eq (3)
+// composite with it, or the DFAOIT composite (eq (2))
+constexpr int kTail = 0, kComp = 1, kDfa = 2;
+
 struct InferArgs {
   int W, H;
   const float4* tail;
+  const float4* tail_avg;  // tail means (DFAOIT only)
   const uint32_t* count;
   const float4* layer1;
   const float4* layer2;
@@ -48,9 +53,11 @@ struct InferArgs {
 // inputs of one pixel for the network and the composite
 struct PixIn {
   uint32_t n;
-  float x[5];          // upscaled features (n >= 3)
+  float x[11];         // upscaled network input (n >= 3): 5 values, or 11 (DFAOIT)
+  float tt;            // upscaled t_tail (n >= 3)
   float4 l1;           // layer 1 (composite only)
   float4 l2;           // upscaled layer 2 (composite only)
+  float e0, e1, e2;    // exact two-layer colour (DFAOIT only)
 };
 
 __device__ __forceinline__ float lerp1(float p, float q, float w) { return fmaf(w, q - p, p); }
@@ -62,14 +69,15 @@ __device__ __forceinline__ float4 lerp4(float4 a, float4 b, float w) {
 // loaded values, so a prefetched group costs one memory round trip.
 struct PixRaw {
   uint32_t n;
-  float4 t[4];   // x0..x3 of the four pass-3 taps
-  float t4[4];   // x4 of the four taps
+  float4 t[4];   // (N, t_tail, Ct_r, Ct_g) of the four pass-3 taps
+  float2 t4[4];  // (Ct_b, A) of the four taps (A: DFAOIT only)
+  float4 av[4];  // tail means of the four taps (DFAOIT only)
   float4 l1;
   float4 l2[4];  // the four pass-2 taps
   float wx3, wy3, wx2, wy2;
 };
 
-template <bool COMP>
+template <int MODE>
 __device__ __forceinline__ void issue_loads(const InferArgs& a, const Grids& g, int p, PixRaw& r) {
   r.n = a.count[p];
   int x, y;
@@ -85,11 +93,13 @@ __device__ __forceinline__ void issue_loads(const InferArgs& a, const Grids& g, 
   for (int k = 0; k < 4; ++k) {
     const uint32_t i = i3[k < taps3 ? k : 0];
     r.t[k] = a.tail[2u * i];
-    r.t4[k] = a.tail[2u * i + 1u].x;
+    const float4 hi = a.tail[2u * i + 1u];
+    r.t4[k] = make_float2(hi.x, MODE == kDfa ? hi.y : 0.0f);
+    if constexpr (MODE == kDfa) r.av[k] = a.tail_avg[i];
   }
   r.wx3 = tx.w1;
   r.wy3 = ty.w1;
-  if constexpr (COMP) {
+  if constexpr (MODE >= kComp) {
     r.l1 = a.layer1[p];
     const Taps ux = axis_taps(x, a.W, g.w2), uy = axis_taps(y, a.H, g.h2);
     const uint32_t i2[4] = {(uint32_t)(uy.i0 * g.w2 + ux.i0), (uint32_t)(uy.i0 * g.w2 + ux.i1),
@@ -103,63 +113,113 @@ __device__ __forceinline__ void issue_loads(const InferArgs& a, const Grids& g, 
 }
 
 // bilinear blend of the raw taps; the full-resolution count gates the terms
-template <bool COMP>
+__device__ __forceinline__ float blend4(float p0, float p1, float p2, float p3, float wx, float wy) {
+  return lerp1(lerp1(p0, p1, wx), lerp1(p2, p3, wx), wy);
+}
+
+template <int MODE>
 __device__ __forceinline__ PixIn blend(const PixRaw& r) {
   PixIn in;
   in.n = r.n;
+#pragma unroll
+  for (int e = 0; e < 11; ++e) in.x[e] = 0.0f;
+  in.tt = 1.0f;
   if (r.n >= 3) {
     const float4 v = lerp4(lerp4(r.t[0], r.t[1], r.wx3), lerp4(r.t[2], r.t[3], r.wx3), r.wy3);
-    in.x[0] = v.x; in.x[1] = v.y; in.x[2] = v.z; in.x[3] = v.w;
-    in.x[4] = lerp1(lerp1(r.t4[0], r.t4[1], r.wx3), lerp1(r.t4[2], r.t4[3], r.wx3), r.wy3);
-  } else {
-    in.x[0] = in.x[1] = in.x[2] = in.x[3] = in.x[4] = 0.0f;
+    const float cb = blend4(r.t4[0].x, r.t4[1].x, r.t4[2].x, r.t4[3].x, r.wx3, r.wy3);
+    in.tt = v.y;
+    if constexpr (MODE == kDfa) {
+      // x = (exact two-layer colour, tail mean colour, tail mean opacity,
+      // tail accumulated colour S = Ct A, N); S is formed per tap and then
+      // blended like every other input
+      const float4 av = lerp4(lerp4(r.av[0], r.av[1], r.wx3), lerp4(r.av[2], r.av[3], r.wx3), r.wy3);
+      in.x[3] = av.x; in.x[4] = av.y; in.x[5] = av.z; in.x[6] = av.w;
+      in.x[7] = blend4(r.t[0].z * r.t4[0].y, r.t[1].z * r.t4[1].y, r.t[2].z * r.t4[2].y, r.t[3].z * r.t4[3].y,
+                       r.wx3, r.wy3);
+      in.x[8] = blend4(r.t[0].w * r.t4[0].y, r.t[1].w * r.t4[1].y, r.t[2].w * r.t4[2].y, r.t[3].w * r.t4[3].y,
+                       r.wx3, r.wy3);
+      in.x[9] = blend4(r.t4[0].x * r.t4[0].y, r.t4[1].x * r.t4[1].y, r.t4[2].x * r.t4[2].y,
+                       r.t4[3].x * r.t4[3].y, r.wx3, r.wy3);
+      in.x[10] = v.x;
+    } else {
+      in.x[0] = v.x; in.x[1] = v.y; in.x[2] = v.z; in.x[3] = v.w;
+      in.x[4] = cb;
+    }
   }
-  if constexpr (COMP) {
+  if constexpr (MODE >= kComp) {
     in.l1 = r.l1;
     in.l2 = r.n >= 2 ? lerp4(lerp4(r.l2[0], r.l2[1], r.wx2), lerp4(r.l2[2], r.l2[3], r.wx2), r.wy2)
                      : make_float4(0.f, 0.f, 0.f, 0.f);
   }
+  if constexpr (MODE == kDfa) {
+    const float om1 = 1.0f - in.l1.w;
+    in.e0 = fmaf(om1, in.l2.x, in.l1.x);
+    in.e1 = fmaf(om1, in.l2.y, in.l1.y);
+    in.e2 = fmaf(om1, in.l2.z, in.l1.z);
+    if (r.n >= 3) { in.x[0] = in.e0; in.x[1] = in.e1; in.x[2] = in.e2; }
+  }
   return in;
 }
 
-template <bool COMP>
+template <int MODE>
 __device__ __forceinline__ void load_pixel(const InferArgs& a, const Grids& g, int p, bool, PixIn& in) {
   PixRaw r;
-  issue_loads<COMP>(a, g, p, r);
-  in = blend<COMP>(r);
+  issue_loads<MODE>(a, g, p, r);
+  in = blend<MODE>(r);
 }
 
-// write the tail colour, or the eq (3) composite with it
-template <bool COMP>
+// write the tail colour, the eq (3) composite with it, or the DFAOIT
+// composite (eq (2)): C_t + C_b prod(1 - a), with C_t the network's colour
+// where N >= 3 and the exact two-layer colour elsewhere
+template <int MODE>
 __device__ __forceinline__ void store_pixel(const InferArgs& a, int p, const PixIn& in, float f0, float f1, float f2) {
   const bool on = in.n >= 3;
-  if (!on) { f0 = f1 = f2 = 0.0f; }
-  if constexpr (COMP) {
-    const float tt = on ? in.x[1] : 1.0f;
-    const float om1 = 1.0f - in.l1.w;
-    const float T2 = om1 * (1.0f - in.l2.w);
-    const float Tb = T2 * tt;
-    a.out[3 * (size_t)p + 0] = in.l1.x + om1 * in.l2.x + T2 * f0 + Tb * a.bg0;
-    a.out[3 * (size_t)p + 1] = in.l1.y + om1 * in.l2.y + T2 * f1 + Tb * a.bg1;
-    a.out[3 * (size_t)p + 2] = in.l1.z + om1 * in.l2.z + T2 * f2 + Tb * a.bg2;
+  float* o = a.out + 3 * (size_t)p;
+  if constexpr (MODE == kDfa) {
+    const float T = (1.0f - in.l1.w) * (1.0f - in.l2.w) * (on ? in.tt : 1.0f);
+    o[0] = fmaf(T, a.bg0, on ? f0 : in.e0);
+    o[1] = fmaf(T, a.bg1, on ? f1 : in.e1);
+    o[2] = fmaf(T, a.bg2, on ? f2 : in.e2);
   } else {
-    a.out[3 * (size_t)p + 0] = f0;
-    a.out[3 * (size_t)p + 1] = f1;
-    a.out[3 * (size_t)p + 2] = f2;
+    if (!on) { f0 = f1 = f2 = 0.0f; }
+    if constexpr (MODE == kComp) {
+      const float tt = on ? in.tt : 1.0f;
+      const float om1 = 1.0f - in.l1.w;
+      const float T2 = om1 * (1.0f - in.l2.w);
+      const float Tb = T2 * tt;
+      o[0] = in.l1.x + om1 * in.l2.x + T2 * f0 + Tb * a.bg0;
+      o[1] = in.l1.y + om1 * in.l2.y + T2 * f1 + Tb * a.bg1;
+      o[2] = in.l1.z + om1 * in.l2.z + T2 * f2 + Tb * a.bg2;
+    } else {
+      o[0] = f0;
+      o[1] = f1;
+      o[2] = f2;
+    }
   }
 }
+
+// output activation: ReLU (STAR-NT) or the logistic sigmoid (DFAOIT)
+template <int MODE>
+__device__ __forceinline__ float out_act(float z) {
+  if constexpr (MODE == kDfa) return 1.0f / (1.0f + __expf(-z));
+  else return fmaxf(z, 0.0f);
+}
+
+// number of network inputs in use
+template <int MODE>
+constexpr int n_inputs() { return MODE == kDfa ? 11 : 5; }
 
 // ---------------------------------------------------------------------------
 // FP32 VALU path
 
-template <int H1, int H2, bool COMP>
+template <int H1, int H2, int MODE>
 __global__ __launch_bounds__(256) void infer_f32_kernel(InferArgs a) {
   const int P = a.W * a.H;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
   const Grids g = load_grids(a.sched, a.W, a.H);
   PixIn in;
-  load_pixel<COMP>(a, g, p, true, in);
+  load_pixel<MODE>(a, g, p, true, in);
   float o0 = 0.f, o1 = 0.f, o2 = 0.f;
   if (in.n >= 3) {
     float h1[H1];
@@ -167,7 +227,7 @@ __global__ __launch_bounds__(256) void infer_f32_kernel(InferArgs a) {
     for (int j = 0; j < H1; ++j) {
       float s = a.b1[j];
 #pragma unroll
-      for (int i = 0; i < 5; ++i) s = fmaf(a.W1[j * a.in + i], in.x[i], s);
+      for (int i = 0; i < n_inputs<MODE>(); ++i) s = fmaf(a.W1[j * a.in + i], in.x[i], s);
       h1[j] = fmaxf(s, 0.0f);
     }
     float h2[H2];
@@ -185,11 +245,11 @@ __global__ __launch_bounds__(256) void infer_f32_kernel(InferArgs a) {
       s1 = fmaf(a.W3[H2 + k], h2[k], s1);
       s2 = fmaf(a.W3[2 * H2 + k], h2[k], s2);
     }
-    o0 = fmaxf(s0, 0.0f);
-    o1 = fmaxf(s1, 0.0f);
-    o2 = fmaxf(s2, 0.0f);
+    o0 = out_act<MODE>(s0);
+    o1 = out_act<MODE>(s1);
+    o2 = out_act<MODE>(s2);
   }
-  store_pixel<COMP>(a, p, in, o0, o1, o2);
+  store_pixel<MODE>(a, p, in, o0, o1, o2);
 }
 
 // ---------------------------------------------------------------------------
@@ -279,7 +339,7 @@ constexpr int kMaxParams = 64 * 16 + 64 + 64 * 64 + 64 + 3 * 64 + 3;
 // A wave step covers 64 pixels: every lane loads its own pixel, the second
 // 32-pixel group's inputs cross to lane half 0 with one xor-32 shuffle, and
 // its outputs cross back the same way.
-template <int T1, int T2, bool FP8, bool COMP>
+template <int T1, int T2, bool FP8, int MODE>
 __global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
   __shared__ float s_w[kMaxParams];
   using V = typename Op<FP8>::vec;
@@ -328,7 +388,7 @@ __global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int k = 8 * half + e;
-      w[e] = (u < a.h1 && k < 5) ? sW1[u * 16 + k] : 0.0f;
+      w[e] = (u < a.h1 && k < n_inputs<MODE>()) ? sW1[u * 16 + k] : 0.0f;
     }
     set8<FP8>(A1[t], w, iw0);
 #pragma unroll
@@ -376,13 +436,14 @@ __global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
   }
   const float b30 = sb3[0], b31 = sb3[1], b32 = sb3[2];
 
-  // the network on one 32-pixel group whose inputs sit in lane half 0
-  auto net = [&](const float xv[5], float& o0, float& o1, float& o2) {
+  // the network on one 32-pixel group; xv holds this lane's half of the
+  // group's K inputs (half 0: inputs 0..7, half 1: inputs 8..15)
+  auto net = [&](const float xv[8], float& o0, float& o1, float& o2) {
     V X;
     {
       float xx[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) xx[e] = (half == 0 && e < 5) ? xv[e] : 0.0f;
+      for (int e = 0; e < 8; ++e) xx[e] = xv[e];
       set8<FP8>(X, xx, ia0);
     }
     V Hb[C2];
@@ -415,9 +476,9 @@ __global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
     f32x16 acc = {};
 #pragma unroll
     for (int c = 0; c < C3; ++c) acc = mfma<FP8>(A3[c], Hb2[c], acc);
-    o0 = fmaxf(fmaf(acc[0], dq2, b30), 0.0f);
-    o1 = fmaxf(fmaf(acc[1], dq2, b31), 0.0f);
-    o2 = fmaxf(fmaf(acc[2], dq2, b32), 0.0f);
+    o0 = out_act<MODE>(fmaf(acc[0], dq2, b30));
+    o1 = out_act<MODE>(fmaf(acc[1], dq2, b31));
+    o2 = out_act<MODE>(fmaf(acc[2], dq2, b32));
   };
 
   // software pipeline: the loads of the wave's next step are in flight while
@@ -425,41 +486,50 @@ __global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
   PixRaw r;
   r.n = 0;
   int pn = wave * 64 + lane;
-  if (wave < nsteps && pn < P) issue_loads<COMP>(a, g, pn, r);
+  if (wave < nsteps && pn < P) issue_loads<MODE>(a, g, pn, r);
   for (int st = wave; st < nsteps; st += nwaves) {
     const int p = pn;
     const bool live = p < P;
-    const PixIn in = blend<COMP>(r);
+    const PixIn in = blend<MODE>(r);
     const int sn = st + nwaves;
     pn = sn * 64 + lane;
     r.n = 0;
-    if (sn < nsteps && pn < P) issue_loads<COMP>(a, g, pn, r);
-    float xs[5], xo[5];
+    if (sn < nsteps && pn < P) issue_loads<MODE>(a, g, pn, r);
+    // group A is the pixels of lanes 0..31, group B those of lanes 32..63; a
+    // group's inputs 0..7 go to half 0 and 8..15 to half 1 of the same
+    // column, so each lane exchanges one half with its xor-32 partner
+    float own[16];
 #pragma unroll
-    for (int e = 0; e < 5; ++e) {
-      xs[e] = (live && in.n >= 3) ? in.x[e] : 0.0f;
-      xo[e] = __shfl_xor(xs[e], 32);  // half 0 receives the second group's inputs
+    for (int e = 0; e < 16; ++e) own[e] = (e < n_inputs<MODE>() && live && in.n >= 3) ? in.x[e < 11 ? e : 0] : 0.0f;
+    float xa[8], xb[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float lo = own[e], hi = own[8 + e];
+      const float lo_x = e < n_inputs<MODE>() ? __shfl_xor(lo, 32) : 0.0f;
+      const float hi_x = 8 + e < n_inputs<MODE>() ? __shfl_xor(hi, 32) : 0.0f;
+      xa[e] = half == 0 ? lo : hi_x;
+      xb[e] = half == 0 ? lo_x : hi;
     }
     float a0, a1, a2, b0, b1, b2;
-    net(xs, a0, a1, a2);   // first group (lanes 0..31)
-    net(xo, b0, b1, b2);   // second group (lanes 32..63), outputs in half 0
+    net(xa, a0, a1, a2);   // group A, outputs in half 0
+    net(xb, b0, b1, b2);   // group B, outputs in half 0
     b0 = __shfl_xor(b0, 32);
     b1 = __shfl_xor(b1, 32);
     b2 = __shfl_xor(b2, 32);
     if (live) {
-      if (half == 0) store_pixel<COMP>(a, p, in, a0, a1, a2);
-      else store_pixel<COMP>(a, p, in, b0, b1, b2);
+      if (half == 0) store_pixel<MODE>(a, p, in, a0, a1, a2);
+      else store_pixel<MODE>(a, p, in, b0, b1, b2);
     }
   }
 }
 
-template <int H1, int H2, bool COMP>
+template <int H1, int H2, int MODE>
 void launch_f32(const InferArgs& a, hipStream_t s) {
   const int P = a.W * a.H;
-  hipLaunchKernelGGL((infer_f32_kernel<H1, H2, COMP>), dim3((P + 255) / 256), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((infer_f32_kernel<H1, H2, MODE>), dim3((P + 255) / 256), dim3(256), 0, s, a);
 }
 
-template <int T1, int T2, bool FP8, bool COMP>
+template <int T1, int T2, bool FP8, int MODE>
 void launch_mfma(const InferArgs& a, hipStream_t s) {
   const int P = a.W * a.H;
   const int steps = (P + 63) / 64;
@@ -467,14 +537,14 @@ void launch_mfma(const InferArgs& a, hipStream_t s) {
   int blocks = (steps + 3) / 4;
   if (blocks > 1024) blocks = 1024;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL((infer_mfma_kernel<T1, T2, FP8, COMP>), dim3(blocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((infer_mfma_kernel<T1, T2, FP8, MODE>), dim3(blocks), dim3(256), 0, s, a);
 }
 
-template <bool COMP>
+template <int MODE>
 int dispatch(const starnt_mlp& m, const InferArgs& a, hipStream_t s) {
   if (m.dtype == STARNT_F32) {
 #define F32CASE(A, B) \
-  if (m.h1 == A && m.h2 == B) { launch_f32<A, B, COMP>(a, s); return STARNT_OK; }
+  if (m.h1 == A && m.h2 == B) { launch_f32<A, B, MODE>(a, s); return STARNT_OK; }
     F32CASE(16, 16) F32CASE(16, 32) F32CASE(32, 16) F32CASE(32, 32) F32CASE(32, 64) F32CASE(64, 32)
     F32CASE(64, 64) F32CASE(16, 64) F32CASE(64, 16)
 #undef F32CASE
@@ -485,7 +555,7 @@ int dispatch(const starnt_mlp& m, const InferArgs& a, hipStream_t s) {
   const int t1 = (m.h1 + 31) / 32, t2 = (m.h2 + 31) / 32;
 #define MCASE(A, B)                                                              \
   if (t1 == A && t2 == B) {                                                      \
-    if (f8) launch_mfma<A, B, true, COMP>(a, s); else launch_mfma<A, B, false, COMP>(a, s); \
+    if (f8) launch_mfma<A, B, true, MODE>(a, s); else launch_mfma<A, B, false, MODE>(a, s); \
     return STARNT_OK;                                                            \
   }
   MCASE(1, 1) MCASE(1, 2) MCASE(2, 1) MCASE(2, 2)
@@ -494,11 +564,13 @@ int dispatch(const starnt_mlp& m, const InferArgs& a, hipStream_t s) {
 }
 
 InferArgs make_args(const starnt_mlp& m, const float* tail, const uint32_t* count, const float* layer1,
-                    const float* layer2, const starnt_sched* sched, int W, int H, const float* bg, float* out) {
+                    const float* layer2, const float* tail_avg, const starnt_sched* sched, int W, int H,
+                    const float* bg, float* out) {
   InferArgs a;
   a.W = W;
   a.H = H;
   a.tail = reinterpret_cast<const float4*>(tail);
+  a.tail_avg = reinterpret_cast<const float4*>(tail_avg);
   a.count = count;
   a.layer1 = reinterpret_cast<const float4*>(layer1);
   a.layer2 = reinterpret_cast<const float4*>(layer2);
@@ -516,12 +588,27 @@ InferArgs make_args(const starnt_mlp& m, const float* tail, const uint32_t* coun
   return a;
 }
 
+// the DFAOIT network input of every pixel, x [P][16] (zero where N < 3)
+__global__ __launch_bounds__(256) void dfa_inputs_kernel(InferArgs a) {
+  const int P = a.W * a.H;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const Grids g = load_grids(a.sched, a.W, a.H);
+  PixIn in;
+  load_pixel<kDfa>(a, g, p, true, in);
+  float4* o = reinterpret_cast<float4*>(a.out) + 4 * (size_t)p;
+  o[0] = make_float4(in.x[0], in.x[1], in.x[2], in.x[3]);
+  o[1] = make_float4(in.x[4], in.x[5], in.x[6], in.x[7]);
+  o[2] = make_float4(in.x[8], in.x[9], in.x[10], 0.0f);
+  o[3] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
 }  // namespace
 
 int launch_infer(const starnt_mlp& m, const float* tail, const uint32_t* count, const starnt_sched* sched,
                  int W, int H, float* out, hipStream_t s) {
-  const InferArgs a = make_args(m, tail, count, nullptr, nullptr, sched, W, H, nullptr, out);
-  const int rc = dispatch<false>(m, a, s);
+  const InferArgs a = make_args(m, tail, count, nullptr, nullptr, nullptr, sched, W, H, nullptr, out);
+  const int rc = dispatch<kTail>(m, a, s);
   if (rc) return fail(rc, "starnt_infer: unsupported dtype / hidden widths");
   STARNT_LAUNCH_CHECK("starnt_infer launch");
   return STARNT_OK;
@@ -529,10 +616,21 @@ int launch_infer(const starnt_mlp& m, const float* tail, const uint32_t* count, 
 
 int launch_infer_composite(const starnt_mlp& m, const starnt_feats& f, const starnt_sched* sched,
                            const float bg[3], float* rgb, hipStream_t s) {
-  const InferArgs a = make_args(m, f.tail, f.count, f.layer1, f.layer2, sched, f.width, f.height, bg, rgb);
-  const int rc = dispatch<true>(m, a, s);
+  const InferArgs a = make_args(m, f.tail, f.count, f.layer1, f.layer2, f.tail_avg, sched, f.width, f.height, bg,
+                                rgb);
+  const int rc = m.variant == STARNT_NET_DFAOIT ? dispatch<kDfa>(m, a, s) : dispatch<kComp>(m, a, s);
   if (rc) return fail(rc, "starnt_infer_composite: unsupported dtype / hidden widths");
   STARNT_LAUNCH_CHECK("starnt_infer_composite launch");
+  return STARNT_OK;
+}
+
+int launch_dfa_inputs(const starnt_feats& f, const starnt_sched* sched, float* x, hipStream_t s) {
+  starnt_mlp none{};
+  const InferArgs a = make_args(none, f.tail, f.count, f.layer1, f.layer2, f.tail_avg, sched, f.width, f.height,
+                                nullptr, x);
+  const int P = f.width * f.height;
+  hipLaunchKernelGGL(dfa_inputs_kernel, dim3((P + 255) / 256), dim3(256), 0, s, a);
+  STARNT_LAUNCH_CHECK("starnt_dfa_inputs launch");
   return STARNT_OK;
 }
 

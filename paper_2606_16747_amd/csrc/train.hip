@@ -29,6 +29,7 @@ struct TrainArgs {
   float* partial_loss;  // [nblocks]
   int nparam;
   float inv_count;      // 1 / (batch * 3)
+  int out_act;          // 0 ReLU, 1 logistic sigmoid
 };
 
 template <bool BF>
@@ -87,10 +88,11 @@ __global__ __launch_bounds__(256) void train_fwd_bwd(TrainArgs a) {
     if (s < ns) {
       float z = b3[o];
       for (int k = 0; k < H2; ++k) z = fmaf(q<BF>(W3[o * H2 + k]), s_h2[s][k], z);
-      const float f = fmaxf(z, 0.0f);
+      const float f = a.out_act ? 1.0f / (1.0f + expf(-z)) : fmaxf(z, 0.0f);
       const float e = f - a.y[(size_t)(s0 + s) * 3 + o];
       lsum = fmaf(e * e, a.inv_count, lsum);
-      d = z > 0.0f ? 2.0f * e * a.inv_count : 0.0f;
+      const float df = a.out_act ? f * (1.0f - f) : (z > 0.0f ? 1.0f : 0.0f);
+      d = 2.0f * e * a.inv_count * df;
     }
     s_d3[s][o] = q<BF>(d);
   }
@@ -230,6 +232,7 @@ int launch_train(const starnt_train& tr, const float* x, const float* y, int bat
   t.partial_loss = reinterpret_cast<float*>(static_cast<char*>(ws) + align256((size_t)nb * np * 4));
   t.nparam = np;
   t.inv_count = (float)(1.0 / (3.0 * (double)batch));
+  t.out_act = tr.out_act;
   const bool bf = tr.dtype == STARNT_BF16;
   bool ok = true;
 #define TCASE(A, B)                                                        \

@@ -2,7 +2,9 @@
 
 Pairs (x, f*) come from the library itself: starnt_features gives the five
 features at full resolution and the exact A-buffer path gives the exact tail
-colour f* of every pixel with at least three fragments. Inputs are
+colour f* of every pixel with at least three fragments. For the DFAOIT
+network the input is starnt_dfa_inputs and the target the whole transparent
+colour C_t (the exact composite over a black background). Inputs are
 standardised for training; the affine map is folded into layer 1 afterwards,
 so inference sees raw features. Every gradient step is starnt_train_step.
 """
@@ -11,8 +13,8 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import (BF16, F32, WS_TRAIN, Adam, DeviceFrags, DeviceMlp, FeatBuffers, Train, starnt_features,
-               starnt_train_step, starnt_workspace_size, workspace)
+from . import (BF16, F32, NET_DFAOIT, WS_TRAIN, Adam, DeviceFrags, DeviceMlp, FeatBuffers, Train,
+               starnt_dfa_inputs, starnt_features, starnt_train_step, starnt_workspace_size, workspace)
 from .frames import exact_frame
 
 
@@ -32,12 +34,27 @@ def pairs_from(frags: DeviceFrags, bg=(1.0, 1.0, 1.0)):
     return x, fstar.cpu().numpy()[keep]
 
 
+def dfa_pairs_from(frags: DeviceFrags):
+    """(x [M, 16], C_t [M, 3]) on the host for the pixels with N >= 3: the
+    DFAOIT input and the exact transparent colour without background."""
+    fb = FeatBuffers(frags.width, frags.height, with_avg=True)
+    starnt_features(frags, None, fb)
+    P = frags.width * frags.height
+    x = torch.empty(P, 16, dtype=torch.float32, device=fb.d1.device)
+    starnt_dfa_inputs(fb, None, x)
+    ct = torch.empty(P, 3, dtype=torch.float32, device=fb.d1.device)
+    exact_frame(frags, ct, (0.0, 0.0, 0.0))
+    torch.cuda.synchronize()
+    keep = fb.count.cpu().numpy() >= 3
+    return x.cpu().numpy()[keep], ct.cpu().numpy()[keep]
+
+
 class Standardiser:
-    def __init__(self, x):
+    def __init__(self, x, n_in=5):
         self.mu = np.zeros(16)
         self.sd = np.ones(16)
-        self.mu[:5] = x[:, :5].mean(0)
-        self.sd[:5] = np.maximum(x[:, :5].std(0), 1e-6)
+        self.mu[:n_in] = x[:, :n_in].mean(0)
+        self.sd[:n_in] = np.maximum(x[:, :n_in].std(0), 1e-6)
 
     def apply(self, x):
         return ((x - self.mu) / self.sd).astype(np.float32)
@@ -50,11 +67,13 @@ class Standardiser:
 
 
 def train(x, y, Ws, bs, steps=3000, batch=65536, lr=2e-3, lr_min=1e-4, dtype=BF16, seed=0, log_every=0,
-          device="cuda", stream=None):
+          device="cuda", stream=None, variant=0):
     """Train from initial weights (Ws, bs); returns (Ws, bs, losses) with the
-    standardisation folded into layer 1."""
+    standardisation folded into layer 1. variant NET_DFAOIT trains the
+    sigmoid-output network on its eleven inputs."""
     dims = (Ws[0].shape[1], Ws[0].shape[0], Ws[1].shape[0], Ws[2].shape[0])
-    st = Standardiser(x)
+    dfa = variant == NET_DFAOIT
+    st = Standardiser(x, 11 if dfa else 5)
     rng = np.random.default_rng(seed)
     order = rng.permutation(len(x))
     xs = torch.from_numpy(st.apply(x[order])).to(device)
@@ -68,7 +87,8 @@ def train(x, y, Ws, bs, steps=3000, batch=65536, lr=2e-3, lr_min=1e-4, dtype=BF1
     m = torch.zeros_like(p)
     v = torch.zeros_like(p)
     g = torch.zeros_like(p)
-    tr = Train(16, dims[1], dims[2], 3, dtype, p.data_ptr(), m.data_ptr(), v.data_ptr(), g.data_ptr())
+    tr = Train(16, dims[1], dims[2], 3, dtype, p.data_ptr(), m.data_ptr(), v.data_ptr(), g.data_ptr(),
+               1 if dfa else 0)
     ws = workspace(starnt_workspace_size(WS_TRAIN, batch, dims[1], dims[2]), device)
     loss = torch.zeros(steps, dtype=torch.float32, device=device)
     for t in range(steps):

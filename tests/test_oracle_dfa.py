@@ -83,3 +83,21 @@ def test_dfa_composite_with_the_exact_colour_is_exact(oracle_mod):
     Ct = oracle_mod.frame(*csr, 9, 9, bg=(0.0, 0.0, 0.0), want=("rgb",))["rgb"]
     out = oracle_mod.dfa_composite(o["lay"], o["tail"], Ct, bg)
     np.testing.assert_allclose(out, o["rgb"], rtol=0, atol=1e-13)
+
+
+def test_dfa_mixed_resolution_reduces_to_full_resolution(oracle_mod, sg):
+    """At s = 1 the upscale is the identity: the mixed-resolution DFAOIT path
+    equals dfa_features and dfa_composite at full resolution."""
+    fr = sg.Scene("c1_256", width=48, height=40, num_tris=30).frame(0)
+    o = oracle_mod.frame_of(fr, want=("rgb", "lay", "tail", "tavg"))
+    Ws, bs = sg.init_mlp((16, 8, 8, 3), seed=4, out_bias=0.1)
+    m = oracle_mod.Mlp(Ws, bs, act=1)
+    W, H = fr.width, fr.height
+    rgb, x, f = oracle_mod.dfa_learned(o["lay"], o["tail"], o["tavg"], W, H, (W, H, W, H), m, bg=(0.5, 0.5, 0.5))
+    x0 = oracle_mod.dfa_features(o["lay"], o["tail"], o["tavg"])
+    t = o["lay"][:, 0] >= 3
+    np.testing.assert_allclose(x[t], x0[t], rtol=0, atol=1e-12)
+    assert np.all(x[~t] == 0)
+    f0 = m.forward(x0)
+    want = oracle_mod.dfa_composite(o["lay"], o["tail"], f0, (0.5, 0.5, 0.5))
+    np.testing.assert_allclose(rgb, want, rtol=0, atol=1e-12)

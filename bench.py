@@ -228,6 +228,7 @@ def main():
     ap.add_argument("--train-steps", type=int, default=8000)
     ap.add_argument("--train-scenes", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the ten-feature DFAOIT comparison")
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of single-threaded oracle work for the cpu_baseline sample")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -270,12 +271,17 @@ def main():
     # 512x512 scene recipe): material diversity is what makes it generalise
     dims = (16, 32, 32, 3)
     Ws0, bs0 = sg.init_mlp(dims, seed=sg.BASE_SEED + 100, out_bias=0.05)
-    xs, ys = [], []
+    xs, ys, dxs, dys = [], [], [], []
     for k in range(args.train_scenes):
         tf = sg.Scene("c3_512", seed=sg.BASE_SEED + 3 + 1000 * (k + 1), width=256, height=256).frame(0)
-        x, y = learn.pairs_from(st.DeviceFrags.from_frame(tf, max_per_pixel=128), bg)
+        tdf = st.DeviceFrags.from_frame(tf, max_per_pixel=128)
+        x, y = learn.pairs_from(tdf, bg)
         xs.append(x)
         ys.append(y)
+        if not args.no_ablation:
+            x, y = learn.dfa_pairs_from(tdf)
+            dxs.append(x)
+            dys.append(y)
     x = np.concatenate(xs)
     y = np.concatenate(ys)
     if len(x) > 8_000_000:
@@ -287,6 +293,18 @@ def main():
     train_s = time.perf_counter() - tt
     log("trained %d steps in %.2f s, loss %.3e -> %.3e" % (args.train_steps, train_s, losses[0], losses[-1]))
     mlp = st.DeviceMlp(Ws, bs, st.BF16)
+    dfa_mlp = None
+    if not args.no_ablation:
+        # the ten-feature DFAOIT network, same shape, pairs budget and steps
+        x, y = np.concatenate(dxs), np.concatenate(dys)
+        if len(x) > 8_000_000:
+            pick = np.random.default_rng(0).choice(len(x), 8_000_000, replace=False)
+            x, y = x[pick], y[pick]
+        dWs, dbs, dlosses = learn.train(x, y, Ws0, bs0, steps=args.train_steps, batch=65536, dtype=st.BF16,
+                                        variant=st.NET_DFAOIT)
+        dfa_mlp = st.DeviceMlp(dWs, dbs, st.BF16, variant=st.NET_DFAOIT)
+        log("DFAOIT network trained, loss %.3e -> %.3e" % (dlosses[0], dlosses[-1]))
+        del dxs, dys
 
     # ---- exact references -------------------------------------------------
     exact = [torch.empty(P, 3, dtype=torch.float32, device=dev) for _ in range(NF)]
@@ -487,6 +505,47 @@ def main():
         d = (outs[t] - exact[t]).double()
         plain_psnr.append(10 * np.log10(1.0 / float((d * d).mean())))
 
+    # ten-versus-five-feature ablation at full resolution (every frame real):
+    # quality against the exact composite and the cost of the network pass
+    ablation = None
+    if dfa_mlp is not None:
+        fbd = st.FeatBuffers(W, H, with_avg=True)
+        dpsnr = []
+        for t in range(NF):
+            st.starnt_features(frags[t], None, fbd)
+            st.starnt_infer_composite(dfa_mlp, fbd, None, bg, outs[t])
+            torch.cuda.synchronize()
+            d = (outs[t] - exact[t]).double()
+            dpsnr.append(10 * np.log10(1.0 / float((d * d).mean())))
+        st.starnt_features(frags[0], None, fbd)
+        torch.cuda.synchronize()
+
+        def time_us(fn, n=20):
+            fn()
+            torch.cuda.synchronize()
+            a0 = torch.cuda.Event(enable_timing=True)
+            a1 = torch.cuda.Event(enable_timing=True)
+            a0.record()
+            for _ in range(n):
+                fn()
+            a1.record()
+            torch.cuda.synchronize()
+            return a0.elapsed_time(a1) / n * 1e3
+
+        ablation = {
+            "psnr_db_fullres_mean": {"starnt_5_features": round(float(np.mean(plain_psnr)), 2),
+                                     "dfaoit_10_features": round(float(np.mean(dpsnr)), 2)},
+            "infer_composite_us_fullres_bf16": {
+                "starnt_5_features": round(time_us(lambda: st.starnt_infer_composite(mlp, fbd, None, bg, outs[0])), 2),
+                "dfaoit_10_features": round(time_us(lambda: st.starnt_infer_composite(dfa_mlp, fbd, None, bg,
+                                                                                      outs[0])), 2)},
+            "features_us_fullres": {
+                "without_tail_means": round(time_us(lambda: st.starnt_features(frags[0], None, rend.feats)), 2),
+                "with_tail_means": round(time_us(lambda: st.starnt_features(frags[0], None, fbd)), 2)},
+            "network": "16-32-32-3 BF16, same pairs budget and steps; DFAOIT predicts the whole colour (sigmoid)",
+        }
+        log("ablation %s" % ablation)
+
     if args.calib_copy_mb:
         src_t = torch.ones(args.calib_copy_mb * (1 << 20) // 4, dtype=torch.float32, device=dev)
         dst_t = torch.empty_like(src_t)
@@ -571,6 +630,7 @@ def main():
         "fp32_mlp_ms_per_frame": round(fp32_step_ms / NF, 4),
         "plain_fullres_ms_per_frame": round(plain_step_ms / NF, 4),
         "plain_fullres_psnr_db_mean": round(float(np.mean(plain_psnr)), 2),
+        "ablation_10_vs_5_features": ablation,
         "train": {"steps": args.train_steps, "batch": 65536, "pairs": int(len(x)), "seconds": round(train_s, 3),
                   "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
                   "step_us_16_64_64_3_bf16": round(train_step_us, 1),

@@ -172,3 +172,33 @@ def test_ablation_ten_versus_five_features(starnt, gpu, sg, capsys):
                                                                   nets["dfaoit"][2][-20:].mean()))
     assert m["starnt"] > m["f0"] + 10.0
     assert m["dfaoit"] > m["f0"] + 5.0
+
+
+def test_dfa_composite_fp8_against_same_operands(starnt, gpu, sg, oracle_mod):
+    """FP8 (E4M3, per-layer scales) DFAOIT composite against the oracle on
+    e4m3-rounded operands; the bar of the other FP8 tests (one e4m3 step per
+    rounding flip), relative to the colour."""
+    fr = sg.Scene("c1_256").frame(0)
+    W, H = fr.width, fr.height
+    df, fb, sched = _run(starnt, fr, 1.0, 1.0)
+    o = oracle_mod.frame_of(fr, want=("lay", "tail", "tavg"))
+    x = oracle_mod.dfa_features(o["lay"], o["tail"], o["tavg"])
+    tailed = o["lay"][:, 0] >= 3
+    Ws, bs = sg.init_mlp((16, 32, 32, 3), seed=64, out_bias=0.0)
+    sa, sw = [], []
+    h = x[tailed]
+    for w, b in zip(Ws, bs):
+        sa.append(float(np.abs(h).max()) / 448.0)
+        sw.append(float(np.abs(w).max()) / 448.0)
+        h = np.maximum(h @ w.T.astype(np.float64) + b, 0.0)
+    mlp = starnt.DeviceMlp(Ws, bs, starnt.FP8, fp8_scales=[v for pair in zip(sa, sw) for v in pair],
+                           variant=starnt.NET_DFAOIT)
+    rgb = torch.empty(W * H, 3, dtype=torch.float32, device="cuda")
+    starnt.starnt_infer_composite(mlp, fb, None, (1, 1, 1), rgb)
+    sync()
+    f = np.zeros((W * H, 3))
+    f[tailed] = oracle_mod.Mlp(Ws, bs, act=1).forward_q(x[tailed], 2, np.array(sa), np.array(sw))
+    want = oracle_mod.dfa_composite(o["lay"], o["tail"], f, (1, 1, 1))
+    err = np.abs(to_np(rgb) - want).max(axis=1)
+    assert np.mean(err <= 2e-3) >= 0.99, np.mean(err <= 2e-3)
+    assert (err <= 0.25 * (np.abs(want).max(axis=1) + 0.1)).all(), err.max()

@@ -505,6 +505,36 @@ def main():
         d = (outs[t] - exact[t]).double()
         plain_psnr.append(10 * np.log10(1.0 / float((d * d).mean())))
 
+    # spatially selective inference: the same sequence with the network only
+    # off the flat leaves of the last real frame's quadtree
+    selr = fm.Renderer(W, H, mlp, base=64, bg=bg, selective=True)
+
+    def sel_step():
+        selr.reset()
+        for t in range(NF):
+            if t % 2 == 0:
+                selr.real_frame(frags[t], outs[t])
+            else:
+                selr.interpolated_frame(mmis[t], outs[t])
+
+    for _ in range(2):
+        sel_step()
+    torch.cuda.synchronize()
+    q0 = torch.cuda.Event(enable_timing=True)
+    q1 = torch.cuda.Event(enable_timing=True)
+    q0.record()
+    for _ in range(max(3, args.steps // 4)):
+        sel_step()
+    q1.record()
+    torch.cuda.synchronize()
+    sel_step_ms = q0.elapsed_time(q1) / max(3, args.steps // 4)
+    sel_step()
+    torch.cuda.synchronize()
+    sel_psnr = []
+    for t in range(NF):
+        d = (outs[t] - exact[t]).double()
+        sel_psnr.append(10 * np.log10(1.0 / float((d * d).mean())))
+
     # ten-versus-five-feature ablation at full resolution (every frame real):
     # quality against the exact composite and the cost of the network pass
     ablation = None
@@ -631,6 +661,9 @@ def main():
         "plain_fullres_ms_per_frame": round(plain_step_ms / NF, 4),
         "plain_fullres_psnr_db_mean": round(float(np.mean(plain_psnr)), 2),
         "ablation_10_vs_5_features": ablation,
+        "selective_inference": {"ms_per_frame": round(sel_step_ms / NF, 4),
+                                "psnr_db_mean": round(float(np.mean(sel_psnr)), 2),
+                                "psnr_db_real_frames": round(float(np.mean(sel_psnr[0::2])), 2)},
         "train": {"steps": args.train_steps, "batch": 65536, "pairs": int(len(x)), "seconds": round(train_s, 3),
                   "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
                   "step_us_16_64_64_3_bf16": round(train_step_us, 1),

@@ -207,6 +207,17 @@ int starnt_infer(const starnt_mlp* mlp, const float* tail, const uint32_t* count
 int starnt_infer_composite(const starnt_mlp* mlp, const starnt_feats* feats, const starnt_sched* sched,
                            const float* bg, float* rgb, void* stream);
 
+/* Spatially selective inference (future work of the paper, Sec. 5):
+ * starnt_infer_composite with a STARNT_NET_STARNT network, except that pixels
+ * in a level-0 (flat) leaf of `level` take the order-free tail estimate
+ * f = f_avg = Ct (1 - t_tail) instead of the network, and a 64-pixel step
+ * whose pixels all have that, or no tail, skips the network. level
+ * [Cw * Ch] is a quadtree leaf-level map (starnt_quadtree, base tile `base`
+ * px, cells of base / 8 px, Cw = ceil(W / (base / 8))), normally the last
+ * real frame's. */
+int starnt_infer_composite_sel(const starnt_mlp* mlp, const starnt_feats* feats, const starnt_sched* sched,
+                               const uint8_t* level, int32_t base, const float* bg, float* rgb, void* stream);
+
 /* The DFAOIT network input of every pixel (Sec. 3.3), x [P][16] float, zero
  * where count < 3: (exact two-layer colour a1 c1 + (1 - a1) a2 c2, tail mean
  * colour, tail mean opacity, tail accumulated colour S = Ct A, N, 0 x 5), with

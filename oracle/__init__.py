@@ -546,3 +546,17 @@ def dfa_learned(lay, tail, tavg, width, height, grids, mlp, bg=(1.0, 1.0, 1.0)):
     Ct = np.where(tailed[:, None], f, exact2)
     rgb = Ct + (1.0 - a1) * (1.0 - a2) * tt * np.asarray(bg, np.float64)[None, :]
     return rgb, x, f
+
+
+def selective(lay, tail, width, height, grids, mlp, level, base, bg=(1.0, 1.0, 1.0)):
+    """Spatially selective inference: the learned composite (eq (3)), except
+    that pixels whose quadtree cell (base / 8 px) is a level-0 leaf use the
+    order-free tail f_avg. eq (3) is the same in both; only f differs."""
+    W, H = int(width), int(height)
+    rgb_l, _, _ = learned(lay, tail, W, H, grids, mlp, MODE_LEARNED, bg)
+    rgb_a, _, _ = learned(lay, tail, W, H, grids, None, MODE_FAVG, bg)
+    cs = int(base) // 8
+    Cw = (W + cs - 1) // cs
+    ys, xs = np.divmod(np.arange(W * H), W)
+    flat = np.asarray(level).ravel()[(ys // cs) * Cw + xs // cs] == 0
+    return np.where(flat[:, None], rgb_a, rgb_l)

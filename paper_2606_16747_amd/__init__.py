@@ -84,7 +84,7 @@ class Interval(ctypes.Structure):
 assert ctypes.sizeof(Sched) == 64
 
 EXPORTS = ("starnt_features", "starnt_infer", "starnt_infer_composite", "starnt_composite", "starnt_baseline",
-           "starnt_dfa_inputs",
+           "starnt_dfa_inputs", "starnt_infer_composite_sel",
            "starnt_quadtree", "starnt_reproject", "starnt_interval_init", "starnt_interval_next",
            "starnt_interval_report",
            "starnt_train_step", "starnt_sched_init", "starnt_wbar", "starnt_pass_scales", "starnt_grid_dim",
@@ -102,6 +102,8 @@ def _load():
     lib.starnt_composite.argtypes = [ctypes.POINTER(Frags), ctypes.POINTER(Feats), _P, _P,
                                      ctypes.POINTER(ctypes.c_float), ctypes.c_int32, _P, _P, _P]
     lib.starnt_dfa_inputs.argtypes = [ctypes.POINTER(Feats), _P, _P, _P]
+    lib.starnt_infer_composite_sel.argtypes = [ctypes.POINTER(Mlp), ctypes.POINTER(Feats), _P, _P, ctypes.c_int32,
+                                               ctypes.POINTER(ctypes.c_float), _P, _P]
     lib.starnt_baseline.argtypes = [ctypes.POINTER(Frags), ctypes.c_int32, ctypes.POINTER(ctypes.c_float), _P, _P]
     lib.starnt_interval_init.argtypes = [ctypes.POINTER(Interval), ctypes.c_double, ctypes.c_int32, ctypes.c_double]
     lib.starnt_interval_next.argtypes = [ctypes.POINTER(Interval)]
@@ -280,6 +282,12 @@ def starnt_composite(frags, feats, tail_rgb, sched, bg, mode, rgb, fstar=None, s
     _check(lib.starnt_composite(ctypes.byref(frags._c) if frags is not None else None,
                                 ctypes.byref(feats._c) if feats is not None else None, _ptr(tail_rgb), _ptr(sched),
                                 bgc, int(mode), _ptr(rgb), _ptr(fstar), _stream(stream)))
+
+
+def starnt_infer_composite_sel(mlp: DeviceMlp, feats: FeatBuffers, sched, level, base, bg, rgb, stream=None):
+    bgc = (ctypes.c_float * 3)(*[float(v) for v in bg])
+    _check(lib.starnt_infer_composite_sel(ctypes.byref(mlp._c), ctypes.byref(feats._c), _ptr(sched), _ptr(level),
+                                          int(base), bgc, _ptr(rgb), _stream(stream)))
 
 
 def starnt_dfa_inputs(feats: FeatBuffers, sched, x, stream=None):

@@ -112,6 +112,22 @@ int starnt_infer_composite(const starnt_mlp* mlp, const starnt_feats* feats, con
   return launch_infer_composite(*mlp, *feats, sched, bg, rgb, as_stream(stream));
 }
 
+int starnt_infer_composite_sel(const starnt_mlp* mlp, const starnt_feats* feats, const starnt_sched* sched,
+                               const uint8_t* level, int32_t base, const float* bg, float* rgb, void* stream) {
+  if (!feats) return fail(STARNT_EINVAL, "starnt_infer_composite_sel: NULL feats");
+  int rc = check_frame(feats->width, feats->height, "starnt_infer_composite_sel");
+  if (rc) return rc;
+  if (!bg || !rgb || !level || !feats->layer1 || !feats->count || !feats->layer2 || !feats->tail)
+    return fail(STARNT_EINVAL, "starnt_infer_composite_sel: NULL argument");
+  if (base < 8 || base % 8 || base > 4096)
+    return fail(STARNT_EINVAL, "starnt_infer_composite_sel: base must be a multiple of 8 in [8, 4096]");
+  rc = check_mlp(mlp, "starnt_infer_composite_sel");
+  if (rc) return rc;
+  if (mlp->variant != STARNT_NET_STARNT)
+    return fail(STARNT_EINVAL, "starnt_infer_composite_sel: STAR-NT networks only");
+  return launch_infer_composite_sel(*mlp, *feats, sched, level, base, bg, rgb, as_stream(stream));
+}
+
 int starnt_dfa_inputs(const starnt_feats* feats, const starnt_sched* sched, float* x, void* stream) {
   if (!feats) return fail(STARNT_EINVAL, "starnt_dfa_inputs: NULL feats");
   int rc = check_frame(feats->width, feats->height, "starnt_dfa_inputs");

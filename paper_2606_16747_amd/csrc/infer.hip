@@ -28,12 +28,14 @@ namespace {
 
 // what a kernel produces: the tail colour (starnt_infer), the eq (3)
 // composite with it, or the DFAOIT composite (eq (2))
-constexpr int kTail = 0, kComp = 1, kDfa = 2;
+constexpr int kTail = 0, kComp = 1, kDfa = 2, kSel = 3;  // kSel: kComp, network only off flat cells
 
 struct InferArgs {
   int W, H;
   const float4* tail;
   const float4* tail_avg;  // tail means (DFAOIT only)
+  const uint8_t* level;    // leaf level per quadtree cell (selective only)
+  int cs, Cw;              // cell side in pixels, cells per row
   const uint32_t* count;
   const float4* layer1;
   const float4* layer2;
@@ -58,6 +60,7 @@ struct PixIn {
   float4 l1;           // layer 1 (composite only)
   float4 l2;           // upscaled layer 2 (composite only)
   float e0, e1, e2;    // exact two-layer colour (DFAOIT only)
+  bool flat;           // in a level-0 quadtree leaf (selective only)
 };
 
 __device__ __forceinline__ float lerp1(float p, float q, float w) { return fmaf(w, q - p, p); }
@@ -75,6 +78,7 @@ struct PixRaw {
   float4 l1;
   float4 l2[4];  // the four pass-2 taps
   float wx3, wy3, wx2, wy2;
+  uint32_t lvl;  // leaf level of the pixel's quadtree cell (selective only)
 };
 
 template <int MODE>
@@ -99,6 +103,7 @@ __device__ __forceinline__ void issue_loads(const InferArgs& a, const Grids& g, 
   }
   r.wx3 = tx.w1;
   r.wy3 = ty.w1;
+  if constexpr (MODE == kSel) r.lvl = a.level[(y / a.cs) * a.Cw + x / a.cs];
   if constexpr (MODE >= kComp) {
     r.l1 = a.layer1[p];
     const Taps ux = axis_taps(x, a.W, g.w2), uy = axis_taps(y, a.H, g.h2);
@@ -121,6 +126,7 @@ template <int MODE>
 __device__ __forceinline__ PixIn blend(const PixRaw& r) {
   PixIn in;
   in.n = r.n;
+  in.flat = MODE == kSel && r.lvl == 0;
 #pragma unroll
   for (int e = 0; e < 11; ++e) in.x[e] = 0.0f;
   in.tt = 1.0f;
@@ -182,7 +188,16 @@ __device__ __forceinline__ void store_pixel(const InferArgs& a, int p, const Pix
     o[2] = fmaf(T, a.bg2, on ? f2 : in.e2);
   } else {
     if (!on) { f0 = f1 = f2 = 0.0f; }
-    if constexpr (MODE == kComp) {
+    if constexpr (MODE == kSel) {
+      // flat cells take the order-free tail estimate f_avg = Ct (1 - t_tail)
+      if (in.flat) {
+        const float w = 1.0f - in.tt;
+        f0 = on ? in.x[2] * w : 0.0f;
+        f1 = on ? in.x[3] * w : 0.0f;
+        f2 = on ? in.x[4] * w : 0.0f;
+      }
+    }
+    if constexpr (MODE == kComp || MODE == kSel) {
       const float tt = on ? in.tt : 1.0f;
       const float om1 = 1.0f - in.l1.w;
       const float T2 = om1 * (1.0f - in.l2.w);
@@ -221,7 +236,7 @@ __global__ __launch_bounds__(256) void infer_f32_kernel(InferArgs a) {
   PixIn in;
   load_pixel<MODE>(a, g, p, true, in);
   float o0 = 0.f, o1 = 0.f, o2 = 0.f;
-  if (in.n >= 3) {
+  if (in.n >= 3 && !in.flat) {
     float h1[H1];
 #pragma unroll
     for (int j = 0; j < H1; ++j) {
@@ -498,9 +513,10 @@ __global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
     // group A is the pixels of lanes 0..31, group B those of lanes 32..63; a
     // group's inputs 0..7 go to half 0 and 8..15 to half 1 of the same
     // column, so each lane exchanges one half with its xor-32 partner
+    const bool need = live && in.n >= 3 && !in.flat;
     float own[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) own[e] = (e < n_inputs<MODE>() && live && in.n >= 3) ? in.x[e < 11 ? e : 0] : 0.0f;
+    for (int e = 0; e < 16; ++e) own[e] = (e < n_inputs<MODE>() && need) ? in.x[e < 11 ? e : 0] : 0.0f;
     float xa[8], xb[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -510,9 +526,12 @@ __global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
       xa[e] = half == 0 ? lo : hi_x;
       xb[e] = half == 0 ? lo_x : hi;
     }
-    float a0, a1, a2, b0, b1, b2;
-    net(xa, a0, a1, a2);   // group A, outputs in half 0
-    net(xb, b0, b1, b2);   // group B, outputs in half 0
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, b0 = 0.f, b1 = 0.f, b2 = 0.f;
+    // (selective: a step with no pixel off the flat cells skips the network)
+    if (MODE != kSel || __builtin_amdgcn_ballot_w64(need) != 0) {
+      net(xa, a0, a1, a2);   // group A, outputs in half 0
+      net(xb, b0, b1, b2);   // group B, outputs in half 0
+    }
     b0 = __shfl_xor(b0, 32);
     b1 = __shfl_xor(b1, 32);
     b2 = __shfl_xor(b2, 32);
@@ -571,6 +590,9 @@ InferArgs make_args(const starnt_mlp& m, const float* tail, const uint32_t* coun
   a.H = H;
   a.tail = reinterpret_cast<const float4*>(tail);
   a.tail_avg = reinterpret_cast<const float4*>(tail_avg);
+  a.level = nullptr;
+  a.cs = 8;
+  a.Cw = 1;
   a.count = count;
   a.layer1 = reinterpret_cast<const float4*>(layer1);
   a.layer2 = reinterpret_cast<const float4*>(layer2);
@@ -621,6 +643,18 @@ int launch_infer_composite(const starnt_mlp& m, const starnt_feats& f, const sta
   const int rc = m.variant == STARNT_NET_DFAOIT ? dispatch<kDfa>(m, a, s) : dispatch<kComp>(m, a, s);
   if (rc) return fail(rc, "starnt_infer_composite: unsupported dtype / hidden widths");
   STARNT_LAUNCH_CHECK("starnt_infer_composite launch");
+  return STARNT_OK;
+}
+
+int launch_infer_composite_sel(const starnt_mlp& m, const starnt_feats& f, const starnt_sched* sched,
+                               const uint8_t* level, int base, const float bg[3], float* rgb, hipStream_t s) {
+  InferArgs a = make_args(m, f.tail, f.count, f.layer1, f.layer2, nullptr, sched, f.width, f.height, bg, rgb);
+  a.level = level;
+  a.cs = base / 8;
+  a.Cw = (f.width + a.cs - 1) / a.cs;
+  const int rc = dispatch<kSel>(m, a, s);
+  if (rc) return fail(rc, "starnt_infer_composite_sel: unsupported dtype / hidden widths");
+  STARNT_LAUNCH_CHECK("starnt_infer_composite_sel launch");
   return STARNT_OK;
 }
 

@@ -113,6 +113,8 @@ __device__ __forceinline__ float4 load_rgba(const void* rgba, uint32_t k) {
 int launch_features(const starnt_frags& f, const starnt_sched* sched, const starnt_feats& o, hipStream_t s);
 int launch_exact(const starnt_frags& f, const float bg[3], float* rgb, float* fstar, uint32_t* err,
                  hipStream_t s);
+int launch_infer_composite_sel(const starnt_mlp& m, const starnt_feats& f, const starnt_sched* sched,
+                               const uint8_t* level, int base, const float bg[3], float* rgb, hipStream_t s);
 int launch_dfa_inputs(const starnt_feats& f, const starnt_sched* sched, float* x, hipStream_t s);
 int launch_baseline(const starnt_frags& f, int32_t method, const float bg[3], float* rgb, hipStream_t s);
 int launch_composite(const starnt_feats& o, const float* tail_rgb, const starnt_sched* sched, int W, int H,

@@ -12,7 +12,8 @@ import numpy as np
 import torch
 
 from . import (MODE_EXACT, MODE_LEARNED, WS_QUADTREE, DeviceFrags, DeviceMlp, FeatBuffers, QtParams,
-               starnt_composite, starnt_features, starnt_infer_composite, starnt_interval_init,
+               starnt_composite, starnt_features, starnt_infer_composite, starnt_infer_composite_sel,
+               starnt_interval_init,
                starnt_interval_next, starnt_interval_report, starnt_quadtree, starnt_reproject, starnt_sched_init,
                starnt_workspace_size, workspace)
 
@@ -24,10 +25,13 @@ def m_minus_i(vp_real, vp_cur):
 
 
 class Renderer:
-    """Buffers and calls for one frame size. Outputs are [P, 3] float32."""
+    """Buffers and calls for one frame size. Outputs are [P, 3] float32.
+    With selective=True a real frame after the first runs the network only
+    off the flat (level-0) leaves of the last real frame's quadtree."""
 
     def __init__(self, width, height, mlp: DeviceMlp, base=64, tau_split=0.10, tau_merge=0.05, k_relax=2,
-                 bg=(1.0, 1.0, 1.0), device="cuda", mode=MODE_LEARNED):
+                 bg=(1.0, 1.0, 1.0), device="cuda", mode=MODE_LEARNED, selective=False):
+        self.selective = bool(selective)
         self.W, self.H = int(width), int(height)
         P = self.W * self.H
         self.mlp = mlp
@@ -60,7 +64,10 @@ class Renderer:
 
     def real_frame(self, frags: DeviceFrags, out, stream=None):
         self._call("features", lambda: starnt_features(frags, self.sched, self.feats, stream))
-        if self.mode == MODE_LEARNED:
+        if self.mode == MODE_LEARNED and self.selective and self.n_real > 0:
+            self._call("infer_composite", lambda: starnt_infer_composite_sel(
+                self.mlp, self.feats, self.sched, self.level, self.qp.base, self.bg, out, stream))
+        elif self.mode == MODE_LEARNED:
             self._call("infer_composite", lambda: starnt_infer_composite(self.mlp, self.feats, self.sched, self.bg,
                                                                          out, stream))
         else:

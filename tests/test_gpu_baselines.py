@@ -83,3 +83,34 @@ def test_over_list_on_sorted_lists_matches_exact_path(starnt, gpu, sg):
     starnt.starnt_composite(df, None, None, None, BG, starnt.MODE_EXACT, ex)
     sync()
     np.testing.assert_allclose(got, to_np(ex), rtol=0, atol=TOL)
+
+
+@pytest.mark.parametrize("s2,s3", [(1.0, 1.0), (0.5, 0.31)])
+def test_selective_inference_against_oracle(starnt, gpu, sg, oracle_mod, s2, s3):
+    """Flat quadtree cells take f_avg, the rest the network (FP32), on a
+    seeded level map; the same map is given to the oracle."""
+    fr = sg.Scene("c1_256", width=250, height=131, num_tris=60).frame(0)
+    W, H = fr.width, fr.height
+    sched = starnt.new_sched(W, H, s2, s3)
+    df = starnt.DeviceFrags.from_frame(fr, max_per_pixel=64)
+    fb = starnt.FeatBuffers(W, H)
+    starnt.starnt_features(df, sched, fb)
+    base = 64
+    Cw, Ch = (W + 7) // 8, (H + 7) // 8
+    lv = np.random.default_rng(9).integers(0, 4, Cw * Ch).astype(np.uint8)
+    Ws, bs = sg.init_mlp((16, 32, 32, 3), seed=65, out_bias=0.05)
+    mlp = starnt.DeviceMlp(Ws, bs, starnt.F32)
+    rgb = torch.empty(W * H, 3, dtype=torch.float32, device="cuda")
+    starnt.starnt_infer_composite_sel(mlp, fb, sched, torch.from_numpy(lv).cuda(), base, BG, rgb)
+    sync()
+    o = oracle_mod.frame_of(fr, want=("lay", "tail"))
+    grids = (oracle_mod.grid_dim(W, s2), oracle_mod.grid_dim(H, s2), oracle_mod.grid_dim(W, s3),
+             oracle_mod.grid_dim(H, s3))
+    want = oracle_mod.selective(o["lay"], o["tail"], W, H, grids, oracle_mod.Mlp(Ws, bs), lv, base, BG)
+    assert np.abs(to_np(rgb) - want).max() <= 1e-4
+    # BF16 runs the same selection (flat cells need no network at all)
+    mlp.set_dtype(starnt.BF16)
+    starnt.starnt_infer_composite_sel(mlp, fb, sched, torch.from_numpy(np.zeros_like(lv)).cuda(), base, BG, rgb)
+    sync()
+    favg, _, _ = oracle_mod.learned(o["lay"], o["tail"], W, H, grids, None, oracle_mod.MODE_FAVG, BG)
+    assert np.abs(to_np(rgb) - favg).max() <= 1e-4

@@ -105,3 +105,27 @@ def test_baselines_empty_pixels_and_unknown_method(oracle_mod):
         np.testing.assert_array_equal(oracle_mod.baseline(off, dep, rgba, 2, 1, m, bg), [bg, bg])
     with pytest.raises(ValueError):
         oracle_mod.baseline(off, dep, rgba, 2, 1, 7, bg)
+
+
+def test_selective_inference_extremes(oracle_mod, sg):
+    """All cells flat: the f_avg composite; no cell flat: the learned one."""
+    fr = sg.Scene("c1_256", width=40, height=24, num_tris=20).frame(0)
+    o = oracle_mod.frame_of(fr, want=("lay", "tail"))
+    W, H = fr.width, fr.height
+    grids = (W, H, W, H)
+    Ws, bs = sg.init_mlp((16, 8, 8, 3), seed=2, out_bias=0.1)
+    m = oracle_mod.Mlp(Ws, bs)
+    cells = ((W + 7) // 8) * ((H + 7) // 8)
+    learned, _, _ = oracle_mod.learned(o["lay"], o["tail"], W, H, grids, m)
+    favg, _, _ = oracle_mod.learned(o["lay"], o["tail"], W, H, grids, None, oracle_mod.MODE_FAVG)
+    np.testing.assert_array_equal(oracle_mod.selective(o["lay"], o["tail"], W, H, grids, m, np.zeros(cells), 64), favg)
+    np.testing.assert_array_equal(oracle_mod.selective(o["lay"], o["tail"], W, H, grids, m, np.full(cells, 2), 64),
+                                  learned)
+    # only cell (1, 0) flat: exactly the pixels of columns 8..15, rows 0..7
+    lv = np.full(cells, 3)
+    lv[1] = 0
+    out = oracle_mod.selective(o["lay"], o["tail"], W, H, grids, m, lv, 64).reshape(H, W, 3)
+    np.testing.assert_array_equal(out[0:8, 8:16], favg.reshape(H, W, 3)[0:8, 8:16])
+    mask = np.ones((H, W), bool)
+    mask[0:8, 8:16] = False
+    np.testing.assert_array_equal(out[mask], learned.reshape(H, W, 3)[mask])

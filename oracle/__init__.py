@@ -92,6 +92,8 @@ def _load():
             lib.orc_reproject.argtypes = [ctypes.c_int32, ctypes.c_int32] + [_P] * 6
             lib.orc_reproject_full.restype = ctypes.c_int
             lib.orc_reproject_full.argtypes = [ctypes.c_int32, ctypes.c_int32] + [_P] * 5
+            lib.orc_reproject_check.restype = ctypes.c_int
+            lib.orc_reproject_check.argtypes = [ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_double, _P, _P]
             lib.orc_inverse4.restype = ctypes.c_int
             lib.orc_inverse4.argtypes = [_P, _P]
             lib.orc_mlp_loss_grad.restype = ctypes.c_double
@@ -560,3 +562,15 @@ def selective(lay, tail, width, height, grids, mlp, level, base, bg=(1.0, 1.0, 1
     ys, xs = np.divmod(np.arange(W * H), W)
     flat = np.asarray(level).ravel()[(ys // cs) * Cw + xs // cs] == 0
     return np.where(flat[:, None], rgb_a, rgb_l)
+
+
+def reproject_check(d1_r, mmi, width, height, tol):
+    """Trust codes of the gather: q (trusted source), -2 (depth mismatch
+    beyond tol), -1 (outside the frame or behind the camera); and the depth
+    difference at the source."""
+    W, H = int(width), int(height)
+    code = np.empty(W * H, np.int32)
+    zd = np.empty(W * H, np.float64)
+    _load().orc_reproject_check(W, H, _ptr(_c(d1_r, np.float32)), _ptr(_c(np.asarray(mmi).ravel(), np.float64)),
+                                float(tol), _ptr(code), _ptr(zd))
+    return code, zd

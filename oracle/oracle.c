@@ -761,6 +761,42 @@ int orc_reproject(int32_t W, int32_t H, const float* rgb_r, const float* d1_r, c
   return 0;
 }
 
+/*
+ * Trust test of the gather (selective re-rendering of interpolated frames):
+ * with the same mapping as orc_reproject, code[p] = q for a source inside the
+ * frame whose first-fragment depth matches the reprojected depth
+ * z' = h_z / h_w within tol; -2 when it does not (a disocclusion or a depth
+ * edge); -1 outside the frame or behind the camera. tol <= 0 disables the
+ * depth test. zdiff (optional) receives |d1_r(q) - z'| (0 where q < 0).
+ */
+int orc_reproject_check(int32_t W, int32_t H, const float* d1_r, const double* mmi, double tol, int32_t* code,
+                        double* zdiff) {
+  for (int32_t py = 0; py < H; ++py)
+    for (int32_t px = 0; px < W; ++px) {
+      int64_t p = (int64_t)py * W + px;
+      double X[4] = {(2.0 * px + 1.0) / W - 1.0, 1.0 - (2.0 * py + 1.0) / H, (double)d1_r[p], 1.0};
+      double h[4];
+      for (int r = 0; r < 4; ++r) {
+        h[r] = X[r];
+        for (int c = 0; c < 4; ++c) h[r] += mmi[4 * r + c] * X[c];
+      }
+      int32_t q = -1;
+      double dz = 0.0;
+      if (h[3] > 0.0) {
+        double u = h[0] / h[3], v = h[1] / h[3];
+        double qx = floor((u + 1.0) * 0.5 * W), qy = floor((1.0 - v) * 0.5 * H);
+        if (qx >= 0 && qx < W && qy >= 0 && qy < H) {
+          q = (int32_t)((int64_t)qy * W + (int64_t)qx);
+          dz = fabs((double)d1_r[q] - h[2] / h[3]);
+          if (tol > 0.0 && dz > tol) q = -2;
+        }
+      }
+      code[p] = q;
+      if (zdiff) zdiff[p] = dz;
+    }
+  return 0;
+}
+
 /* 4x4 inverse by Gauss-Jordan with partial pivoting (for the full-matrix form) */
 int orc_inverse4(const double* a, double* inv) {
   double m[4][8];

@@ -362,3 +362,30 @@ def test_overfit_tiny_batch(oracle_mod, sg):
         oracle_mod.adam(w, m, v, g, lr=3e-3, t=t)
     loss, _ = oracle_mod.loss_grad(dims, w, x, y)
     assert loss < 1e-6
+
+
+def test_reproject_check_identity_trusts_everything(oracle_mod):
+    W, H = 31, 17
+    d1 = np.random.default_rng(1).random(W * H).astype(np.float32)
+    code, zd = oracle_mod.reproject_check(d1, np.zeros(16), W, H, 1e-6)
+    np.testing.assert_array_equal(code, np.arange(W * H))
+    assert np.all(zd == 0)
+
+
+def test_reproject_check_depth_step_under_a_shift(oracle_mod):
+    """A depth step at column 20 (0.3 left, 0.7 right) seen after a 3-pixel
+    shift to the right: columns 17..19 land on the far side of the step (-2),
+    the last 3 columns leave the frame (-1), every other pixel is trusted."""
+    W, H = 40, 6
+    d1 = np.where(np.arange(W)[None, :] < 20, 0.3, 0.7).astype(np.float32).repeat(H, 0).ravel()
+    mmi = np.zeros((4, 4))
+    mmi[0, 3] = 2.0 * 3 / W
+    code, _ = oracle_mod.reproject_check(d1, mmi, W, H, 0.01)
+    code = code.reshape(H, W)
+    cols = np.arange(W)
+    want = np.where(cols >= W - 3, -1, np.where((cols >= 17) & (cols < 20), -2, cols + 3))
+    for y in range(H):
+        np.testing.assert_array_equal(np.where(code[y] >= 0, code[y] - y * W, code[y]), want)
+    # without the depth test only the frame border is untrusted
+    code0, _ = oracle_mod.reproject_check(d1, mmi, W, H, 0.0)
+    assert np.all(code0.reshape(H, W)[:, 17:20] >= 0)

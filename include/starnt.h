@@ -20,6 +20,8 @@
  *   starnt_quadtree   screen-tile quadtree update from the composite (Sec. 3.1)
  *                     and the pass scales of the next frame (Sec. 3.2, eq (4))
  *   starnt_reproject  interpolated frame by depth reprojection (Sec. 3.3)
+ *   starnt_reproject_check, starnt_patch
+ *                     its trust test and the re-rendering of untrusted pixels
  *   starnt_train_step one MSE + Adam step of the tail network (Sec. 3.3)
  *
  * Conventions for every call:
@@ -61,6 +63,8 @@ extern "C" {
 #define STARNT_DERR_DEPTH 1u  /* a depth outside [0,1] or NaN                  */
 #define STARNT_DERR_ALPHA 2u  /* an alpha outside [0,1] or NaN                 */
 #define STARNT_DERR_COUNT 4u  /* a list longer than max_per_pixel              */
+#define STARNT_DERR_LIST 8u   /* starnt_patch: a listed pixel outside the frame
+                                 or a list longer than its capacity           */
 
 /* ---- element types -------------------------------------------------------- */
 #define STARNT_F32 0
@@ -287,6 +291,36 @@ int starnt_quadtree(const float* rgb, const uint32_t* count, int32_t width, int3
  * src may be NULL. */
 int starnt_reproject(const float* rgb_prev, const float* d1_prev, int32_t width, int32_t height,
                      const float* m_minus_i, float* rgb_out, int32_t* src, void* stream);
+
+/* Interpolated frame with a trust test (Sec. 3.3: pixels the reprojection
+ * cannot fill are rendered afresh). Same gather as starnt_reproject, plus a
+ * depth test at the source: with z' = h_z / h_w the reprojected depth,
+ * src[p] = -2 where |d1_prev[q] - z'| > depth_tol (the source shows another
+ * surface); depth_tol = 0 disables the test. Every pixel with src[p] < 0 is
+ * appended to list (device uint32 [width*height], the caller's) and
+ * *list_count (device uint32) receives their number; the call clears it
+ * first, on the stream. The list's order varies from run to run, its set of
+ * pixels does not. src may be NULL; depth_tol must be finite and >= 0. */
+int starnt_reproject_check(const float* rgb_prev, const float* d1_prev, int32_t width, int32_t height,
+                           const float* m_minus_i, float depth_tol, float* rgb_out, int32_t* src, uint32_t* list,
+                           uint32_t* list_count, void* stream);
+
+/* Re-render the listed pixels of a frame from its fragment lists (Sec. 3.3,
+ * the untrusted pixels of an interpolated frame): passes 1-3 at full
+ * resolution and the STAR-NT network with the eq (3) composite, for pixel
+ * list[i] of frags, i < min(*list_count, capacity) (list must hold that
+ * many entries; list_count is a device uint32); rgb[list[i]] is overwritten and every
+ * other pixel of rgb is left as it is. Each pixel's result equals that of
+ * starnt_features + starnt_infer_composite at full resolution on the same
+ * frame, whatever the list's order.
+ * slots is scratch of the caller: a starnt_feats of width = capacity, height 1
+ * (d1, layer1, count, layer2, tail and err required; sel optional), whose
+ * slot i receives the features of list[i]. A count above the capacity is
+ * clamped and entries outside the frame are skipped; both set
+ * STARNT_DERR_LIST in slots->err. The DFAOIT network is not supported here
+ * (EUNSUPPORTED). */
+int starnt_patch(const starnt_frags* frags, const starnt_mlp* mlp, const uint32_t* list,
+                 const uint32_t* list_count, const starnt_feats* slots, const float* bg, float* rgb, void* stream);
 
 /* One training step on a batch (Sec. 3.3): loss = mean over batch x 3 of
  * (f(x) - y)^2 (ReLU derivative 0 at 0), gradient into t->grad, then Adam on

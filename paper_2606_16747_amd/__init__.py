@@ -24,7 +24,7 @@ MODE_LEARNED, MODE_F0, MODE_FAVG, MODE_EXACT = 0, 1, 2, 3
 NET_STARNT, NET_DFAOIT = 0, 1
 BASE_WBOIT, BASE_OVER_LIST = 0, 1
 WS_QUADTREE, WS_TRAIN = 1, 2
-DERR_DEPTH, DERR_ALPHA, DERR_COUNT = 1, 2, 4
+DERR_DEPTH, DERR_ALPHA, DERR_COUNT, DERR_LIST = 1, 2, 4, 8
 STATUS = {0: "OK", 1: "EINVAL", 2: "ERANGE", 3: "ENOMEM", 4: "EHIP", 5: "EUNSUPPORTED"}
 
 _P = ctypes.c_void_p
@@ -85,7 +85,7 @@ assert ctypes.sizeof(Sched) == 64
 
 EXPORTS = ("starnt_features", "starnt_infer", "starnt_infer_composite", "starnt_composite", "starnt_baseline",
            "starnt_dfa_inputs", "starnt_infer_composite_sel",
-           "starnt_quadtree", "starnt_reproject", "starnt_interval_init", "starnt_interval_next",
+           "starnt_quadtree", "starnt_reproject", "starnt_reproject_check", "starnt_patch", "starnt_interval_init", "starnt_interval_next",
            "starnt_interval_report",
            "starnt_train_step", "starnt_sched_init", "starnt_wbar", "starnt_pass_scales", "starnt_grid_dim",
            "starnt_workspace_size", "starnt_check", "starnt_last_error", "starnt_version")
@@ -112,6 +112,10 @@ def _load():
                                     _P, _P, ctypes.c_size_t, _P]
     lib.starnt_reproject.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), _P,
                                      _P, _P]
+    lib.starnt_reproject_check.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_float),
+                                           ctypes.c_float, _P, _P, _P, _P, _P]
+    lib.starnt_patch.argtypes = [ctypes.POINTER(Frags), ctypes.POINTER(Mlp), _P, _P, ctypes.POINTER(Feats),
+                                 ctypes.POINTER(ctypes.c_float), _P, _P]
     lib.starnt_train_step.argtypes = [ctypes.POINTER(Train), _P, _P, ctypes.c_int32, ctypes.POINTER(Adam), _P, _P,
                                       ctypes.c_size_t, _P]
     lib.starnt_sched_init.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _P]
@@ -330,6 +334,22 @@ def starnt_reproject(rgb_prev, d1_prev, width, height, m_minus_i, rgb_out, src=N
     mc = (ctypes.c_float * 16)(*[float(v) for v in m])
     _check(lib.starnt_reproject(_ptr(rgb_prev), _ptr(d1_prev), int(width), int(height), mc, _ptr(rgb_out), _ptr(src),
                                 _stream(stream)))
+
+
+def starnt_reproject_check(rgb_prev, d1_prev, width, height, m_minus_i, depth_tol, rgb_out, src, lst, count,
+                           stream=None):
+    m = np.asarray(m_minus_i, np.float32).ravel()
+    mc = (ctypes.c_float * 16)(*[float(v) for v in m])
+    _check(lib.starnt_reproject_check(_ptr(rgb_prev), _ptr(d1_prev), int(width), int(height), mc, float(depth_tol),
+                                      _ptr(rgb_out), _ptr(src), _ptr(lst), _ptr(count), _stream(stream)))
+
+
+def starnt_patch(frags, mlp: DeviceMlp, lst, count, slots: FeatBuffers, bg, rgb, stream=None):
+    """slots: FeatBuffers(capacity, 1), scratch for the listed pixels."""
+    bgc = (ctypes.c_float * 3)(*[float(v) for v in bg])
+    _check(lib.starnt_patch(ctypes.byref(frags._c) if frags is not None else None, ctypes.byref(mlp._c), _ptr(lst),
+                            _ptr(count), ctypes.byref(slots._c) if slots is not None else None, bgc, _ptr(rgb),
+                            _stream(stream)))
 
 
 def starnt_train_step(train: Train, x, y, batch, adam: Adam, loss, workspace, stream=None):

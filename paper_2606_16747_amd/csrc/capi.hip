@@ -208,6 +208,42 @@ int starnt_reproject(const float* rgb_prev, const float* d1_prev, int32_t width,
   return launch_reproject(rgb_prev, d1_prev, width, height, m_minus_i, rgb_out, src, as_stream(stream));
 }
 
+int starnt_reproject_check(const float* rgb_prev, const float* d1_prev, int32_t width, int32_t height,
+                           const float* m_minus_i, float depth_tol, float* rgb_out, int32_t* src, uint32_t* list,
+                           uint32_t* list_count, void* stream) {
+  int rc = check_frame(width, height, "starnt_reproject_check");
+  if (rc) return rc;
+  if (!rgb_prev || !d1_prev || !m_minus_i || !rgb_out || !list || !list_count)
+    return fail(STARNT_EINVAL, "starnt_reproject_check: NULL argument");
+  if (rgb_prev == rgb_out) return fail(STARNT_EINVAL, "starnt_reproject_check: rgb_out aliases rgb_prev");
+  for (int i = 0; i < 16; ++i)
+    if (!std::isfinite(m_minus_i[i])) return fail(STARNT_EINVAL, "starnt_reproject_check: non-finite matrix");
+  if (!std::isfinite(depth_tol) || depth_tol < 0.0f)
+    return fail(STARNT_EINVAL, "starnt_reproject_check: depth_tol must be finite and >= 0");
+  return launch_reproject(rgb_prev, d1_prev, width, height, m_minus_i, rgb_out, src, as_stream(stream), depth_tol,
+                          list, list_count);
+}
+
+int starnt_patch(const starnt_frags* frags, const starnt_mlp* mlp, const uint32_t* list,
+                 const uint32_t* list_count, const starnt_feats* slots, const float* bg, float* rgb, void* stream) {
+  int rc = check_frags(frags, "starnt_patch");
+  if (rc) return rc;
+  rc = check_mlp(mlp, "starnt_patch");
+  if (rc) return rc;
+  if (mlp->variant != STARNT_NET_STARNT)
+    return fail(STARNT_EUNSUPPORTED, "starnt_patch: only the STAR-NT network re-renders pixel lists");
+  if (!list || !list_count || !bg || !rgb) return fail(STARNT_EINVAL, "starnt_patch: NULL argument");
+  if (!slots || !slots->d1 || !slots->layer1 || !slots->count || !slots->layer2 || !slots->tail || !slots->err)
+    return fail(STARNT_EINVAL, "starnt_patch: NULL slot array (d1, layer1, count, layer2, tail, err)");
+  if (slots->height != 1 || slots->width < 1)
+    return fail(STARNT_EINVAL, "starnt_patch: slots must be a 1-row block (width = capacity, height = 1)");
+  const hipStream_t s = as_stream(stream);
+  rc = launch_features_list(*frags, list, list_count, *slots, s);
+  if (rc) return rc;
+  return launch_infer_patch(*mlp, *slots, list, list_count, (uint32_t)frags->width * (uint32_t)frags->height, bg,
+                            rgb, s);
+}
+
 int starnt_train_step(const starnt_train* t, const float* x, const float* y, int32_t batch,
                       const starnt_adam* hp, float* loss, void* workspace, size_t workspace_bytes,
                       void* stream) {
@@ -266,6 +302,7 @@ int starnt_check(uint32_t err_word) {
   if (err_word & STARNT_DERR_DEPTH) m += " depth outside [0,1];";
   if (err_word & STARNT_DERR_ALPHA) m += " alpha outside [0,1];";
   if (err_word & STARNT_DERR_COUNT) m += " list longer than max_per_pixel;";
+  if (err_word & STARNT_DERR_LIST) m += " pixel list entry outside the frame or longer than its capacity;";
   return fail(STARNT_ERANGE, m);
 }
 

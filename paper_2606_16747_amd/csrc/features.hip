@@ -77,6 +77,9 @@ struct FeatArgs {
   uint2* sel;
   uint32_t* err;
   float4* tail_avg;  // optional tail means (DFAOIT inputs)
+  const uint32_t* list;    // listed pixels (patch only)
+  const uint32_t* list_n;  // number of listed pixels (patch only)
+  uint32_t frame_p;        // pixels of the frame the list indexes (patch only)
 };
 
 // Fixed-point terms of one fragment. Each is an exact integer function of
@@ -338,10 +341,76 @@ __global__ __launch_bounds__(256) void features_kernel(FeatArgs a) {
     pixel<HALF, false, AVG>(a, g, p, q, b, e, i2, j2, i3, j3);
 }
 
+// Features of a list of pixels (re-rendering of untrusted interpolated
+// pixels): entry i of the list is pixel p = list[i] of the frame, and its
+// outputs go to slot i of compact arrays, all at full resolution. A quad owns
+// one entry; quads stride through the list, whose length is read on the
+// device. Entries outside the frame and a length above the capacity are
+// flagged, not followed.
+template <bool HALF>
+__global__ __launch_bounds__(256) void features_list_kernel(FeatArgs a) {
+  const uint32_t cap = (uint32_t)a.W;
+  const uint32_t given = *a.list_n;
+  const uint32_t n = given < cap ? given : cap;
+  const int q = threadIdx.x & (kG - 1);
+  const uint32_t first = (blockIdx.x * (unsigned)blockDim.x + threadIdx.x) / kG;
+  const uint32_t stride = gridDim.x * (unsigned)blockDim.x / kG;
+  if (first == 0 && q == 0 && given > cap) atomicOr(a.err, STARNT_DERR_LIST);
+  Grids g;
+  g.w2 = g.w3 = (int)cap;
+  g.h2 = g.h3 = 1;
+  for (uint32_t i = first; i < n; i += stride) {
+    const uint32_t p = a.list[i];
+    if (p >= a.frame_p) {
+      if (q == 0) atomicOr(a.err, STARNT_DERR_LIST);
+      continue;  // the same p for the whole quad
+    }
+    const uint32_t b = a.off[p], e = a.off[p + 1];
+    if (__builtin_amdgcn_ballot_w64(e - b > kNarrow) != 0)
+      pixel<HALF, true, false>(a, g, (int)i, q, b, e, (int)i, 0, (int)i, 0);
+    else
+      pixel<HALF, false, false>(a, g, (int)i, q, b, e, (int)i, 0, (int)i, 0);
+  }
+}
+
 }  // namespace
 
+int launch_features_list(const starnt_frags& f, const uint32_t* list, const uint32_t* list_n,
+                         const starnt_feats& o, hipStream_t s) {
+  FeatArgs a{};
+  a.W = o.width;  // capacity: the compact arrays hold o.width entries
+  a.H = 1;
+  a.off = f.offsets;
+  a.depth = f.depth;
+  a.rgba = f.rgba;
+  a.prim = f.prim;
+  a.max_n = f.max_per_pixel;
+  a.sched = nullptr;
+  a.d1 = o.d1;
+  a.layer1 = reinterpret_cast<float4*>(o.layer1);
+  a.count = o.count;
+  a.layer2 = reinterpret_cast<float4*>(o.layer2);
+  a.tail = reinterpret_cast<float4*>(o.tail);
+  a.sel = reinterpret_cast<uint2*>(o.sel);
+  a.err = o.err;
+  a.tail_avg = nullptr;
+  a.list = list;
+  a.list_n = list_n;
+  a.frame_p = (uint32_t)f.width * (uint32_t)f.height;
+  // enough quads to fill the chip; each walks the list with a stride
+  const int64_t quads = o.width;
+  int64_t blocks = (quads * kG + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  const dim3 block(256), grid((unsigned)blocks);
+  if (f.rgba_dtype == STARNT_F16) hipLaunchKernelGGL(features_list_kernel<true>, grid, block, 0, s, a);
+  else hipLaunchKernelGGL(features_list_kernel<false>, grid, block, 0, s, a);
+  STARNT_LAUNCH_CHECK("starnt_patch features launch");
+  return STARNT_OK;
+}
+
 int launch_features(const starnt_frags& f, const starnt_sched* sched, const starnt_feats& o, hipStream_t s) {
-  FeatArgs a;
+  FeatArgs a{};
   a.W = f.width;
   a.H = f.height;
   a.off = f.offsets;

@@ -29,6 +29,7 @@ namespace {
 // what a kernel produces: the tail colour (starnt_infer), the eq (3)
 // composite with it, or the DFAOIT composite (eq (2))
 constexpr int kTail = 0, kComp = 1, kDfa = 2, kSel = 3;  // kSel: kComp, network only off flat cells
+constexpr int kPatch = 4;  // kComp over a pixel list: compact full-resolution inputs
 
 struct InferArgs {
   int W, H;
@@ -50,7 +51,20 @@ struct InferArgs {
   float sa[3], sw[3];  // FP8 scales
   float bg0, bg1, bg2;
   float* out;          // tail colour [P][3] or composite rgb [P][3]
+  const uint32_t* list;    // kPatch: slot i holds pixel list[i] of the frame
+  const uint32_t* list_n;  // kPatch: number of slots in use (device)
+  uint32_t frame_p;        // kPatch: pixels of the output frame
 };
+
+// pixels a launch covers: the frame, or the slots of the list in use
+template <int MODE>
+__device__ __forceinline__ int pixel_count(const InferArgs& a) {
+  if constexpr (MODE == kPatch) {
+    const uint32_t n = *a.list_n, cap = (uint32_t)a.W;
+    return (int)(n < cap ? n : cap);
+  }
+  return a.W * a.H;
+}
 
 // inputs of one pixel for the network and the composite
 struct PixIn {
@@ -84,6 +98,20 @@ struct PixRaw {
 template <int MODE>
 __device__ __forceinline__ void issue_loads(const InferArgs& a, const Grids& g, int p, PixRaw& r) {
   r.n = a.count[p];
+  if constexpr (MODE == kPatch) {
+    // slot p holds its own full-resolution features: one tap, weight 0
+    const float4 lo = a.tail[2u * p], hi = a.tail[2u * p + 1u];
+    const float4 l2 = a.layer2[p];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      r.t[k] = lo;
+      r.t4[k] = make_float2(hi.x, 0.0f);
+      r.l2[k] = l2;
+    }
+    r.l1 = a.layer1[p];
+    r.wx3 = r.wy3 = r.wx2 = r.wy2 = 0.0f;
+    return;
+  }
   int x, y;
   pixel_xy(p, a.W, x, y);
   const Taps tx = axis_taps(x, a.W, g.w3), ty = axis_taps(y, a.H, g.h3);
@@ -180,7 +208,12 @@ __device__ __forceinline__ void load_pixel(const InferArgs& a, const Grids& g, i
 template <int MODE>
 __device__ __forceinline__ void store_pixel(const InferArgs& a, int p, const PixIn& in, float f0, float f1, float f2) {
   const bool on = in.n >= 3;
-  float* o = a.out + 3 * (size_t)p;
+  size_t dst = (size_t)p;
+  if constexpr (MODE == kPatch) {
+    dst = a.list[p];
+    if (dst >= a.frame_p) return;  // flagged by the list's feature pass
+  }
+  float* o = a.out + 3 * dst;
   if constexpr (MODE == kDfa) {
     const float T = (1.0f - in.l1.w) * (1.0f - in.l2.w) * (on ? in.tt : 1.0f);
     o[0] = fmaf(T, a.bg0, on ? f0 : in.e0);
@@ -197,7 +230,7 @@ __device__ __forceinline__ void store_pixel(const InferArgs& a, int p, const Pix
         f2 = on ? in.x[4] * w : 0.0f;
       }
     }
-    if constexpr (MODE == kComp || MODE == kSel) {
+    if constexpr (MODE == kComp || MODE == kSel || MODE == kPatch) {
       const float tt = on ? in.tt : 1.0f;
       const float om1 = 1.0f - in.l1.w;
       const float T2 = om1 * (1.0f - in.l2.w);
@@ -229,7 +262,7 @@ constexpr int n_inputs() { return MODE == kDfa ? 11 : 5; }
 
 template <int H1, int H2, int MODE>
 __global__ __launch_bounds__(256) void infer_f32_kernel(InferArgs a) {
-  const int P = a.W * a.H;
+  const int P = pixel_count<MODE>(a);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
   const Grids g = load_grids(a.sched, a.W, a.H);
@@ -380,7 +413,7 @@ __global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
   const int waves_per_block = blockDim.x >> 6;
   const int wave = blockIdx.x * waves_per_block + (threadIdx.x >> 6);
   const int nwaves = gridDim.x * waves_per_block;
-  const int P = a.W * a.H;
+  const int P = pixel_count<MODE>(a);
   const int nsteps = (P + 63) / 64;
   const Grids g = load_grids(a.sched, a.W, a.H);
   // FP8: activation scale of each layer's input, inverse weight scale, and
@@ -607,6 +640,9 @@ InferArgs make_args(const starnt_mlp& m, const float* tail, const uint32_t* coun
   a.bg1 = bg ? bg[1] : 0.0f;
   a.bg2 = bg ? bg[2] : 0.0f;
   a.out = out;
+  a.list = nullptr;
+  a.list_n = nullptr;
+  a.frame_p = 0;
   return a;
 }
 
@@ -655,6 +691,20 @@ int launch_infer_composite_sel(const starnt_mlp& m, const starnt_feats& f, const
   const int rc = dispatch<kSel>(m, a, s);
   if (rc) return fail(rc, "starnt_infer_composite_sel: unsupported dtype / hidden widths");
   STARNT_LAUNCH_CHECK("starnt_infer_composite_sel launch");
+  return STARNT_OK;
+}
+
+int launch_infer_patch(const starnt_mlp& m, const starnt_feats& slots, const uint32_t* list,
+                       const uint32_t* list_n, uint32_t frame_p, const float bg[3], float* rgb, hipStream_t s) {
+  // the slots are a 1-row frame of `slots.width` pixels at full resolution
+  InferArgs a = make_args(m, slots.tail, slots.count, slots.layer1, slots.layer2, nullptr, nullptr, slots.width, 1,
+                          bg, rgb);
+  a.list = list;
+  a.list_n = list_n;
+  a.frame_p = frame_p;
+  const int rc = dispatch<kPatch>(m, a, s);
+  if (rc) return fail(rc, "starnt_patch: unsupported dtype / hidden widths");
+  STARNT_LAUNCH_CHECK("starnt_patch launch");
   return STARNT_OK;
 }
 

@@ -4,7 +4,9 @@ A real frame runs passes 1-3 on the grids the device schedule holds, the tail
 network, the eq (3) composite and the quadtree update, which leaves the next
 frame's grids in the schedule (eq (4)); no host round trip is needed between
 frames. An interpolated frame is one reprojection gather from the last real
-frame. Every step is a libstarnt call on the caller's stream.
+frame; given that frame's fragment lists it also re-renders the pixels the
+gather cannot trust (source outside the frame, behind the camera, or showing
+another surface). Every step is a libstarnt call on the caller's stream.
 """
 from __future__ import annotations
 
@@ -14,7 +16,8 @@ import torch
 from . import (MODE_EXACT, MODE_LEARNED, WS_QUADTREE, DeviceFrags, DeviceMlp, FeatBuffers, QtParams,
                starnt_composite, starnt_features, starnt_infer_composite, starnt_infer_composite_sel,
                starnt_interval_init,
-               starnt_interval_next, starnt_interval_report, starnt_quadtree, starnt_reproject, starnt_sched_init,
+               starnt_interval_next, starnt_interval_report, starnt_patch, starnt_quadtree, starnt_reproject,
+               starnt_reproject_check, starnt_sched_init,
                starnt_workspace_size, workspace)
 
 
@@ -27,11 +30,14 @@ def m_minus_i(vp_real, vp_cur):
 class Renderer:
     """Buffers and calls for one frame size. Outputs are [P, 3] float32.
     With selective=True a real frame after the first runs the network only
-    off the flat (level-0) leaves of the last real frame's quadtree."""
+    off the flat (level-0) leaves of the last real frame's quadtree.
+    depth_tol is the trust test's tolerance on window-space depth for
+    interpolated frames that are given their fragment lists."""
 
     def __init__(self, width, height, mlp: DeviceMlp, base=64, tau_split=0.10, tau_merge=0.05, k_relax=2,
-                 bg=(1.0, 1.0, 1.0), device="cuda", mode=MODE_LEARNED, selective=False):
+                 bg=(1.0, 1.0, 1.0), device="cuda", mode=MODE_LEARNED, selective=False, depth_tol=0.01):
         self.selective = bool(selective)
+        self.depth_tol = float(depth_tol)
         self.W, self.H = int(width), int(height)
         P = self.W * self.H
         self.mlp = mlp
@@ -48,6 +54,12 @@ class Renderer:
         self.ws = workspace(starnt_workspace_size(WS_QUADTREE, self.W, self.H, base), device)
         self.rgb_real = None
         self.n_real = 0
+        # untrusted pixels of an interpolated frame and the slots of their
+        # features (allocated on first use)
+        self.list = torch.empty(P, dtype=torch.int32, device=device)
+        self.list_count = torch.zeros(1, dtype=torch.int32, device=device)
+        self.slots = None
+        self.device = device
         self.timer = None  # optional callable(name, fn) wrapping each call
 
     def _call(self, name, fn):
@@ -83,10 +95,21 @@ class Renderer:
         self.n_real += 1
         return out
 
-    def interpolated_frame(self, mmi, out, stream=None):
+    def interpolated_frame(self, mmi, out, stream=None, frags: DeviceFrags | None = None):
+        """The gather from the last real frame; with the frame's own fragment
+        lists (learned mode), its untrusted pixels are rendered afresh."""
         assert self.rgb_real is not None, "an interpolated frame needs a real frame before it"
-        self._call("reproject", lambda: starnt_reproject(self.rgb_real, self.feats.d1, self.W, self.H, mmi, out, None,
-                                                         stream))
+        if frags is None or self.mode != MODE_LEARNED:
+            self._call("reproject", lambda: starnt_reproject(self.rgb_real, self.feats.d1, self.W, self.H, mmi, out,
+                                                             None, stream))
+            return out
+        if self.slots is None:
+            self.slots = FeatBuffers(self.W * self.H, 1, self.device)
+        self._call("reproject", lambda: starnt_reproject_check(self.rgb_real, self.feats.d1, self.W, self.H, mmi,
+                                                               self.depth_tol, out, None, self.list,
+                                                               self.list_count, stream))
+        self._call("patch", lambda: starnt_patch(frags, self.mlp, self.list, self.list_count, self.slots, self.bg,
+                                                 out, stream))
         return out
 
 
@@ -101,10 +124,12 @@ class AdaptiveSequence:
     frame it just queued). `cost` may instead be a callable (t, real) -> ms
     that supplies them, which makes a sequence deterministic. The output of a
     real frame is the source of the frames interpolated after it, so it must
-    stay untouched until the next real frame."""
+    stay untouched until the next real frame. With patch=True an interpolated
+    frame also takes its fragment lists and re-renders its untrusted pixels."""
 
-    def __init__(self, renderer: Renderer, target_ms, max_interval=4, smoothing=0.25, cost=None):
+    def __init__(self, renderer: Renderer, target_ms, max_interval=4, smoothing=0.25, cost=None, patch=False):
         self.r = renderer
+        self.patch = bool(patch)
         self.state = starnt_interval_init(target_ms, max_interval, smoothing)
         self.cost = cost
         self.vp_real = None
@@ -126,7 +151,8 @@ class AdaptiveSequence:
 
     def frame(self, vp, frags_fn, out, stream=None):
         """Render frame t into out; frags_fn() gives its fragment lists and is
-        called only for a real frame. Returns True for a real frame."""
+        called only for a real frame (and, with patch, for every frame).
+        Returns True for a real frame."""
         self._report()
         real = starnt_interval_next(self.state)
         if self.t == 0 or self.r.n_real == 0:
@@ -140,7 +166,8 @@ class AdaptiveSequence:
             self.r.real_frame(frags_fn(), out, stream)
             self.vp_real = np.asarray(vp, np.float64)
         else:
-            self.r.interpolated_frame(m_minus_i(self.vp_real, vp), out, stream)
+            self.r.interpolated_frame(m_minus_i(self.vp_real, vp), out, stream,
+                                      frags=frags_fn() if self.patch else None)
         if b is not None:
             b.record(stream) if stream is not None else b.record()
         self._pending = (self.t, real, a, b)

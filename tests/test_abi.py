@@ -96,6 +96,26 @@ def test_host_validation_rejects_bad_arguments(starnt):
     assert b"method" in lib.starnt_last_error()
     assert lib.starnt_baseline(ctypes.byref(fr), 0, bg, None, None) == 1
     assert lib.starnt_baseline(None, 0, bg, 16, None) == 1
+    m = (ctypes.c_float * 16)(*([0.0] * 16))
+    rc = lib.starnt_reproject_check
+    rc.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                   ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                   ctypes.c_void_p]
+    assert rc(16, 32, 8, 8, m, -0.5, 48, None, 64, 80, None) == 1  # negative tolerance
+    assert b"depth_tol" in lib.starnt_last_error()
+    assert rc(16, 32, 8, 8, m, float("inf"), 48, None, 64, 80, None) == 1
+    assert rc(16, 32, 8, 8, m, 0.01, 48, None, None, 80, None) == 1  # no list
+    assert rc(16, 16, 8, 8, m, 0.01, 16, None, 64, 80, None) == 1    # output aliases input
+    fr = starnt.Frags(8, 8, 16, 16, 16, 0, 16, 10, 1)
+    slots = starnt.Feats(4, 1, 16, 16, 16, 16, 16, None, 16, None)
+    mlp = starnt.Mlp(16, 32, 32, 3, 0, 16, 16, 16, 16, 16, 16, None)
+    patch = lib.starnt_patch
+    bad = starnt.Feats(4, 2, 16, 16, 16, 16, 16, None, 16, None)  # slots must be one row
+    assert patch(ctypes.byref(fr), ctypes.byref(mlp), 16, 16, ctypes.byref(bad), bg, 16, None) == 1
+    assert b"1-row" in lib.starnt_last_error()
+    assert patch(ctypes.byref(fr), ctypes.byref(mlp), None, 16, ctypes.byref(slots), bg, 16, None) == 1
+    dfa = starnt.Mlp(16, 32, 32, 3, 0, 16, 16, 16, 16, 16, 16, None, 1)
+    assert patch(ctypes.byref(fr), ctypes.byref(dfa), 16, 16, ctypes.byref(slots), bg, 16, None) == 5
 
 
 def test_product_package_has_no_cpu_fallback():

@@ -1,0 +1,213 @@
+"""Interpolated frames with re-rendered untrusted pixels (Sec. 3.3): the trust
+test of the gather against the oracle, the compact list it builds, and
+starnt_patch, whose pixels must equal a full-resolution real render of the
+same frame (against the GPU's own full-frame path bit for bit, and against the
+FP64 oracle within the FP32 bar)."""
+import numpy as np
+import pytest
+import torch
+
+from csr_util import make_csr
+from gpu_util import run_features, sync, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def _list_np(lst, count):
+    n = int(to_np(count)[0])
+    return np.sort(to_np(lst)[:n].view(np.uint32).astype(np.int64))
+
+
+@pytest.mark.parametrize("t1,tol", [(3, 0.01), (5, 0.003), (5, 0.0)])
+def test_reproject_check_matches_oracle(starnt, gpu, sg, oracle_mod, t1, tol):
+    """Trust codes bit-exact against the FP64 oracle on the same FP32 inputs,
+    except where the source coordinate lies within 1e-4 px of a rounding
+    boundary or the depth difference within 1e-5 of the tolerance; the list
+    holds exactly the pixels the GPU marked untrusted; the gathered colours are
+    those of the plain reprojection."""
+    sc = sg.Scene("c2_1080p", width=640, height=360, num_tris=400)
+    W, H = 640, 360
+    P = W * H
+    fr = sc.frame(2)
+    o = oracle_mod.frame_of(fr, want=("rgb", "lay"))
+    rgb = torch.from_numpy(o["rgb"].astype(np.float32)).cuda()
+    d1n = o["lay"][:, 1].astype(np.float32)
+    d1 = torch.from_numpy(d1n).cuda()
+    mmi = oracle_mod.m_minus_i(sc.camera(2), sc.camera(t1)).astype(np.float32)
+    out = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+    src = torch.empty(P, dtype=torch.int32, device="cuda")
+    lst = torch.full((P,), -1, dtype=torch.int32, device="cuda")
+    count = torch.full((1,), 12345, dtype=torch.int32, device="cuda")  # the call clears it
+    starnt.starnt_reproject_check(rgb, d1, W, H, mmi, tol, out, src, lst, count)
+    plain = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+    starnt.starnt_reproject(rgb, d1, W, H, mmi, plain)
+    sync()
+    code, zd = oracle_mod.reproject_check(d1n, mmi.astype(np.float64), W, H, tol)
+    _, _, margin = oracle_mod.reproject(o["rgb"].astype(np.float32), d1n, mmi.astype(np.float64), W, H)
+    ok = (margin >= 1e-4) & ((tol == 0) | (np.abs(zd - tol) >= 1e-5))
+    assert ok.mean() > 0.99
+    got = to_np(src)
+    np.testing.assert_array_equal(got[ok], code[ok])
+    np.testing.assert_array_equal(_list_np(lst, count), np.flatnonzero(got < 0))
+    assert torch.equal(out, plain)
+    if tol > 0:
+        assert (got == -2).mean() > 0.01
+    else:
+        assert not (got == -2).any()
+
+
+def _full_render(starnt, df, mlp, bg):
+    P = df.width * df.height
+    fb = starnt.FeatBuffers(df.width, df.height)
+    starnt.starnt_features(df, None, fb)
+    rgb = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+    starnt.starnt_infer_composite(mlp, fb, None, bg, rgb)
+    return rgb, fb
+
+
+def _patch(starnt, df, mlp, pix, bg, capacity=None, fill=-7.0):
+    P = df.width * df.height
+    buf = np.zeros(max(len(pix), 1), np.uint32)  # an empty list still has an address
+    buf[:len(pix)] = np.asarray(pix, np.uint32)
+    lst = torch.from_numpy(buf.view(np.int32)).cuda()
+    count = torch.tensor([len(pix)], dtype=torch.int32, device="cuda")
+    slots = starnt.FeatBuffers(capacity or max(len(pix), 1), 1)
+    rgb = torch.full((P, 3), fill, dtype=torch.float32, device="cuda")
+    starnt.starnt_patch(df, mlp, lst, count, slots, bg, rgb)
+    sync()
+    return rgb, slots
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+def test_patch_equals_full_frame_render(starnt, gpu, sg, oracle_mod, dtype):
+    """A random third of the pixels of a config-1 frame, in shuffled order:
+    each patched pixel equals the full-frame render bit for bit, every other
+    pixel keeps its old value; FP32 patched pixels match the oracle's
+    full-resolution learned composite within 1e-4."""
+    fr = sg.Scene("c1_256", width=250, height=131, num_tris=60).frame(0)
+    W, H = fr.width, fr.height
+    P = W * H
+    df = starnt.DeviceFrags.from_frame(fr, max_per_pixel=64)
+    Ws, bs = sg.init_mlp((16, 32, 32, 3), out_bias=0.05)
+    kw = {}
+    if dtype == "fp8":
+        kw["fp8_scales"] = [1.0 / 64, float(np.abs(Ws[0]).max()) / 448.0, 4.0 / 448, float(np.abs(Ws[1]).max()) / 448,
+                            4.0 / 448, float(np.abs(Ws[2]).max()) / 448]
+    mlp = starnt.DeviceMlp(Ws, bs, {"f32": starnt.F32, "bf16": starnt.BF16, "fp8": starnt.FP8}[dtype], **kw)
+    bg = (0.9, 0.8, 0.7)
+    full, fb = _full_render(starnt, df, mlp, bg)
+    rng = np.random.default_rng(3)
+    pix = rng.permutation(P)[: P // 3]
+    got, slots = _patch(starnt, df, mlp, pix, bg)
+    g, f = to_np(got), to_np(full)
+    np.testing.assert_array_equal(g[pix], f[pix])
+    rest = np.ones(P, bool)
+    rest[pix] = False
+    assert np.all(g[rest] == -7.0)
+    assert int(to_np(slots.err)[0]) == 0
+    N = to_np(fb.count)[pix]
+    assert (N == 0).any() and (N == 1).any() and (N == 2).any() and (N >= 3).sum() > 100
+    # slot i holds pixel pix[i]'s features
+    np.testing.assert_array_equal(to_np(slots.count), N)
+    np.testing.assert_array_equal(to_np(slots.d1), to_np(fb.d1)[pix])
+    if dtype == "f32":
+        o = oracle_mod.frame_of(fr)
+        want, _, _ = oracle_mod.learned(o["lay"], o["tail"], W, H, (W, H, W, H), oracle_mod.Mlp(Ws, bs),
+                                        oracle_mod.MODE_LEARNED, bg=bg)
+        assert np.abs(g[pix] - want[pix]).max() <= TOL
+
+
+def test_patch_long_lists_and_ragged_list(starnt, gpu, oracle_mod):
+    """Lists above 255 fragments (the 64-bit sums) and a list length that is
+    not a multiple of the wave's 16 pixels; order of the list is arbitrary."""
+    rng = np.random.default_rng(21)
+    W, H = 23, 7
+    lists = []
+    for p in range(W * H):
+        n = int(rng.choice([0, 1, 2, 5, 40, 300, 900])) if p % 5 == 0 else int(rng.integers(0, 12))
+        z = rng.permutation(n).astype(np.float32) / max(n, 1)
+        lists.append([(float(z[k]), k, *rng.random(3), float(rng.uniform(0.01, 0.3))) for k in range(n)])
+    csr = make_csr(lists, W, H)
+    df = starnt.DeviceFrags(*csr, W, H, 1024)
+    Ws = [rng.normal(0, 0.4, (32, 16)), rng.normal(0, 0.3, (32, 32)), rng.normal(0, 0.3, (3, 32))]
+    bs = [rng.normal(0, 0.1, 32), rng.normal(0, 0.1, 32), np.full(3, 0.05)]
+    mlp = starnt.DeviceMlp(Ws, bs, starnt.F32)
+    bg = (0.2, 0.4, 0.6)
+    full, _ = _full_render(starnt, df, mlp, bg)
+    pix = rng.permutation(W * H)[:37]
+    got, slots = _patch(starnt, df, mlp, pix, bg)
+    np.testing.assert_array_equal(to_np(got)[pix], to_np(full)[pix])
+    assert int(to_np(slots.err)[0]) == 0
+    o = oracle_mod.frame(*csr, W, H)
+    want, _, _ = oracle_mod.learned(o["lay"], o["tail"], W, H, (W, H, W, H), oracle_mod.Mlp(Ws, bs),
+                                    oracle_mod.MODE_LEARNED, bg=bg)
+    assert np.abs(to_np(got)[pix] - want[pix]).max() <= TOL
+
+
+def test_patch_empty_list_and_flagged_entries(starnt, gpu, sg):
+    """An empty list writes nothing; entries outside the frame are skipped and
+    a count above the capacity is clamped, both flagged in the error word,
+    while the valid entries are still rendered."""
+    fr = sg.Scene("c1_256", width=64, height=40, num_tris=20).frame(0)
+    P = fr.num_pixels
+    df = starnt.DeviceFrags.from_frame(fr, max_per_pixel=64)
+    Ws, bs = sg.init_mlp((16, 32, 32, 3), out_bias=0.05)
+    mlp = starnt.DeviceMlp(Ws, bs, starnt.F32)
+    bg = (1.0, 1.0, 1.0)
+    full, _ = _full_render(starnt, df, mlp, bg)
+    got, slots = _patch(starnt, df, mlp, [], bg)
+    assert torch.all(got == -7.0) and int(to_np(slots.err)[0]) == 0
+    # entries outside the frame
+    pix = np.array([5, P + 3, 17, 0xFFFFFFF0, P - 1], np.uint32)
+    got, slots = _patch(starnt, df, mlp, pix, bg)
+    ok = pix[pix < P].astype(np.int64)
+    np.testing.assert_array_equal(to_np(got)[ok], to_np(full)[ok])
+    assert int(to_np(slots.err)[0]) & starnt.DERR_LIST
+    assert int((to_np(got) != -7.0).any(axis=1).sum()) == len(ok)
+    # a count above the capacity: only the first `capacity` entries
+    lst = torch.from_numpy(np.arange(10, dtype=np.int32)).cuda()
+    count = torch.tensor([10], dtype=torch.int32, device="cuda")
+    slots = starnt.FeatBuffers(4, 1)
+    rgb = torch.full((P, 3), -7.0, dtype=torch.float32, device="cuda")
+    starnt.starnt_patch(df, mlp, lst, count, slots, bg, rgb)
+    sync()
+    changed = np.flatnonzero((to_np(rgb) != -7.0).any(axis=1))
+    np.testing.assert_array_equal(changed, np.arange(4))
+    assert int(to_np(slots.err)[0]) & starnt.DERR_LIST
+
+
+def test_renderer_patches_untrusted_pixels(starnt, gpu, sg, oracle_mod):
+    """Renderer.interpolated_frame with the frame's fragments: trusted pixels
+    are the gather, untrusted ones the full real render of that frame, and the
+    frame is closer to the exact composite than the gather alone."""
+    from paper_2606_16747_amd import frames as fm
+    sc = sg.Scene("c2_1080p", width=320, height=180, num_tris=300)
+    W, H = 320, 180
+    P = W * H
+    Ws, bs = sg.init_mlp((16, 32, 32, 3), out_bias=0.05)
+    mlp = starnt.DeviceMlp(Ws, bs, starnt.F32)
+    rend = fm.Renderer(W, H, mlp, depth_tol=0.01)
+    rend.reset()
+    f0, f2 = sc.frame(0), sc.frame(2)
+    out0 = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+    rend.real_frame(starnt.DeviceFrags.from_frame(f0, max_per_pixel=64), out0)
+    mmi = fm.m_minus_i(f0.vp, f2.vp)
+    df2 = starnt.DeviceFrags.from_frame(f2, max_per_pixel=64)
+    gather = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+    rend.interpolated_frame(mmi, gather)
+    patched = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+    rend.interpolated_frame(mmi, patched, frags=df2)
+    sync()
+    bad = _list_np(rend.list, rend.list_count)
+    assert 0 < len(bad) < P // 2
+    good = np.ones(P, bool)
+    good[bad] = False
+    np.testing.assert_array_equal(to_np(patched)[good], to_np(gather)[good])
+    # untrusted pixels: the full-resolution real render of frame 2
+    full, _ = _full_render(starnt, df2, mlp, (1.0, 1.0, 1.0))
+    sync()
+    np.testing.assert_array_equal(to_np(patched)[bad], to_np(full)[bad])
+    exact = oracle_mod.frame_of(f2, want=("rgb",))["rgb"]
+    assert oracle_mod.psnr(to_np(patched), exact) > oracle_mod.psnr(to_np(gather), exact)

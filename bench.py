@@ -138,7 +138,7 @@ def profile_summary(d, calib_mb):
     write_b = float(np.mean(wk)) * 1024 * wfac
     alg = bench["trace"]["roofline"]["algorithmic_bytes_per_launch"]
     rec = {
-        "kernel": "starnt_features (features_kernel<false>), 1080p sequence, timed region",
+        "kernel": "starnt_features (features_kernel<false, false>), 1080p sequence, timed region",
         "sources": list(FEATURE_SOURCES),
         "source_sha256": feature_sources_sha256(),
         "launches": i1 - i0,
@@ -535,6 +535,56 @@ def main():
         d = (outs[t] - exact[t]).double()
         sel_psnr.append(10 * np.log10(1.0 / float((d * d).mean())))
 
+    # interpolated frames whose untrusted pixels (source outside the frame or
+    # showing another surface, window-space depth tolerance 0.01) are
+    # re-rendered from the frame's own fragment lists
+    patr = fm.Renderer(W, H, mlp, base=64, bg=bg, depth_tol=0.01)
+    pcounts = []
+
+    def patch_step(record=False):
+        patr.reset()
+        for t in range(NF):
+            if t % 2 == 0:
+                patr.real_frame(frags[t], outs[t])
+            else:
+                patr.interpolated_frame(mmis[t], outs[t], frags=frags[t])
+                if record:
+                    pcounts.append(patr.list_count.clone())
+
+    for _ in range(2):
+        patch_step()
+    torch.cuda.synchronize()
+    q0 = torch.cuda.Event(enable_timing=True)
+    q1 = torch.cuda.Event(enable_timing=True)
+    q0.record()
+    for _ in range(max(3, args.steps // 4)):
+        patch_step()
+    q1.record()
+    torch.cuda.synchronize()
+    patch_step_ms = q0.elapsed_time(q1) / max(3, args.steps // 4)
+    pnames = {}
+
+    def timer_patch(name, fn):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        pnames.setdefault(name, []).append((a, b))
+
+    patr.timer = timer_patch
+    patch_step(record=True)
+    torch.cuda.synchronize()
+    patr.timer = None
+    patch_us = {k: round(1e3 * float(np.mean([a.elapsed_time(b) for a, b in v])), 2) for k, v in pnames.items()}
+    patch_psnr = []
+    for t in range(NF):
+        d = (outs[t] - exact[t]).double()
+        patch_psnr.append(10 * np.log10(1.0 / float((d * d).mean())))
+    patch_frac = [int(c.item()) / P for c in pcounts]
+    log("patched interpolated frames: %.4f ms/frame, interpolated PSNR %.2f dB, patched %s" %
+        (patch_step_ms / NF, float(np.mean(patch_psnr[1::2])), patch_frac))
+
     # ten-versus-five-feature ablation at full resolution (every frame real):
     # quality against the exact composite and the cost of the network pass
     ablation = None
@@ -664,6 +714,12 @@ def main():
         "selective_inference": {"ms_per_frame": round(sel_step_ms / NF, 4),
                                 "psnr_db_mean": round(float(np.mean(sel_psnr)), 2),
                                 "psnr_db_real_frames": round(float(np.mean(sel_psnr[0::2])), 2)},
+        "interpolated_with_patch": {"ms_per_frame": round(patch_step_ms / NF, 4),
+                                    "psnr_db_interpolated_frames": round(float(np.mean(patch_psnr[1::2])), 2),
+                                    "psnr_db_mean": round(float(np.mean(patch_psnr)), 2),
+                                    "patched_pixel_fraction": [round(v, 4) for v in patch_frac],
+                                    "depth_tol": 0.01,
+                                    "kernels_us": patch_us},
         "train": {"steps": args.train_steps, "batch": 65536, "pairs": int(len(x)), "seconds": round(train_s, 3),
                   "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
                   "step_us_16_64_64_3_bf16": round(train_step_us, 1),

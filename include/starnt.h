@@ -180,6 +180,7 @@ typedef struct {
 /* workspace kinds for starnt_workspace_size */
 #define STARNT_WS_QUADTREE 1
 #define STARNT_WS_TRAIN 2
+#define STARNT_WS_REPROJECT 3
 
 /* ======================================================================== */
 
@@ -296,14 +297,16 @@ int starnt_reproject(const float* rgb_prev, const float* d1_prev, int32_t width,
  * cannot fill are rendered afresh). Same gather as starnt_reproject, plus a
  * depth test at the source: with z' = h_z / h_w the reprojected depth,
  * src[p] = -2 where |d1_prev[q] - z'| > depth_tol (the source shows another
- * surface); depth_tol = 0 disables the test. Every pixel with src[p] < 0 is
- * appended to list (device uint32 [width*height], the caller's) and
- * *list_count (device uint32) receives their number; the call clears it
- * first, on the stream. The list's order varies from run to run, its set of
- * pixels does not. src may be NULL; depth_tol must be finite and >= 0. */
+ * surface); depth_tol = 0 disables the test. The pixels with src[p] < 0 are
+ * written to list (device uint32 [width*height], the caller's) in increasing
+ * pixel order, and *list_count (device uint32) receives their number; the
+ * compaction is deterministic (no atomics). src may be NULL; depth_tol must
+ * be finite and >= 0.
+ * Workspace: starnt_workspace_size(STARNT_WS_REPROJECT, W, H, 0) bytes,
+ * 256-byte aligned (EINVAL otherwise; ENOMEM when smaller). */
 int starnt_reproject_check(const float* rgb_prev, const float* d1_prev, int32_t width, int32_t height,
                            const float* m_minus_i, float depth_tol, float* rgb_out, int32_t* src, uint32_t* list,
-                           uint32_t* list_count, void* stream);
+                           uint32_t* list_count, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Re-render the listed pixels of a frame from its fragment lists (Sec. 3.3,
  * the untrusted pixels of an interpolated frame): passes 1-3 at full

@@ -23,7 +23,7 @@ F32, F16, BF16, FP8 = 0, 1, 2, 3
 MODE_LEARNED, MODE_F0, MODE_FAVG, MODE_EXACT = 0, 1, 2, 3
 NET_STARNT, NET_DFAOIT = 0, 1
 BASE_WBOIT, BASE_OVER_LIST = 0, 1
-WS_QUADTREE, WS_TRAIN = 1, 2
+WS_QUADTREE, WS_TRAIN, WS_REPROJECT = 1, 2, 3
 DERR_DEPTH, DERR_ALPHA, DERR_COUNT, DERR_LIST = 1, 2, 4, 8
 STATUS = {0: "OK", 1: "EINVAL", 2: "ERANGE", 3: "ENOMEM", 4: "EHIP", 5: "EUNSUPPORTED"}
 
@@ -113,7 +113,7 @@ def _load():
     lib.starnt_reproject.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), _P,
                                      _P, _P]
     lib.starnt_reproject_check.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_float),
-                                           ctypes.c_float, _P, _P, _P, _P, _P]
+                                           ctypes.c_float, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
     lib.starnt_patch.argtypes = [ctypes.POINTER(Frags), ctypes.POINTER(Mlp), _P, _P, ctypes.POINTER(Feats),
                                  ctypes.POINTER(ctypes.c_float), _P, _P]
     lib.starnt_train_step.argtypes = [ctypes.POINTER(Train), _P, _P, ctypes.c_int32, ctypes.POINTER(Adam), _P, _P,
@@ -337,11 +337,13 @@ def starnt_reproject(rgb_prev, d1_prev, width, height, m_minus_i, rgb_out, src=N
 
 
 def starnt_reproject_check(rgb_prev, d1_prev, width, height, m_minus_i, depth_tol, rgb_out, src, lst, count,
-                           stream=None):
+                           workspace, stream=None):
+    """workspace: starnt_workspace_size(WS_REPROJECT, width, height) bytes."""
     m = np.asarray(m_minus_i, np.float32).ravel()
     mc = (ctypes.c_float * 16)(*[float(v) for v in m])
     _check(lib.starnt_reproject_check(_ptr(rgb_prev), _ptr(d1_prev), int(width), int(height), mc, float(depth_tol),
-                                      _ptr(rgb_out), _ptr(src), _ptr(lst), _ptr(count), _stream(stream)))
+                                      _ptr(rgb_out), _ptr(src), _ptr(lst), _ptr(count), _ptr(workspace),
+                                      workspace.numel() * workspace.element_size(), _stream(stream)))
 
 
 def starnt_patch(frags, mlp: DeviceMlp, lst, count, slots: FeatBuffers, bg, rgb, stream=None):
@@ -376,7 +378,7 @@ def starnt_grid_dim(n, s):
     return int(lib.starnt_grid_dim(int(n), float(s)))
 
 
-def starnt_workspace_size(kind, a, b, c):
+def starnt_workspace_size(kind, a, b, c=0):
     return int(lib.starnt_workspace_size(int(kind), int(a), int(b), int(c)))
 
 

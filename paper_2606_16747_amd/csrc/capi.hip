@@ -210,7 +210,7 @@ int starnt_reproject(const float* rgb_prev, const float* d1_prev, int32_t width,
 
 int starnt_reproject_check(const float* rgb_prev, const float* d1_prev, int32_t width, int32_t height,
                            const float* m_minus_i, float depth_tol, float* rgb_out, int32_t* src, uint32_t* list,
-                           uint32_t* list_count, void* stream) {
+                           uint32_t* list_count, void* workspace, size_t workspace_bytes, void* stream) {
   int rc = check_frame(width, height, "starnt_reproject_check");
   if (rc) return rc;
   if (!rgb_prev || !d1_prev || !m_minus_i || !rgb_out || !list || !list_count)
@@ -220,8 +220,13 @@ int starnt_reproject_check(const float* rgb_prev, const float* d1_prev, int32_t 
     if (!std::isfinite(m_minus_i[i])) return fail(STARNT_EINVAL, "starnt_reproject_check: non-finite matrix");
   if (!std::isfinite(depth_tol) || depth_tol < 0.0f)
     return fail(STARNT_EINVAL, "starnt_reproject_check: depth_tol must be finite and >= 0");
+  if (!workspace) return fail(STARNT_EINVAL, "starnt_reproject_check: NULL workspace");
+  if (workspace_bytes < reproject_ws_bytes(width, height))
+    return fail(STARNT_ENOMEM, "starnt_reproject_check: workspace smaller than starnt_workspace_size");
+  if (reinterpret_cast<uintptr_t>(workspace) & 255)
+    return fail(STARNT_EINVAL, "starnt_reproject_check: workspace must be 256-byte aligned");
   return launch_reproject(rgb_prev, d1_prev, width, height, m_minus_i, rgb_out, src, as_stream(stream), depth_tol,
-                          list, list_count);
+                          list, list_count, workspace);
 }
 
 int starnt_patch(const starnt_frags* frags, const starnt_mlp* mlp, const uint32_t* list,
@@ -293,6 +298,7 @@ int32_t starnt_grid_dim(int32_t n, double s) {
 size_t starnt_workspace_size(int32_t kind, int64_t a, int64_t b, int64_t c) {
   if (kind == STARNT_WS_QUADTREE) return quadtree_ws_bytes(a, b, c);
   if (kind == STARNT_WS_TRAIN) return train_ws_bytes(a, b, c);
+  if (kind == STARNT_WS_REPROJECT) return reproject_ws_bytes(a, b);
   return 0;
 }
 

@@ -129,7 +129,8 @@ int launch_quadtree(const float* rgb, const uint32_t* count, int W, int H, const
 size_t quadtree_ws_bytes(int64_t W, int64_t H, int64_t base);
 int launch_reproject(const float* rgb_prev, const float* d1_prev, int W, int H, const float mmi[16],
                      float* rgb_out, int32_t* src, hipStream_t s, float tol = 0.0f, uint32_t* list = nullptr,
-                     uint32_t* list_n = nullptr);
+                     uint32_t* list_n = nullptr, void* ws = nullptr);
+size_t reproject_ws_bytes(int64_t W, int64_t H);
 int launch_features_list(const starnt_frags& f, const uint32_t* list, const uint32_t* list_n,
                          const starnt_feats& slots, hipStream_t s);
 int launch_infer_patch(const starnt_mlp& m, const starnt_feats& slots, const uint32_t* list,

@@ -9,12 +9,20 @@
 // those whose source pixel's first-fragment depth differs from the
 // reprojected depth z' = h_z / h_w by more than the tolerance (the source
 // shows another surface: a disocclusion or a depth edge), src = -2. Untrusted
-// pixels are appended to a list for re-rendering; a wave takes its slots with
-// one atomic, so the list's order varies between runs, its contents do not.
+// pixels are compacted into a list in increasing pixel order for
+// re-rendering, without atomics (thousands of waves appending to one counter
+// serialise on it): the gather writes one ballot mask per wave and one count
+// per block, a single block scans the block counts, and a scatter kernel
+// writes each wave's pixels at its block offset plus the counts of the
+// block's earlier waves.
 #include "internal.h"
 
 namespace starnt {
 namespace {
+
+constexpr int kBlock = 256;               // pixels (threads) per block
+constexpr int kWaves = kBlock / 64;       // waves per block
+constexpr int kScanThreads = 1024;
 
 struct Mat4 {
   float m[16];
@@ -28,70 +36,130 @@ struct ReprojArgs {
   float* out;
   int32_t* src;
   float tol;          // depth tolerance, 0: no depth test
-  uint32_t* list;     // untrusted pixels (optional)
-  uint32_t* list_n;   // their number, zero on entry
+  uint64_t* mask;     // per wave: untrusted lanes (trust test only)
+  uint32_t* bcount;   // per block: untrusted pixels (trust test only)
 };
 
-__global__ void clear_count_kernel(uint32_t* n) { *n = 0u; }
+__device__ __forceinline__ uint32_t popc64(uint64_t v) { return (uint32_t)__builtin_popcountll(v); }
 
-__global__ __launch_bounds__(256) void reproject_kernel(ReprojArgs a) {
+__global__ __launch_bounds__(kBlock) void reproject_kernel(ReprojArgs a) {
   const int P = a.W * a.H;
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= P) return;
-  int px, py;
-  pixel_xy(p, a.W, px, py);
-  const float X0 = (2.0f * px + 1.0f) / (float)a.W - 1.0f;
-  const float X1 = 1.0f - (2.0f * py + 1.0f) / (float)a.H;
-  const float X2 = a.d1[p];
-  const float* d = a.d.m;
-  // (M - I) X : the change of the homogeneous coordinates
-  const float dx = fmaf(d[0], X0, fmaf(d[1], X1, fmaf(d[2], X2, d[3])));
-  const float dy = fmaf(d[4], X0, fmaf(d[5], X1, fmaf(d[6], X2, d[7])));
-  const float dz = fmaf(d[8], X0, fmaf(d[9], X1, fmaf(d[10], X2, d[11])));
-  const float dw = fmaf(d[12], X0, fmaf(d[13], X1, fmaf(d[14], X2, d[15])));
-  const float w = 1.0f + dw;
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  const bool valid = p < P;
   int q = -1;
-  int s = p;
-  if (w > 0.0f) {
-    // u - x = (dx - x dw) / w, in pixels: (u - x) W / 2; same for v (y up)
-    const float ox = (dx - X0 * dw) / w * (0.5f * a.W);
-    const float oy = (dy - X1 * dw) / w * (0.5f * a.H);
-    // displacement in whole pixels, bounded so the integer conversion is safe
-    const float fx = fminf(fmaxf(floorf(ox + 0.5f), -1e8f), 1e8f);
-    const float fy = fminf(fmaxf(floorf(0.5f - oy), -1e8f), 1e8f);
-    const long long qx = px + (long long)fx, qy = py + (long long)fy;
-    if (qx >= 0 && qx < a.W && qy >= 0 && qy < a.H) {
-      q = (int)(qy * a.W + qx);
-      // reprojected depth against the depth the source pixel holds
-      if (a.tol > 0.0f && fabsf(a.d1[q] - (X2 + dz) / w) > a.tol) q = -2;
+  if (valid) {
+    int px, py;
+    pixel_xy(p, a.W, px, py);
+    const float X0 = (2.0f * px + 1.0f) / (float)a.W - 1.0f;
+    const float X1 = 1.0f - (2.0f * py + 1.0f) / (float)a.H;
+    const float X2 = a.d1[p];
+    const float* d = a.d.m;
+    // (M - I) X : the change of the homogeneous coordinates
+    const float dx = fmaf(d[0], X0, fmaf(d[1], X1, fmaf(d[2], X2, d[3])));
+    const float dy = fmaf(d[4], X0, fmaf(d[5], X1, fmaf(d[6], X2, d[7])));
+    const float dz = fmaf(d[8], X0, fmaf(d[9], X1, fmaf(d[10], X2, d[11])));
+    const float dw = fmaf(d[12], X0, fmaf(d[13], X1, fmaf(d[14], X2, d[15])));
+    const float w = 1.0f + dw;
+    int s = p;
+    if (w > 0.0f) {
+      // u - x = (dx - x dw) / w, in pixels: (u - x) W / 2; same for v (y up)
+      const float ox = (dx - X0 * dw) / w * (0.5f * a.W);
+      const float oy = (dy - X1 * dw) / w * (0.5f * a.H);
+      // displacement in whole pixels, bounded so the integer conversion is safe
+      const float fx = fminf(fmaxf(floorf(ox + 0.5f), -1e8f), 1e8f);
+      const float fy = fminf(fmaxf(floorf(0.5f - oy), -1e8f), 1e8f);
+      const long long qx = px + (long long)fx, qy = py + (long long)fy;
+      if (qx >= 0 && qx < a.W && qy >= 0 && qy < a.H) {
+        q = (int)(qy * a.W + qx);
+        // reprojected depth against the depth the source pixel holds
+        if (a.tol > 0.0f && fabsf(a.d1[q] - (X2 + dz) / w) > a.tol) q = -2;
+      }
+      // outside the frame: edge extension (src stays -1)
+      const int cx = (int)(qx < 0 ? 0 : (qx > a.W - 1 ? a.W - 1 : qx));
+      const int cy = (int)(qy < 0 ? 0 : (qy > a.H - 1 ? a.H - 1 : qy));
+      s = cy * a.W + cx;
     }
-    // outside the frame: edge extension (src stays -1)
-    const int cx = (int)(qx < 0 ? 0 : (qx > a.W - 1 ? a.W - 1 : qx));
-    const int cy = (int)(qy < 0 ? 0 : (qy > a.H - 1 ? a.H - 1 : qy));
-    s = cy * a.W + cx;
+    a.out[3 * (size_t)p + 0] = a.rgb[3 * (size_t)s + 0];
+    a.out[3 * (size_t)p + 1] = a.rgb[3 * (size_t)s + 1];
+    a.out[3 * (size_t)p + 2] = a.rgb[3 * (size_t)s + 2];
+    if (a.src) a.src[p] = q;
   }
-  a.out[3 * (size_t)p + 0] = a.rgb[3 * (size_t)s + 0];
-  a.out[3 * (size_t)p + 1] = a.rgb[3 * (size_t)s + 1];
-  a.out[3 * (size_t)p + 2] = a.rgb[3 * (size_t)s + 2];
-  if (a.src) a.src[p] = q;
-  if (a.list) {
-    const bool bad = q < 0;
-    const uint64_t m = __builtin_amdgcn_ballot_w64(bad);
-    if (m != 0) {
-      const int lane = (int)__lane_id();
-      const int leader = __builtin_ctzll(m);
-      uint32_t base = 0;
-      if (lane == leader) base = atomicAdd(a.list_n, (uint32_t)__builtin_popcountll(m));
-      base = __shfl(base, leader);
-      if (bad) a.list[base + (uint32_t)__builtin_popcountll(m & ((1ull << lane) - 1ull))] = (uint32_t)p;
+  if (a.mask) {  // uniform over the launch
+    __shared__ uint32_t s_cnt[kWaves];
+    const uint64_t m = __builtin_amdgcn_ballot_w64(valid && q < 0);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // lane 0 holds the wave's lowest pixel, so it is valid iff any lane is
+    if (lane == 0) {
+      if (valid) a.mask[p >> 6] = m;
+      s_cnt[wave] = popc64(m);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t c = 0;
+      for (int i = 0; i < kWaves; ++i) c += s_cnt[i];
+      a.bcount[blockIdx.x] = c;
     }
   }
 }
 
+// exclusive scan of the block counts in one block; the total is the list's
+// length. Thread t owns a contiguous run of blocks.
+__global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(const uint32_t* bcount, int nb, uint32_t* boff,
+                                                                  uint32_t* total) {
+  __shared__ uint32_t s_sum[kScanThreads];
+  const int t = threadIdx.x;
+  const int per = (nb + kScanThreads - 1) / kScanThreads;
+  const int b0 = t * per, b1 = min(b0 + per, nb);
+  uint32_t mine = 0;
+  for (int b = b0; b < b1; ++b) mine += bcount[b];
+  s_sum[t] = mine;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over the threads' sums
+  for (int k = 1; k < kScanThreads; k <<= 1) {
+    const uint32_t v = t >= k ? s_sum[t - k] : 0u;
+    __syncthreads();
+    s_sum[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = s_sum[t] - mine;
+  for (int b = b0; b < b1; ++b) {
+    boff[b] = run;
+    run += bcount[b];
+  }
+  if (t == kScanThreads - 1) *total = s_sum[t];
+}
+
+// each wave writes its untrusted pixels at the block offset plus the counts
+// of the block's earlier waves, in lane (pixel) order
+__global__ __launch_bounds__(kBlock) void scatter_list_kernel(const uint64_t* mask, const uint32_t* boff, int P,
+                                                               uint32_t* list) {
+  __shared__ uint32_t s_cnt[kWaves];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int w = blockIdx.x * kWaves + wave;  // global wave index
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  const bool live = w * 64 < P;              // the wave covers a pixel
+  const uint64_t m = live ? mask[w] : 0ull;
+  if (lane == 0) s_cnt[wave] = popc64(m);
+  __syncthreads();
+  uint32_t base = boff[blockIdx.x];
+  for (int i = 0; i < wave; ++i) base += s_cnt[i];
+  if ((m >> lane) & 1ull) list[base + popc64(m & ((1ull << lane) - 1ull))] = (uint32_t)p;
+}
+
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
 }  // namespace
 
+size_t reproject_ws_bytes(int64_t W, int64_t H) {
+  if (W <= 0 || H <= 0) return 0;
+  const int64_t P = W * H;
+  const int64_t nb = (P + kBlock - 1) / kBlock;
+  return align256((size_t)((P + 63) / 64) * 8) + 2 * align256((size_t)nb * 4);
+}
+
 int launch_reproject(const float* rgb_prev, const float* d1_prev, int W, int H, const float mmi[16],
-                     float* rgb_out, int32_t* src, hipStream_t s, float tol, uint32_t* list, uint32_t* list_n) {
+                     float* rgb_out, int32_t* src, hipStream_t s, float tol, uint32_t* list, uint32_t* list_n,
+                     void* ws) {
   ReprojArgs a;
   a.W = W;
   a.H = H;
@@ -101,12 +169,23 @@ int launch_reproject(const float* rgb_prev, const float* d1_prev, int W, int H, 
   a.out = rgb_out;
   a.src = src;
   a.tol = tol;
-  a.list = list;
-  a.list_n = list_n;
   const int P = W * H;
-  // a fill kernel rather than a memset, so a captured graph replays it safely
-  if (list) hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(1), 0, s, list_n);
-  hipLaunchKernelGGL(reproject_kernel, dim3((P + 255) / 256), dim3(256), 0, s, a);
+  const int nb = (P + kBlock - 1) / kBlock;
+  uint32_t* boff = nullptr;
+  if (list) {
+    uint8_t* base = static_cast<uint8_t*>(ws);
+    a.mask = reinterpret_cast<uint64_t*>(base);
+    a.bcount = reinterpret_cast<uint32_t*>(base + align256((size_t)((P + 63) / 64) * 8));
+    boff = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(a.bcount) + align256((size_t)nb * 4));
+  } else {
+    a.mask = nullptr;
+    a.bcount = nullptr;
+  }
+  hipLaunchKernelGGL(reproject_kernel, dim3(nb), dim3(kBlock), 0, s, a);
+  if (list) {
+    hipLaunchKernelGGL(scan_counts_kernel, dim3(1), dim3(kScanThreads), 0, s, a.bcount, nb, boff, list_n);
+    hipLaunchKernelGGL(scatter_list_kernel, dim3(nb), dim3(kBlock), 0, s, a.mask, boff, P, list);
+  }
   STARNT_LAUNCH_CHECK("starnt_reproject launch");
   return STARNT_OK;
 }

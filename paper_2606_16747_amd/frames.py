@@ -13,7 +13,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import (MODE_EXACT, MODE_LEARNED, WS_QUADTREE, DeviceFrags, DeviceMlp, FeatBuffers, QtParams,
+from . import (MODE_EXACT, MODE_LEARNED, WS_QUADTREE, WS_REPROJECT, DeviceFrags, DeviceMlp, FeatBuffers, QtParams,
                starnt_composite, starnt_features, starnt_infer_composite, starnt_infer_composite_sel,
                starnt_interval_init,
                starnt_interval_next, starnt_interval_report, starnt_patch, starnt_quadtree, starnt_reproject,
@@ -59,6 +59,7 @@ class Renderer:
         self.list = torch.empty(P, dtype=torch.int32, device=device)
         self.list_count = torch.zeros(1, dtype=torch.int32, device=device)
         self.slots = None
+        self.ws_reproj = workspace(starnt_workspace_size(WS_REPROJECT, self.W, self.H), device)
         self.device = device
         self.timer = None  # optional callable(name, fn) wrapping each call
 
@@ -107,7 +108,7 @@ class Renderer:
             self.slots = FeatBuffers(self.W * self.H, 1, self.device)
         self._call("reproject", lambda: starnt_reproject_check(self.rgb_real, self.feats.d1, self.W, self.H, mmi,
                                                                self.depth_tol, out, None, self.list,
-                                                               self.list_count, stream))
+                                                               self.list_count, self.ws_reproj, stream))
         self._call("patch", lambda: starnt_patch(frags, self.mlp, self.list, self.list_count, self.slots, self.bg,
                                                  out, stream))
         return out

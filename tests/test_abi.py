@@ -100,12 +100,18 @@ def test_host_validation_rejects_bad_arguments(starnt):
     rc = lib.starnt_reproject_check
     rc.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                    ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                   ctypes.c_void_p]
-    assert rc(16, 32, 8, 8, m, -0.5, 48, None, 64, 80, None) == 1  # negative tolerance
+                   ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    need = starnt.starnt_workspace_size(starnt.WS_REPROJECT, 8, 8)
+    assert need >= 8 + 2 * 4
+    assert rc(16, 32, 8, 8, m, -0.5, 48, None, 64, 80, 256, need, None) == 1  # negative tolerance
     assert b"depth_tol" in lib.starnt_last_error()
-    assert rc(16, 32, 8, 8, m, float("inf"), 48, None, 64, 80, None) == 1
-    assert rc(16, 32, 8, 8, m, 0.01, 48, None, None, 80, None) == 1  # no list
-    assert rc(16, 16, 8, 8, m, 0.01, 16, None, 64, 80, None) == 1    # output aliases input
+    assert rc(16, 32, 8, 8, m, float("inf"), 48, None, 64, 80, 256, need, None) == 1
+    assert rc(16, 32, 8, 8, m, 0.01, 48, None, None, 80, 256, need, None) == 1  # no list
+    assert rc(16, 16, 8, 8, m, 0.01, 16, None, 64, 80, 256, need, None) == 1    # output aliases input
+    assert rc(16, 32, 8, 8, m, 0.01, 48, None, 64, 80, 256, need - 1, None) == 3  # workspace too small
+    assert rc(16, 32, 8, 8, m, 0.01, 48, None, 64, 80, 272, need, None) == 1      # misaligned workspace
+    assert b"aligned" in lib.starnt_last_error()
+    assert rc(16, 32, 8, 8, m, 0.01, 48, None, 64, 80, None, need, None) == 1
     fr = starnt.Frags(8, 8, 16, 16, 16, 0, 16, 10, 1)
     slots = starnt.Feats(4, 1, 16, 16, 16, 16, 16, None, 16, None)
     mlp = starnt.Mlp(16, 32, 32, 3, 0, 16, 16, 16, 16, 16, 16, None)

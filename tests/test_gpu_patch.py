@@ -25,8 +25,8 @@ def test_reproject_check_matches_oracle(starnt, gpu, sg, oracle_mod, t1, tol):
     """Trust codes bit-exact against the FP64 oracle on the same FP32 inputs,
     except where the source coordinate lies within 1e-4 px of a rounding
     boundary or the depth difference within 1e-5 of the tolerance; the list
-    holds exactly the pixels the GPU marked untrusted; the gathered colours are
-    those of the plain reprojection."""
+    holds exactly the pixels the GPU marked untrusted, in increasing order; the
+    gathered colours are those of the plain reprojection."""
     sc = sg.Scene("c2_1080p", width=640, height=360, num_tris=400)
     W, H = 640, 360
     P = W * H
@@ -39,8 +39,10 @@ def test_reproject_check_matches_oracle(starnt, gpu, sg, oracle_mod, t1, tol):
     out = torch.empty(P, 3, dtype=torch.float32, device="cuda")
     src = torch.empty(P, dtype=torch.int32, device="cuda")
     lst = torch.full((P,), -1, dtype=torch.int32, device="cuda")
-    count = torch.full((1,), 12345, dtype=torch.int32, device="cuda")  # the call clears it
-    starnt.starnt_reproject_check(rgb, d1, W, H, mmi, tol, out, src, lst, count)
+    count = torch.full((1,), 12345, dtype=torch.int32, device="cuda")  # the call overwrites it
+    ws = starnt.workspace(starnt.starnt_workspace_size(starnt.WS_REPROJECT, W, H), "cuda")
+    ws.fill_(0xA5)  # stale contents must not matter
+    starnt.starnt_reproject_check(rgb, d1, W, H, mmi, tol, out, src, lst, count, ws)
     plain = torch.empty(P, 3, dtype=torch.float32, device="cuda")
     starnt.starnt_reproject(rgb, d1, W, H, mmi, plain)
     sync()
@@ -50,12 +52,50 @@ def test_reproject_check_matches_oracle(starnt, gpu, sg, oracle_mod, t1, tol):
     assert ok.mean() > 0.99
     got = to_np(src)
     np.testing.assert_array_equal(got[ok], code[ok])
-    np.testing.assert_array_equal(_list_np(lst, count), np.flatnonzero(got < 0))
+    n = int(to_np(count)[0])
+    np.testing.assert_array_equal(to_np(lst)[:n].astype(np.int64), np.flatnonzero(got < 0))
     assert torch.equal(out, plain)
     if tol > 0:
         assert (got == -2).mean() > 0.01
     else:
         assert not (got == -2).any()
+
+
+@pytest.mark.parametrize("W,H,shift", [(37, 23, 3.3), (1, 1, 0.0), (300, 7, -2.7), (1024, 600, 1.6),
+                                        (64, 4, 1000.0), (97, 61, 0.0)])
+def test_reproject_check_compaction_ragged(starnt, gpu, oracle_mod, W, H, shift):
+    """Frames that are not whole waves or blocks, a scan with several blocks per
+    thread (1024x600), every pixel untrusted (a shift off the frame) and none
+    (identity): count and list agree with the codes and with the oracle."""
+    rng = np.random.default_rng(W * 7 + H)
+    P = W * H
+    # piecewise-constant depth in vertical bands, so a shift crosses edges
+    band = rng.uniform(0.85, 1.0, size=(W + 7) // 8)
+    d1n = np.repeat(band, 8)[:W][None, :].repeat(H, 0).ravel().astype(np.float32)
+    mmi = np.zeros((4, 4), np.float32)
+    mmi[0, 3] = 2.0 * shift / W
+    rgb = torch.from_numpy(rng.random((P, 3)).astype(np.float32)).cuda()
+    d1 = torch.from_numpy(d1n).cuda()
+    out = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+    src = torch.empty(P, dtype=torch.int32, device="cuda")
+    lst = torch.full((P,), -1, dtype=torch.int32, device="cuda")
+    count = torch.full((1,), 777, dtype=torch.int32, device="cuda")
+    ws = starnt.workspace(starnt.starnt_workspace_size(starnt.WS_REPROJECT, W, H), "cuda")
+    ws.fill_(0x5A)
+    starnt.starnt_reproject_check(rgb, d1, W, H, mmi, 0.01, out, src, lst, count, ws)
+    sync()
+    got = to_np(src)
+    n = int(to_np(count)[0])
+    np.testing.assert_array_equal(to_np(lst)[:n].astype(np.int64), np.flatnonzero(got < 0))
+    code, zd = oracle_mod.reproject_check(d1n, mmi.astype(np.float64), W, H, 0.01)
+    _, _, margin = oracle_mod.reproject(to_np(rgb), d1n, mmi.astype(np.float64), W, H)
+    ok = margin >= 1e-4
+    assert ok.mean() > 0.99
+    np.testing.assert_array_equal(got[ok], code[ok])
+    if shift == 0.0:
+        assert n == 0
+    if abs(shift) >= W:
+        assert n == P
 
 
 def _full_render(starnt, df, mlp, bg):

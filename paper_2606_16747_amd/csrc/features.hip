@@ -400,7 +400,7 @@ int launch_features_list(const starnt_frags& f, const uint32_t* list, const uint
   // enough quads to fill the chip; each walks the list with a stride
   const int64_t quads = o.width;
   int64_t blocks = (quads * kG + 255) / 256;
-  if (blocks > 2048) blocks = 2048;
+  if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   const dim3 block(256), grid((unsigned)blocks);
   if (f.rgba_dtype == STARNT_F16) hipLaunchKernelGGL(features_list_kernel<true>, grid, block, 0, s, a);

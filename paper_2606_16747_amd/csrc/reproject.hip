@@ -12,17 +12,17 @@
 // pixels are compacted into a list in increasing pixel order for
 // re-rendering, without atomics (thousands of waves appending to one counter
 // serialise on it): the gather writes one ballot mask per wave and one count
-// per block, a single block scans the block counts, and a scatter kernel
-// writes each wave's pixels at its block offset plus the counts of the
-// block's earlier waves.
+// per block; a scatter kernel then writes each wave's pixels at its block's
+// offset, the sum of the earlier blocks' counts, which every scatter block
+// forms itself with one coalesced block-wide sum (no separate scan launch),
+// plus the counts of the block's earlier waves.
 #include "internal.h"
 
 namespace starnt {
 namespace {
 
-constexpr int kBlock = 256;               // pixels (threads) per block
+constexpr int kBlock = 1024;              // pixels (threads) per block
 constexpr int kWaves = kBlock / 64;       // waves per block
-constexpr int kScanThreads = 1024;
 
 struct Mat4 {
   float m[16];
@@ -102,48 +102,32 @@ __global__ __launch_bounds__(kBlock) void reproject_kernel(ReprojArgs a) {
   }
 }
 
-// exclusive scan of the block counts in one block; the total is the list's
-// length. Thread t owns a contiguous run of blocks.
-__global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(const uint32_t* bcount, int nb, uint32_t* boff,
-                                                                  uint32_t* total) {
-  __shared__ uint32_t s_sum[kScanThreads];
-  const int t = threadIdx.x;
-  const int per = (nb + kScanThreads - 1) / kScanThreads;
-  const int b0 = t * per, b1 = min(b0 + per, nb);
-  uint32_t mine = 0;
-  for (int b = b0; b < b1; ++b) mine += bcount[b];
-  s_sum[t] = mine;
-  __syncthreads();
-  // Hillis-Steele inclusive scan over the threads' sums
-  for (int k = 1; k < kScanThreads; k <<= 1) {
-    const uint32_t v = t >= k ? s_sum[t - k] : 0u;
-    __syncthreads();
-    s_sum[t] += v;
-    __syncthreads();
-  }
-  uint32_t run = s_sum[t] - mine;
-  for (int b = b0; b < b1; ++b) {
-    boff[b] = run;
-    run += bcount[b];
-  }
-  if (t == kScanThreads - 1) *total = s_sum[t];
-}
-
-// each wave writes its untrusted pixels at the block offset plus the counts
-// of the block's earlier waves, in lane (pixel) order
-__global__ __launch_bounds__(kBlock) void scatter_list_kernel(const uint64_t* mask, const uint32_t* boff, int P,
-                                                               uint32_t* list) {
+// each wave writes its untrusted pixels, in lane (pixel) order, at the
+// block's offset plus the counts of the block's earlier waves; the last block
+// also writes the list's length
+__global__ __launch_bounds__(kBlock) void scatter_list_kernel(const uint64_t* mask, const uint32_t* bcount, int nb,
+                                                               int P, uint32_t* list, uint32_t* total) {
   __shared__ uint32_t s_cnt[kWaves];
+  __shared__ uint32_t s_part[kWaves];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int w = blockIdx.x * kWaves + wave;  // global wave index
   const int p = blockIdx.x * kBlock + threadIdx.x;
   const bool live = w * 64 < P;              // the wave covers a pixel
   const uint64_t m = live ? mask[w] : 0ull;
-  if (lane == 0) s_cnt[wave] = popc64(m);
+  // offset of this block: sum of the earlier blocks' counts
+  uint32_t part = 0;
+  for (int b = threadIdx.x; b < (int)blockIdx.x; b += kBlock) part += bcount[b];
+  for (int k = 32; k >= 1; k >>= 1) part += __shfl_xor(part, k);
+  if (lane == 0) {
+    s_cnt[wave] = popc64(m);
+    s_part[wave] = part;
+  }
   __syncthreads();
-  uint32_t base = boff[blockIdx.x];
+  uint32_t base = 0;
+  for (int i = 0; i < kWaves; ++i) base += s_part[i];
   for (int i = 0; i < wave; ++i) base += s_cnt[i];
   if ((m >> lane) & 1ull) list[base + popc64(m & ((1ull << lane) - 1ull))] = (uint32_t)p;
+  if (blockIdx.x == nb - 1 && threadIdx.x == kBlock - 1) *total = base + s_cnt[kWaves - 1];
 }
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -154,7 +138,7 @@ size_t reproject_ws_bytes(int64_t W, int64_t H) {
   if (W <= 0 || H <= 0) return 0;
   const int64_t P = W * H;
   const int64_t nb = (P + kBlock - 1) / kBlock;
-  return align256((size_t)((P + 63) / 64) * 8) + 2 * align256((size_t)nb * 4);
+  return align256((size_t)((P + 63) / 64) * 8) + align256((size_t)nb * 4);
 }
 
 int launch_reproject(const float* rgb_prev, const float* d1_prev, int W, int H, const float mmi[16],
@@ -171,21 +155,16 @@ int launch_reproject(const float* rgb_prev, const float* d1_prev, int W, int H, 
   a.tol = tol;
   const int P = W * H;
   const int nb = (P + kBlock - 1) / kBlock;
-  uint32_t* boff = nullptr;
   if (list) {
     uint8_t* base = static_cast<uint8_t*>(ws);
     a.mask = reinterpret_cast<uint64_t*>(base);
     a.bcount = reinterpret_cast<uint32_t*>(base + align256((size_t)((P + 63) / 64) * 8));
-    boff = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(a.bcount) + align256((size_t)nb * 4));
   } else {
     a.mask = nullptr;
     a.bcount = nullptr;
   }
   hipLaunchKernelGGL(reproject_kernel, dim3(nb), dim3(kBlock), 0, s, a);
-  if (list) {
-    hipLaunchKernelGGL(scan_counts_kernel, dim3(1), dim3(kScanThreads), 0, s, a.bcount, nb, boff, list_n);
-    hipLaunchKernelGGL(scatter_list_kernel, dim3(nb), dim3(kBlock), 0, s, a.mask, boff, P, list);
-  }
+  if (list) hipLaunchKernelGGL(scatter_list_kernel, dim3(nb), dim3(kBlock), 0, s, a.mask, a.bcount, nb, P, list, list_n);
   STARNT_LAUNCH_CHECK("starnt_reproject launch");
   return STARNT_OK;
 }

@@ -581,13 +581,31 @@ void launch_f32(const InferArgs& a, hipStream_t s) {
   hipLaunchKernelGGL((infer_f32_kernel<H1, H2, MODE>), dim3((P + 255) / 256), dim3(256), 0, s, a);
 }
 
+// blocks of 256 threads of `kernel` that the device holds at once (the
+// occupancy the register count allows, times the CUs), cached per device
+template <typename K>
+int resident_blocks(K kernel) {
+  static int cache[16] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) dev = 0;
+  if (cache[dev] == 0) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    cache[dev] = per_cu * cus;
+  }
+  return cache[dev];
+}
+
 template <int T1, int T2, bool FP8, int MODE>
 void launch_mfma(const InferArgs& a, hipStream_t s) {
   const int P = a.W * a.H;
   const int steps = (P + 63) / 64;
-  // persistent blocks: a few per CU, each wave walking many 64-pixel steps
+  // persistent blocks, exactly as many as are resident at once: a second
+  // partial round of blocks would run nearly alone at the end
   int blocks = (steps + 3) / 4;
-  if (blocks > 1024) blocks = 1024;
+  const int resident = resident_blocks(infer_mfma_kernel<T1, T2, FP8, MODE>);
+  if (blocks > resident) blocks = resident;
   // a pixel list is usually a small part of the frame: fewer blocks, so each
   // wave's weight set-up serves several steps (measured best at 1080p with
   // 5-10% of the pixels listed)

@@ -322,15 +322,16 @@ __device__ __forceinline__ void pixel(const FeatArgs& a, const Grids& g, int p, 
   if (errf) atomicOr(a.err, errf);
 }
 
+// A block covers 64 pixels of one row (x from the thread, y = blockIdx.y), so
+// no lane divides to find its pixel and y-dependent values are wave-uniform.
 template <bool HALF, bool AVG>
 __global__ __launch_bounds__(256) void features_kernel(FeatArgs a) {
-  const int P = a.W * a.H;
   const int q = threadIdx.x & (kG - 1);
-  const int p = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) / kG);
-  if (p >= P) return;  // whole quads leave together
+  const int x = (int)(blockIdx.x * (256u / kG) + threadIdx.x / kG);
+  const int y = (int)blockIdx.y;
+  if (x >= a.W) return;  // whole quads leave together
+  const int p = y * a.W + x;
   const Grids g = load_grids(a.sched, a.W, a.H);
-  int x, y;
-  pixel_xy(p, a.W, x, y);
   const int i2 = grid_index_of(x, a.W, g.w2), j2 = grid_index_of(y, a.H, g.h2);
   const int i3 = grid_index_of(x, a.W, g.w3), j3 = grid_index_of(y, a.H, g.h3);
   const uint32_t b = a.off[p], e = a.off[p + 1];
@@ -426,8 +427,7 @@ int launch_features(const starnt_frags& f, const starnt_sched* sched, const star
   a.tail = reinterpret_cast<float4*>(o.tail);
   a.sel = reinterpret_cast<uint2*>(o.sel);
   a.err = o.err;
-  const int P = f.width * f.height;
-  const dim3 block(256), grid((unsigned)(((int64_t)P * kG + 255) / 256));
+  const dim3 block(256), grid((unsigned)((f.width + 256 / kG - 1) / (256 / kG)), (unsigned)f.height);
   a.tail_avg = reinterpret_cast<float4*>(o.tail_avg);
   const bool half = f.rgba_dtype == STARNT_F16;
   if (o.tail_avg) {

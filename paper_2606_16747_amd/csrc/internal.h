@@ -23,6 +23,11 @@ int hip_status(hipError_t e, const char* what);
 
 // ---- device helpers -------------------------------------------------------
 
+// a * b for a, b < 2^24 with a product below 2^32, exactly: one full-rate
+// v_mul_u32_u24 (a 32-bit v_mul_lo_u32 takes four issue cycles). Frame and
+// grid sides are at most 16384, so every index product here qualifies.
+__device__ __forceinline__ uint32_t mul24(uint32_t a, uint32_t b) { return __umul24(a, b); }
+
 // floor(n / d) for n < 2^30, 1 <= d < 2^24 and a quotient below 2^15, exactly.
 // The FP32 estimate n * rcp(d) carries a relative error below 2^-22 (n rounded
 // once, the hardware reciprocal within 1 ulp, the product rounded once), so its
@@ -32,7 +37,7 @@ int hip_status(hipError_t e, const char* what);
 __device__ __forceinline__ uint32_t udiv_small(uint32_t n, uint32_t d) {
   const float f = (float)n * __builtin_amdgcn_rcpf((float)d);
   uint32_t q = (uint32_t)f;
-  const int32_t r = (int32_t)(n - q * d);
+  const int32_t r = (int32_t)(n - mul24(q, d));
   q = r < 0 ? q - 1u : (r >= (int32_t)d ? q + 1u : q);
   return q;
 }
@@ -40,7 +45,7 @@ __device__ __forceinline__ uint32_t udiv_small(uint32_t n, uint32_t d) {
 // Pixel coordinates of linear pixel index p in a frame of width W.
 __device__ __forceinline__ void pixel_xy(int p, int W, int& x, int& y) {
   y = (int)udiv_small((uint32_t)p, (uint32_t)W);
-  x = p - y * W;
+  x = p - (int)mul24((uint32_t)y, (uint32_t)W);
 }
 
 // Grid index i of the W_s-sample grid that samples full-resolution coordinate
@@ -51,10 +56,10 @@ __device__ __forceinline__ void pixel_xy(int p, int W, int& x, int& y) {
 // arithmetic is exact.
 __device__ __forceinline__ int grid_index_of(int x, int W, int Ws) {
   if (Ws >= W) return x;
-  const int num = 2 * Ws * x - W;
+  const int num = (int)mul24(2u * Ws, (uint32_t)x) - W;
   const int den = 2 * W;
   const int i = num <= 0 ? 0 : (int)udiv_small((unsigned)num + (unsigned)den - 1u, (unsigned)den);
-  return (i < Ws && (2 * i + 1) * W < 2 * Ws * (x + 1)) ? i : -1;
+  return (i < Ws && mul24(2u * i + 1u, (uint32_t)W) < mul24(2u * Ws, (uint32_t)x + 1u)) ? i : -1;
 }
 
 // Bilinear taps along one axis for full-resolution coordinate x on a W_s grid:
@@ -67,11 +72,11 @@ struct Taps {
 };
 __device__ __forceinline__ Taps axis_taps(int x, int W, int Ws) {
   Taps t;
-  const int num = (2 * x + 1) * Ws - W;  // >= -W
+  const int num = (int)mul24(2u * x + 1u, (uint32_t)Ws) - W;  // >= -W
   const int den = 2 * W;
   // floor division for num >= -den
   const int q = num >= 0 ? (int)udiv_small((unsigned)num, (unsigned)den) : -1;
-  const int r = num - q * den;
+  const int r = q < 0 ? num + den : num - (int)mul24((uint32_t)q, (uint32_t)den);
   t.w1 = (float)r * __builtin_amdgcn_rcpf((float)den);  // 0 exactly when r = 0
   t.i0 = q < 0 ? 0 : (q > Ws - 1 ? Ws - 1 : q);
   t.i1 = q + 1 < 0 ? 0 : (q + 1 > Ws - 1 ? Ws - 1 : q + 1);

@@ -120,6 +120,16 @@ def profile_summary(d, calib_mb):
     feat = con.execute("select dispatch_id, duration from kernels where name like '%features_kernel%' "
                        "order by dispatch_id").fetchall()
     timed = [dur for _, dur in feat[i0:i1]]
+    # every kernel from the first timed features launch to the end of the
+    # step's last frame (the reprojection after the last timed features
+    # launch): the whole timed region's mix
+    t0 = con.execute("select start from kernels where dispatch_id = ?", (feat[i0][0],)).fetchone()[0]
+    tl = con.execute("select start from kernels where dispatch_id = ?", (feat[i1 - 1][0],)).fetchone()[0]
+    t1 = con.execute("select min(end) from kernels where name like '%reproject_kernel%' and start > ?",
+                     (tl,)).fetchone()[0]
+    region = con.execute("select name, count(*), avg(duration), sum(duration) from kernels where start >= ? and "
+                         "end <= ? group by name order by sum(duration) desc", (t0, t1)).fetchall()
+    span_us = (t1 - t0) / 1e3
     top = con.execute("select name, total_calls, total_duration, average, percentage from top_kernels "
                       "order by total_duration desc limit 12").fetchall()
 
@@ -176,7 +186,15 @@ def profile_summary(d, calib_mb):
                  wfac, rec["write_bytes_per_launch"]),
               "* measured HBM traffic / algorithmic bytes: %.3f" % rec["traffic_over_algorithmic"],
               "* calibration: one %d MiB device-to-device copy in each counter run; factor = copy size / counter"
-              % calib_mb, ""]
+              % calib_mb, "",
+              "## Every kernel of the timed region (same trace)", "",
+              "Span of the timed region in the trace: %.1f us for %d steps; kernels busy %.1f us (the rest is "
+              "launch and event-record gaps)." % (span_us, (i1 - i0) // 4, sum(r[3] for r in region) / 1e3), "",
+              "| kernel | launches | avg us | total ms |", "|---|---|---|---|"]
+    for name, calls, avg, tot in region:
+        short = name.replace("(anonymous namespace)::", "").split("(")[0][:90]
+        lines.append("| %s | %d | %.2f | %.2f |" % (short, calls, avg / 1e3, tot / 1e6))
+    lines.append("")
     with open(os.path.join(ROOT, PROFILE_SUMMARY), "w") as f:
         f.write("\n".join(lines))
     print("\n".join(lines))

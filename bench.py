@@ -200,8 +200,10 @@ def profile_summary(d, calib_mb):
     print("\n".join(lines))
 
 
-def cpu_baseline(host, mlp_w, mlp_b, bg, budget_s):
-    """The FP64 oracle on the host, single-threaded, over the same sequence:
+def cpu_baseline(host, mlp_w, mlp_b, bg, budget_s, nthreads=1):
+    """The FP64 oracle on the host over the same sequence (nthreads OpenMP
+    threads in the per-pixel sort, composite and features stage, which
+    dominates; the rest is single-threaded):
     a real frame is the exact sort and over, the tail features, the FP64
     network, the eq (3) composite at full resolution and the quadtree; an
     interpolated frame is the reprojection of the last real one. Frames run in
@@ -219,7 +221,7 @@ def cpu_baseline(host, mlp_w, mlp_b, bg, budget_s):
         fr = host[t % len(host)]
         W, H = fr.width, fr.height
         if t % 2 == 0:
-            o = oracle.frame_of(fr, bg=bg, nthreads=1, want=("rgb", "lay", "tail"))
+            o = oracle.frame_of(fr, bg=bg, nthreads=nthreads, want=("rgb", "lay", "tail"))
             rgb, _, _ = oracle.learned(o["lay"], o["tail"], W, H, (W, H, W, H), net, bg=bg)
             oracle.quadtree(rgb.astype(np.float32), o["lay"][:, 0].astype(np.uint32), W, H, base=64)
             lay1, vp_real = o["lay"][:, 1].astype(np.float32), fr.vp
@@ -231,10 +233,12 @@ def cpu_baseline(host, mlp_w, mlp_b, bg, budget_s):
         if t % 2 == 0 and time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": frags / dt / 1e9, "unit": "Gfrag/s", "cores": 1, "kind": "oracle",
+    how = ("single-threaded" if nthreads == 1 else
+           "sort, composite and features on %d OpenMP threads, the rest single-threaded" % nthreads)
+    return {"value": frags / dt / 1e9, "unit": "Gfrag/s", "cores": nthreads, "kind": "oracle",
             "sample": "%d frames (%d real: sort+over, features, FP64 MLP 16-32-32-3, eq (3), quadtree; %d "
-                      "reprojected) of the 1080p sequence in order, %.1f s single-threaded"
-                      % (frames, (frames + 1) // 2, frames // 2, dt),
+                      "reprojected) of the 1080p sequence in order, %.1f s, %s"
+                      % (frames, (frames + 1) // 2, frames // 2, dt, how),
             "ms_per_frame": dt * 1e3 / frames}
 
 
@@ -438,6 +442,19 @@ def main():
             vals.append(float((d * d).mean()))
         base_psnr[name] = (float(np.mean([10 * np.log10(1.0 / v) for v in vals])), float(np.mean(vals)))
     log("baselines ms/frame %s" % base_ms)
+
+    # spread of the step time: a separate loop with events around every step
+    # (the timed region above has none, so its total is not perturbed)
+    sev = []
+    for _ in range(30):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        star_step()
+        b.record()
+        sev.append((a, b))
+    torch.cuda.synchronize()
+    step_each = np.array([a.elapsed_time(b) for a, b in sev])
 
     # quality of the last timed step against the exact composite
     star_step()
@@ -676,6 +693,12 @@ def main():
 
     # ---- roofline of the fragment pass --------------------------------------
     real_ts = [t for t in range(NF) if t % 2 == 0]
+    # the network's matrix work: algorithmic (unpadded) flops of 5-32-32-3
+    # for every pixel with N >= 3, per real frame, over the measured call
+    h1, h2 = dims[1], dims[2]
+    flop_px = 2 * (5 * h1 + h1 * h2 + h2 * 3)
+    mlp_flops = float(np.mean([flop_px * int((np.diff(host[t].offsets) >= 3).sum()) for t in real_ts]))
+    mlp_s = breakdown["infer_composite"] * 1e-6
     per_step = [feature_pass_bytes(host[t], grids[t]) for t in real_ts]
     alg_bytes = sum(b for b, _ in per_step) * args.steps
     feat_total_s = sum(feat_ms) / 1e3
@@ -723,6 +746,13 @@ def main():
         "baselines": {k: {"ms_per_frame": round(base_ms[k], 4), "psnr_db_mean": round(base_psnr[k][0], 2),
                           "mse_mean": round(base_psnr[k][1], 8)} for k in base_ms},
         "kernel_gfrag_per_s": round(frags_read / feat_total_s / 1e9, 2),
+        "step_ms": {"p5": round(float(np.percentile(step_each, 5)), 4),
+                    "p50": round(float(np.percentile(step_each, 50)), 4),
+                    "p95": round(float(np.percentile(step_each, 95)), 4), "n": int(len(step_each)),
+                    "note": "separate loop, events around each step"},
+        "mlp_mfma": {"flops_per_launch": int(mlp_flops), "achieved_tflops": round(mlp_flops / mlp_s / 1e12, 2),
+                     "peak_tflops_bf16": 2500.0, "frac": round(mlp_flops / mlp_s / 2.5e15, 5),
+                     "note": "2(5*32+32*32+32*3) flop per pixel with N >= 3 over the fused network call's time"},
         "kernels_us": breakdown,
         "grids": {str(k): v for k, v in grids.items()},
         "fp32_mlp_ms_per_frame": round(fp32_step_ms / NF, 4),
@@ -753,6 +783,9 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         res["cpu_baseline"] = cpu_baseline(host, Ws, bs, bg, args.cpu_budget)
+        threads = max(1, min(16, os.cpu_count() or 1))
+        log("cpu baseline (oracle, %d threads) ..." % threads)
+        res["cpu_baseline_threads"] = cpu_baseline(host, Ws, bs, bg, args.cpu_budget, nthreads=threads)
     print(json.dumps(res), flush=True)
 
 

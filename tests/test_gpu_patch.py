@@ -251,3 +251,32 @@ def test_renderer_patches_untrusted_pixels(starnt, gpu, sg, oracle_mod):
     np.testing.assert_array_equal(to_np(patched)[bad], to_np(full)[bad])
     exact = oracle_mod.frame_of(f2, want=("rgb",))["rgb"]
     assert oracle_mod.psnr(to_np(patched), exact) > oracle_mod.psnr(to_np(gather), exact)
+
+
+def test_patch_half_colour_and_sel(starnt, gpu, sg, oracle_mod):
+    """FP16 RGBA input (the 4K workload's format) through the list pass, with
+    the optional selection output: slot i's selected fragments and every
+    patched pixel equal the full-frame pass on the same frame."""
+    fr = sg.Scene("c1_256", half_rgba=True, width=200, height=90, num_tris=50).frame(0)
+    P = fr.num_pixels
+    df = starnt.DeviceFrags.from_frame(fr, max_per_pixel=64)
+    assert df.rgba_dtype == starnt.F16
+    Ws, bs = sg.init_mlp((16, 32, 32, 3), out_bias=0.05)
+    mlp = starnt.DeviceMlp(Ws, bs, starnt.BF16)
+    bg = (0.3, 0.3, 0.3)
+    fb = starnt.FeatBuffers(fr.width, fr.height, with_sel=True)
+    starnt.starnt_features(df, None, fb)
+    full = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+    starnt.starnt_infer_composite(mlp, fb, None, bg, full)
+    pix = np.random.default_rng(9).permutation(P)[: P // 2]
+    lst = torch.from_numpy(pix.astype(np.uint32).view(np.int32)).cuda()
+    count = torch.tensor([len(pix)], dtype=torch.int32, device="cuda")
+    slots = starnt.FeatBuffers(len(pix), 1, with_sel=True)
+    rgb = torch.full((P, 3), -7.0, dtype=torch.float32, device="cuda")
+    starnt.starnt_patch(df, mlp, lst, count, slots, bg, rgb)
+    sync()
+    np.testing.assert_array_equal(to_np(rgb)[pix], to_np(full)[pix])
+    np.testing.assert_array_equal(to_np(slots.sel), to_np(fb.sel)[pix])
+    o = oracle_mod.frame_of(fr)
+    np.testing.assert_array_equal(to_np(slots.sel).view(np.uint32), o["sel"][pix])
+    assert int(to_np(slots.err)[0]) == 0

@@ -470,3 +470,68 @@ def test_features_list_longer_than_a_batch(starnt, gpu, oracle_mod, s3):
         np.testing.assert_allclose(T[:, 1], o["tail"][:, 4], rtol=1e-4, atol=2e-6)
         np.testing.assert_allclose(T[:, 5], o["tail"][:, 0], rtol=1e-6, atol=1e-5)
     assert int(to_np(fb.err)[0]) == 0
+
+
+@pytest.mark.parametrize("W,H", [(16384, 3), (3, 16384)])
+def test_maximum_frame_sides(starnt, gpu, oracle_mod, W, H):
+    """Frames with the largest side the library accepts (16384): every index
+    product and grid division at its largest. Fragment pass at full and at
+    reduced scales, the FP32 learned composite, the quadtree and the
+    reprojection against the oracle."""
+    rng = np.random.default_rng(W + 7 * H)
+    lists = random_lists(rng, W, H, 6)
+    csr = make_csr(lists, W, H)
+    df = starnt.DeviceFrags(*csr, W, H, 6)
+    o = oracle_mod.frame(*csr, W, H)
+    Ws, bs = [rng.normal(0, 0.3, (32, 16)), rng.normal(0, 0.3, (32, 32)), rng.normal(0, 0.3, (3, 32))], \
+        [rng.normal(0, 0.1, 32), rng.normal(0, 0.1, 32), np.full(3, 0.05)]
+    mlp = starnt.DeviceMlp(Ws, bs, starnt.F32)
+    bg = (0.2, 0.5, 0.8)
+    P = W * H
+    rgb = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+    for s2, s3 in ((1.0, 1.0), (0.5, 0.3)):
+        sched = starnt.new_sched(W, H, s2, s3)
+        fb = starnt.FeatBuffers(W, H, with_sel=True)
+        starnt.starnt_features(df, sched, fb)
+        starnt.starnt_infer_composite(mlp, fb, sched, bg, rgb)
+        sync()
+        np.testing.assert_array_equal(sel_np(fb), o["sel"])
+        np.testing.assert_array_equal(to_np(fb.count).view(np.uint32), o["lay"][:, 0].astype(np.uint32))
+        grids = _grids_for(oracle_mod, W, H, s2, s3)
+        s = starnt.read_sched(sched)
+        assert (s["w2"], s["h2"], s["w3"], s["h3"]) == grids
+        want, _, _ = oracle_mod.learned(o["lay"], o["tail"], W, H, grids, oracle_mod.Mlp(Ws, bs),
+                                        oracle_mod.MODE_LEARNED, bg=bg)
+        assert np.abs(to_np(rgb) - want).max() <= TOL
+    # quadtree on the oracle's composite (the same FP32 input on both sides)
+    img = want.astype(np.float32)
+    N = o["lay"][:, 0].astype(np.uint32)
+    base = 64
+    T = ((W + base - 1) // base) * ((H + base - 1) // base)
+    cs = base // 8
+    Cw, Ch = (W + cs - 1) // cs, (H + cs - 1) // cs
+    ws = starnt.workspace(starnt.starnt_workspace_size(starnt.WS_QUADTREE, W, H, base))
+    mask = torch.zeros(T, dtype=torch.int32, device="cuda")
+    level = torch.zeros(Cw * Ch, dtype=torch.uint8, device="cuda")
+    sched = starnt.new_sched(W, H)
+    starnt.starnt_quadtree(torch.from_numpy(img).cuda(), torch.from_numpy(N.view(np.int32)).cuda(), W, H,
+                           starnt.QtParams(base, 0.10, 0.05, 2), None, mask, level, sched, ws)
+    sync()
+    m, lv, hist, D = oracle_mod.quadtree(img, N, W, H, base=base, tau_split=0.10, tau_merge=0.05, k_relax=2)
+    assert not ((np.abs(D - 0.10) < 1e-6) | (np.abs(D - 0.05) < 1e-6)).any()
+    np.testing.assert_array_equal(to_np(mask).view(np.uint32), m)
+    np.testing.assert_array_equal(to_np(level).reshape(Ch, Cw), lv)
+    assert starnt.read_sched(sched)["hist"] == list(hist)
+    # reprojection under a small shift along both axes
+    d1 = o["lay"][:, 1].astype(np.float32)
+    mmi = np.zeros((4, 4), np.float32)
+    mmi[0, 3], mmi[1, 3] = 2.0 * 2.3 / W, 2.0 * 1.7 / H
+    out = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+    src = torch.empty(P, dtype=torch.int32, device="cuda")
+    starnt.starnt_reproject(torch.from_numpy(img).cuda(), torch.from_numpy(d1).cuda(), W, H, mmi, out, src)
+    sync()
+    want_rgb, want_src, margin = oracle_mod.reproject(img, d1, mmi.astype(np.float64), W, H)
+    ok = margin >= 1e-4
+    assert ok.mean() > 0.99
+    np.testing.assert_array_equal(to_np(src)[ok], want_src[ok])
+    np.testing.assert_array_equal(to_np(out)[ok], want_rgb[ok])

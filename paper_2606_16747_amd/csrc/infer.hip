@@ -95,53 +95,67 @@ struct PixRaw {
   uint32_t lvl;  // leaf level of the pixel's quadtree cell (selective only)
 };
 
+// Which grids are at full resolution (wave-uniform, fixed for a launch): a
+// full-resolution grid's sample for pixel p is p itself, so its taps are not
+// computed, only one is loaded, and the blend takes it as it is (the same
+// value the bilinear blend gives with weight 0).
+struct Full {
+  bool g2, g3;
+};
 template <int MODE>
-__device__ __forceinline__ void issue_loads(const InferArgs& a, const Grids& g, int p, PixRaw& r) {
+__device__ __forceinline__ Full full_grids(const InferArgs& a, const Grids& g) {
+  if constexpr (MODE == kPatch) return Full{true, true};
+  return Full{g.w2 == a.W && g.h2 == a.H, g.w3 == a.W && g.h3 == a.H};
+}
+
+template <int MODE>
+__device__ __forceinline__ void issue_loads(const InferArgs& a, const Grids& g, const Full& f, int p, PixRaw& r) {
   r.n = a.count[p];
   if constexpr (MODE == kPatch) {
-    // slot p holds its own full-resolution features: one tap, weight 0
-    const float4 lo = a.tail[2u * p], hi = a.tail[2u * p + 1u];
-    const float4 l2 = a.layer2[p];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      r.t[k] = lo;
-      r.t4[k] = make_float2(hi.x, 0.0f);
-      r.l2[k] = l2;
-    }
+    // slot p holds its own full-resolution features
+    r.t[0] = a.tail[2u * p];
+    r.t4[0] = make_float2(a.tail[2u * p + 1u].x, 0.0f);
+    r.l2[0] = a.layer2[p];
     r.l1 = a.layer1[p];
-    r.wx3 = r.wy3 = r.wx2 = r.wy2 = 0.0f;
     return;
   }
   int x, y;
   pixel_xy(p, a.W, x, y);
-  const Taps tx = axis_taps(x, a.W, g.w3), ty = axis_taps(y, a.H, g.h3);
-  // grid sides are at most 16384, so sample indices fit 32 bits
-  const uint32_t i3[4] = {(uint32_t)(ty.i0 * g.w3 + tx.i0), (uint32_t)(ty.i0 * g.w3 + tx.i1),
-                          (uint32_t)(ty.i1 * g.w3 + tx.i0), (uint32_t)(ty.i1 * g.w3 + tx.i1)};
-  // a full-resolution grid needs only the pixel's own sample (weights 0);
-  // the test is uniform across the wave
-  const int taps3 = (g.w3 == a.W && g.h3 == a.H) ? 1 : 4;
+  if (f.g3) {
+    r.t[0] = a.tail[2u * p];
+    const float4 hi = a.tail[2u * p + 1u];
+    r.t4[0] = make_float2(hi.x, MODE == kDfa ? hi.y : 0.0f);
+    if constexpr (MODE == kDfa) r.av[0] = a.tail_avg[p];
+  } else {
+    const Taps tx = axis_taps(x, a.W, g.w3), ty = axis_taps(y, a.H, g.h3);
+    // grid sides are at most 16384, so sample indices fit 32 bits
+    const uint32_t r0 = mul24((uint32_t)ty.i0, (uint32_t)g.w3), r1 = mul24((uint32_t)ty.i1, (uint32_t)g.w3);
+    const uint32_t i3[4] = {r0 + tx.i0, r0 + tx.i1, r1 + tx.i0, r1 + tx.i1};
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const uint32_t i = i3[k < taps3 ? k : 0];
-    r.t[k] = a.tail[2u * i];
-    const float4 hi = a.tail[2u * i + 1u];
-    r.t4[k] = make_float2(hi.x, MODE == kDfa ? hi.y : 0.0f);
-    if constexpr (MODE == kDfa) r.av[k] = a.tail_avg[i];
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t i = i3[k];
+      r.t[k] = a.tail[2u * i];
+      const float4 hi = a.tail[2u * i + 1u];
+      r.t4[k] = make_float2(hi.x, MODE == kDfa ? hi.y : 0.0f);
+      if constexpr (MODE == kDfa) r.av[k] = a.tail_avg[i];
+    }
+    r.wx3 = tx.w1;
+    r.wy3 = ty.w1;
   }
-  r.wx3 = tx.w1;
-  r.wy3 = ty.w1;
   if constexpr (MODE == kSel) r.lvl = a.level[(y / a.cs) * a.Cw + x / a.cs];
   if constexpr (MODE >= kComp) {
     r.l1 = a.layer1[p];
-    const Taps ux = axis_taps(x, a.W, g.w2), uy = axis_taps(y, a.H, g.h2);
-    const uint32_t i2[4] = {(uint32_t)(uy.i0 * g.w2 + ux.i0), (uint32_t)(uy.i0 * g.w2 + ux.i1),
-                            (uint32_t)(uy.i1 * g.w2 + ux.i0), (uint32_t)(uy.i1 * g.w2 + ux.i1)};
-    const int taps2 = (g.w2 == a.W && g.h2 == a.H) ? 1 : 4;
+    if (f.g2) {
+      r.l2[0] = a.layer2[p];
+    } else {
+      const Taps ux = axis_taps(x, a.W, g.w2), uy = axis_taps(y, a.H, g.h2);
+      const uint32_t r0 = mul24((uint32_t)uy.i0, (uint32_t)g.w2), r1 = mul24((uint32_t)uy.i1, (uint32_t)g.w2);
+      const uint32_t i2[4] = {r0 + ux.i0, r0 + ux.i1, r1 + ux.i0, r1 + ux.i1};
 #pragma unroll
-    for (int k = 0; k < 4; ++k) r.l2[k] = a.layer2[i2[k < taps2 ? k : 0]];
-    r.wx2 = ux.w1;
-    r.wy2 = uy.w1;
+      for (int k = 0; k < 4; ++k) r.l2[k] = a.layer2[i2[k]];
+      r.wx2 = ux.w1;
+      r.wy2 = uy.w1;
+    }
   }
 }
 
@@ -151,7 +165,7 @@ __device__ __forceinline__ float blend4(float p0, float p1, float p2, float p3, 
 }
 
 template <int MODE>
-__device__ __forceinline__ PixIn blend(const PixRaw& r) {
+__device__ __forceinline__ PixIn blend(const PixRaw& r, const Full& f) {
   PixIn in;
   in.n = r.n;
   in.flat = MODE == kSel && r.lvl == 0;
@@ -159,21 +173,40 @@ __device__ __forceinline__ PixIn blend(const PixRaw& r) {
   for (int e = 0; e < 11; ++e) in.x[e] = 0.0f;
   in.tt = 1.0f;
   if (r.n >= 3) {
-    const float4 v = lerp4(lerp4(r.t[0], r.t[1], r.wx3), lerp4(r.t[2], r.t[3], r.wx3), r.wy3);
-    const float cb = blend4(r.t4[0].x, r.t4[1].x, r.t4[2].x, r.t4[3].x, r.wx3, r.wy3);
+    float4 v;
+    float cb;
+    if (f.g3) {
+      v = r.t[0];
+      cb = r.t4[0].x;
+    } else {
+      v = lerp4(lerp4(r.t[0], r.t[1], r.wx3), lerp4(r.t[2], r.t[3], r.wx3), r.wy3);
+      cb = blend4(r.t4[0].x, r.t4[1].x, r.t4[2].x, r.t4[3].x, r.wx3, r.wy3);
+    }
     in.tt = v.y;
     if constexpr (MODE == kDfa) {
       // x = (exact two-layer colour, tail mean colour, tail mean opacity,
       // tail accumulated colour S = Ct A, N); S is formed per tap and then
       // blended like every other input
-      const float4 av = lerp4(lerp4(r.av[0], r.av[1], r.wx3), lerp4(r.av[2], r.av[3], r.wx3), r.wy3);
+      float4 av;
+      float s0, s1, s2;
+      if (f.g3) {
+        av = r.av[0];
+        s0 = r.t[0].z * r.t4[0].y;
+        s1 = r.t[0].w * r.t4[0].y;
+        s2 = r.t4[0].x * r.t4[0].y;
+      } else {
+        av = lerp4(lerp4(r.av[0], r.av[1], r.wx3), lerp4(r.av[2], r.av[3], r.wx3), r.wy3);
+        s0 = blend4(r.t[0].z * r.t4[0].y, r.t[1].z * r.t4[1].y, r.t[2].z * r.t4[2].y, r.t[3].z * r.t4[3].y,
+                    r.wx3, r.wy3);
+        s1 = blend4(r.t[0].w * r.t4[0].y, r.t[1].w * r.t4[1].y, r.t[2].w * r.t4[2].y, r.t[3].w * r.t4[3].y,
+                    r.wx3, r.wy3);
+        s2 = blend4(r.t4[0].x * r.t4[0].y, r.t4[1].x * r.t4[1].y, r.t4[2].x * r.t4[2].y, r.t4[3].x * r.t4[3].y,
+                    r.wx3, r.wy3);
+      }
       in.x[3] = av.x; in.x[4] = av.y; in.x[5] = av.z; in.x[6] = av.w;
-      in.x[7] = blend4(r.t[0].z * r.t4[0].y, r.t[1].z * r.t4[1].y, r.t[2].z * r.t4[2].y, r.t[3].z * r.t4[3].y,
-                       r.wx3, r.wy3);
-      in.x[8] = blend4(r.t[0].w * r.t4[0].y, r.t[1].w * r.t4[1].y, r.t[2].w * r.t4[2].y, r.t[3].w * r.t4[3].y,
-                       r.wx3, r.wy3);
-      in.x[9] = blend4(r.t4[0].x * r.t4[0].y, r.t4[1].x * r.t4[1].y, r.t4[2].x * r.t4[2].y,
-                       r.t4[3].x * r.t4[3].y, r.wx3, r.wy3);
+      in.x[7] = s0;
+      in.x[8] = s1;
+      in.x[9] = s2;
       in.x[10] = v.x;
     } else {
       in.x[0] = v.x; in.x[1] = v.y; in.x[2] = v.z; in.x[3] = v.w;
@@ -182,8 +215,9 @@ __device__ __forceinline__ PixIn blend(const PixRaw& r) {
   }
   if constexpr (MODE >= kComp) {
     in.l1 = r.l1;
-    in.l2 = r.n >= 2 ? lerp4(lerp4(r.l2[0], r.l2[1], r.wx2), lerp4(r.l2[2], r.l2[3], r.wx2), r.wy2)
-                     : make_float4(0.f, 0.f, 0.f, 0.f);
+    in.l2 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (r.n >= 2)
+      in.l2 = f.g2 ? r.l2[0] : lerp4(lerp4(r.l2[0], r.l2[1], r.wx2), lerp4(r.l2[2], r.l2[3], r.wx2), r.wy2);
   }
   if constexpr (MODE == kDfa) {
     const float om1 = 1.0f - in.l1.w;
@@ -196,10 +230,11 @@ __device__ __forceinline__ PixIn blend(const PixRaw& r) {
 }
 
 template <int MODE>
-__device__ __forceinline__ void load_pixel(const InferArgs& a, const Grids& g, int p, bool, PixIn& in) {
+__device__ __forceinline__ void load_pixel(const InferArgs& a, const Grids& g, int p, PixIn& in) {
   PixRaw r;
-  issue_loads<MODE>(a, g, p, r);
-  in = blend<MODE>(r);
+  const Full f = full_grids<MODE>(a, g);
+  issue_loads<MODE>(a, g, f, p, r);
+  in = blend<MODE>(r, f);
 }
 
 // write the tail colour, the eq (3) composite with it, or the DFAOIT
@@ -267,7 +302,7 @@ __global__ __launch_bounds__(256) void infer_f32_kernel(InferArgs a) {
   if (p >= P) return;
   const Grids g = load_grids(a.sched, a.W, a.H);
   PixIn in;
-  load_pixel<MODE>(a, g, p, true, in);
+  load_pixel<MODE>(a, g, p, in);
   float o0 = 0.f, o1 = 0.f, o2 = 0.f;
   if (in.n >= 3 && !in.flat) {
     float h1[H1];
@@ -534,15 +569,16 @@ __global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
   PixRaw r;
   r.n = 0;
   int pn = wave * 64 + lane;
-  if (wave < nsteps && pn < P) issue_loads<MODE>(a, g, pn, r);
+  const Full full = full_grids<MODE>(a, g);
+  if (wave < nsteps && pn < P) issue_loads<MODE>(a, g, full, pn, r);
   for (int st = wave; st < nsteps; st += nwaves) {
     const int p = pn;
     const bool live = p < P;
-    const PixIn in = blend<MODE>(r);
+    const PixIn in = blend<MODE>(r, full);
     const int sn = st + nwaves;
     pn = sn * 64 + lane;
     r.n = 0;
-    if (sn < nsteps && pn < P) issue_loads<MODE>(a, g, pn, r);
+    if (sn < nsteps && pn < P) issue_loads<MODE>(a, g, full, pn, r);
     // group A is the pixels of lanes 0..31, group B those of lanes 32..63; a
     // group's inputs 0..7 go to half 0 and 8..15 to half 1 of the same
     // column, so each lane exchanges one half with its xor-32 partner
@@ -675,7 +711,7 @@ __global__ __launch_bounds__(256) void dfa_inputs_kernel(InferArgs a) {
   if (p >= P) return;
   const Grids g = load_grids(a.sched, a.W, a.H);
   PixIn in;
-  load_pixel<kDfa>(a, g, p, true, in);
+  load_pixel<kDfa>(a, g, p, in);
   float4* o = reinterpret_cast<float4*>(a.out) + 4 * (size_t)p;
   o[0] = make_float4(in.x[0], in.x[1], in.x[2], in.x[3]);
   o[1] = make_float4(in.x[4], in.x[5], in.x[6], in.x[7]);

@@ -177,7 +177,10 @@ typedef struct {
   int32_t step;             /* 1-based Adam step (bias correction)             */
 } starnt_adam;
 
-/* workspace kinds for starnt_workspace_size */
+/* workspace kinds for starnt_workspace_size(kind, a, b, c):
+ *   STARNT_WS_QUADTREE   starnt_quadtree:        a = W, b = H, c = base
+ *   STARNT_WS_TRAIN      starnt_train_step:      a = batch, b = h1, c = h2
+ *   STARNT_WS_REPROJECT  starnt_reproject_check: a = W, b = H (c unused) */
 #define STARNT_WS_QUADTREE 1
 #define STARNT_WS_TRAIN 2
 #define STARNT_WS_REPROJECT 3

@@ -338,8 +338,6 @@ __global__ __launch_bounds__(256) void infer_f32_kernel(InferArgs a) {
 // ---------------------------------------------------------------------------
 // matrix-core paths (BF16 and FP8)
 
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
-typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 typedef long fp8x8;  // 8 E4M3 bytes
 
 // OCP E4M3 with round-to-nearest-even and saturation (hardware convert)
@@ -349,16 +347,6 @@ __device__ __forceinline__ uint32_t e4m3_pack4(float a, float b, float c, float 
   return (uint32_t)w;
 }
 __device__ __forceinline__ float sat448(float v) { return fminf(fmaxf(v, -448.0f), 448.0f); }
-
-// Physical accumulator row r of a 32-row tile (lane half h = (r % 8) / 4,
-// block b = r / 8, element i = r % 4) holds logical hidden unit
-// 16 (b / 2) + 8 h + 4 (b % 2) + i, so that accumulator register v = 4 b + i
-// of lane half h is element (v % 8) of B-operand chunk (v / 8) for the next
-// layer (chunk K index 8 h + e).
-__device__ __forceinline__ int perm_row(int r) {
-  const int b = r >> 3, h = (r >> 2) & 1, i = r & 3;
-  return 16 * (b >> 1) + 8 * h + 4 * (b & 1) + i;
-}
 
 template <bool FP8>
 struct Op {

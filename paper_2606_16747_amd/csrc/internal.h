@@ -85,6 +85,23 @@ __device__ __forceinline__ Taps axis_taps(int x, int W, int Ws) {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// ---- matrix-core operands (v_mfma_f32_32x32x16_bf16) ----------------------
+// A: lane l holds row l % 32, K elements 8 (l / 32) .. + 7; B: lane l holds
+// column l % 32, the same K elements; C/D: lane l holds column l % 32,
+// register v is row 8 (v / 4) + 4 (l / 32) + v % 4.
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+// Physical accumulator row r of a 32-row tile (lane half h = (r % 8) / 4,
+// block b = r / 8, element i = r % 4) holds logical hidden unit
+// 16 (b / 2) + 8 h + 4 (b % 2) + i, so that accumulator register v = 4 b + i
+// of lane half h is element (v % 8) of B-operand chunk (v / 8) for the next
+// layer (chunk K index 8 h + e).
+__device__ __forceinline__ int perm_row(int r) {
+  const int b = r >> 3, h = (r >> 2) & 1, i = r & 3;
+  return 16 * (b >> 1) + 8 * h + 4 * (b & 1) + i;
+}
+
 // grid sizes from a device schedule (NULL = full resolution), clamped to the frame
 struct Grids {
   int w2, h2, w3, h3;

@@ -10,6 +10,10 @@
 // In BF16 mode every GEMM operand (weights, inputs, activations, output
 // gradients) is rounded to bf16 as the matrix cores would consume it; products
 // of two bf16 values are exact in FP32 and accumulation is FP32.
+//
+// BF16 with hidden widths 32 or 64 runs kernel 1 on the matrix cores
+// (train_mfma_kernel, below); FP32 and other widths use train_fwd_bwd on the
+// vector units. Both take the same rounding points.
 #include <cmath>
 
 #include "internal.h"
@@ -201,6 +205,322 @@ __global__ __launch_bounds__(kRP * kRG) void train_reduce_adam(AdamArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Kernel 1 on the matrix cores (BF16, h1 and h2 in {32, 64}).
+//
+// A block is 4 waves and kMSamples = 256 samples; wave w owns samples
+// 64 w .. 64 w + 63 as two 32-sample groups (the N dimension of
+// v_mfma_f32_32x32x16_bf16).
+//  * Per group, in registers: the forward pass, dL/dz3, dL/dh2 = W3^T dz3 and
+//    dL/dh1 = W2^T dz2. Hidden rows are stored permuted (perm_row), so each
+//    product's accumulators are already the next product's B operand.
+//  * The weight gradients contract over samples. x, h1, h2 and dz1..dz3 of all
+//    256 samples are staged in LDS as [unit][sample] bf16 rows; after one
+//    barrier the waves share out the gradient tiles, each a product with
+//    K = 256 samples whose result is final for the block and goes straight to
+//    the block's partial. Bias gradients are fixed-order row sums, one row
+//    per thread. train_reduce_adam then sums the blocks' partials in order.
+
+constexpr int kMWaves = 4;
+constexpr int kMSamples = 64 * kMWaves;      // samples per block
+constexpr int kRow = kMSamples + 8;          // LDS row stride in bf16 (offsets rows by 4 banks)
+
+__device__ __forceinline__ f32x16 mfma_bf16(const bf16x8& A, const bf16x8& B, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf16x8 pack8(const float* w) {
+  bf16x8 v;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = static_cast<__bf16>(w[e]);
+  return v;
+}
+
+// 8 consecutive bf16 of an LDS row (16-byte aligned)
+__device__ __forceinline__ bf16x8 lds8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+
+template <int T1, int T2>
+struct MfmaShape {
+  static constexpr int H1 = 32 * T1, H2 = 32 * T2;
+  static constexpr int NP = H1 * kIn + H1 + H2 * H1 + H2 + 3 * H2 + 3;
+  static constexpr int oW1 = 0, ob1 = H1 * kIn, oW2 = ob1 + H1, ob2 = oW2 + H2 * H1, oW3 = ob2 + H2,
+                       ob3 = oW3 + 3 * H2;
+  // LDS rows: x (16), h1, h2, dz1, dz2, dz3 (4: the last stays zero)
+  static constexpr int rX = 0, rH1 = kIn, rH2 = rH1 + H1, rD1 = rH2 + H2, rD2 = rD1 + H1, rD3 = rD2 + H2,
+                       rows = rD3 + 4;
+  static constexpr int act_bytes = rows * kRow * 2;
+  // the FP32 weights are staged in the same bytes before the rows are written
+  static constexpr int lds_bytes = act_bytes > NP * 4 ? act_bytes : NP * 4;
+};
+
+template <int T1, int T2>
+__global__ __launch_bounds__(64 * kMWaves) void train_mfma_kernel(TrainArgs a) {
+  using S = MfmaShape<T1, T2>;
+  constexpr int H1 = S::H1, H2 = S::H2, NP = S::NP;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[S::lds_bytes];
+  __shared__ __attribute__((aligned(16))) float sB[H1 + H2 + 4];
+  __shared__ float sLoss[kMWaves];
+  float* sW = reinterpret_cast<float*>(smem);
+  __bf16* sA = reinterpret_cast<__bf16*>(smem);
+  auto row = [&](int r) { return sA + r * kRow; };
+  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, h = l >> 5, col = l & 31;
+
+  for (int i = tid; i < NP; i += 64 * kMWaves) sW[i] = a.params[i];
+  __syncthreads();
+  for (int i = tid; i < H1; i += 64 * kMWaves) sB[i] = sW[S::ob1 + i];
+  for (int i = tid; i < H2; i += 64 * kMWaves) sB[H1 + i] = sW[S::ob2 + i];
+  if (tid < 3) sB[H1 + H2 + tid] = sW[S::ob3 + tid];
+
+  // ---- operands of the weights (every wave holds them) ----
+  bf16x8 A1[T1], A2[T2][2 * T1], A3[2 * T2], A3T[T2], A2T[T1][2 * T2];
+  float w[8];
+#pragma unroll
+  for (int t = 0; t < T1; ++t) {
+    const int u = 32 * t + perm_row(col);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) w[e] = sW[S::oW1 + u * kIn + 8 * h + e];
+    A1[t] = pack8(w);
+  }
+#pragma unroll
+  for (int t = 0; t < T2; ++t) {
+    const int u = 32 * t + perm_row(col);
+#pragma unroll
+    for (int c = 0; c < 2 * T1; ++c) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) w[e] = sW[S::oW2 + u * H1 + 16 * c + 8 * h + e];
+      A2[t][c] = pack8(w);
+    }
+    // W3^T: row = layer-2 unit u, K = output 8 h + e (three live)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) w[e] = (h == 0 && e < 3) ? sW[S::oW3 + e * H2 + u] : 0.0f;
+    A3T[t] = pack8(w);
+  }
+#pragma unroll
+  for (int c = 0; c < 2 * T2; ++c) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) w[e] = col < 3 ? sW[S::oW3 + col * H2 + 16 * c + 8 * h + e] : 0.0f;
+    A3[c] = pack8(w);
+  }
+  // W2^T: row = layer-1 unit j (permuted as layer 1), K = layer-2 unit 16 c + 8 h + e
+#pragma unroll
+  for (int t = 0; t < T1; ++t) {
+    const int j = 32 * t + perm_row(col);
+#pragma unroll
+    for (int c = 0; c < 2 * T2; ++c) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) w[e] = sW[S::oW2 + (16 * c + 8 * h + e) * H1 + j];
+      A2T[t][c] = pack8(w);
+    }
+  }
+  __syncthreads();  // the weight bytes become activation rows from here on
+  for (int i = tid; i < kRow; i += 64 * kMWaves) row(S::rD3 + 3)[i] = static_cast<__bf16>(0.0f);
+
+  // ---- this wave's 64 samples ----
+  const int c0 = 64 * wave;                          // first column of the wave
+  const int smp = blockIdx.x * kMSamples + c0 + l;   // this lane's sample
+  const bool valid = smp < a.batch;
+  float x[kIn];
+#pragma unroll
+  for (int c = 0; c < kIn; c += 4) {
+    const float4 v = valid ? *reinterpret_cast<const float4*>(a.x + (size_t)smp * kIn + c)
+                           : make_float4(0.f, 0.f, 0.f, 0.f);
+    x[c] = q<true>(v.x); x[c + 1] = q<true>(v.y); x[c + 2] = q<true>(v.z); x[c + 3] = q<true>(v.w);
+  }
+  float y[3];
+#pragma unroll
+  for (int o = 0; o < 3; ++o) y[o] = valid ? a.y[(size_t)smp * 3 + o] : 0.0f;
+#pragma unroll
+  for (int c = 0; c < kIn; ++c) row(S::rX + c)[c0 + l] = static_cast<__bf16>(x[c]);
+  // B operands of the two groups: half 0 takes inputs 0..7 and half 1
+  // inputs 8..15 of sample `col` of the group
+  float xa[8], xb[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const float lo = x[e], hi = x[8 + e];
+    const float lo_x = __shfl_xor(lo, 32), hi_x = __shfl_xor(hi, 32);
+    xa[e] = h == 0 ? lo : hi_x;
+    xb[e] = h == 0 ? lo_x : hi;
+  }
+  float lsum = 0.0f;
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const bf16x8 XB = pack8(g == 0 ? xa : xb);
+    const int sl = 32 * g + col;   // the wave's sample this lane's column stands for
+    const int sc = c0 + sl;        // its LDS column
+    // ---- layer 1 ----
+    bf16x8 H1c[2 * T1];
+    uint32_t m1[T1];
+#pragma unroll
+    for (int t = 0; t < T1; ++t) {
+      f32x16 acc = {};
+      acc = mfma_bf16(A1[t], XB, acc);
+      uint32_t m = 0;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        float hv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float z = acc[8 * c + e] + sB[32 * t + 16 * c + 8 * h + e];
+          m |= (z > 0.0f ? 1u : 0u) << (8 * c + e);
+          hv[e] = fmaxf(z, 0.0f);
+        }
+        H1c[2 * t + c] = pack8(hv);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) row(S::rH1 + 32 * t + 16 * c + 8 * h + e)[sc] = H1c[2 * t + c][e];
+      }
+      m1[t] = m;
+    }
+    // ---- layer 2 ----
+    bf16x8 H2c[2 * T2];
+    uint32_t m2[T2];
+#pragma unroll
+    for (int t = 0; t < T2; ++t) {
+      f32x16 acc = {};
+#pragma unroll
+      for (int c = 0; c < 2 * T1; ++c) acc = mfma_bf16(A2[t][c], H1c[c], acc);
+      uint32_t m = 0;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        float hv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float z = acc[8 * c + e] + sB[H1 + 32 * t + 16 * c + 8 * h + e];
+          m |= (z > 0.0f ? 1u : 0u) << (8 * c + e);
+          hv[e] = fmaxf(z, 0.0f);
+        }
+        H2c[2 * t + c] = pack8(hv);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) row(S::rH2 + 32 * t + 16 * c + 8 * h + e)[sc] = H2c[2 * t + c][e];
+      }
+      m2[t] = m;
+    }
+    // ---- output, loss and dL/dz3 (half 0 holds the three outputs) ----
+    f32x16 acc3 = {};
+#pragma unroll
+    for (int c = 0; c < 2 * T2; ++c) acc3 = mfma_bf16(A3[c], H2c[c], acc3);
+    const float yg0 = __shfl(y[0], sl), yg1 = __shfl(y[1], sl), yg2 = __shfl(y[2], sl);
+    const bool vg = blockIdx.x * kMSamples + sc < a.batch;
+    float d3[3] = {0.0f, 0.0f, 0.0f};
+    if (h == 0 && vg) {
+      const float yy[3] = {yg0, yg1, yg2};
+#pragma unroll
+      for (int o = 0; o < 3; ++o) {
+        const float z = acc3[o] + sB[H1 + H2 + o];
+        const float f = a.out_act ? 1.0f / (1.0f + expf(-z)) : fmaxf(z, 0.0f);
+        const float e = f - yy[o];
+        lsum = fmaf(e * e, a.inv_count, lsum);
+        const float df = a.out_act ? f * (1.0f - f) : (z > 0.0f ? 1.0f : 0.0f);
+        d3[o] = q<true>(2.0f * e * a.inv_count * df);
+      }
+    }
+    if (h == 0) {
+#pragma unroll
+      for (int o = 0; o < 3; ++o) row(S::rD3 + o)[sc] = static_cast<__bf16>(d3[o]);
+    }
+    float dv[8] = {d3[0], d3[1], d3[2], 0.f, 0.f, 0.f, 0.f, 0.f};
+    const bf16x8 D3B = pack8(dv);  // half 1 is all zero (d3 stays 0 there)
+    // ---- dL/dz2 = (W3^T dz3) masked by layer 2's ReLU ----
+    bf16x8 D2c[2 * T2];
+#pragma unroll
+    for (int t = 0; t < T2; ++t) {
+      f32x16 acc = {};
+      acc = mfma_bf16(A3T[t], D3B, acc);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        float gv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) gv[e] = ((m2[t] >> (8 * c + e)) & 1u) ? acc[8 * c + e] : 0.0f;
+        D2c[2 * t + c] = pack8(gv);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) row(S::rD2 + 32 * t + 16 * c + 8 * h + e)[sc] = D2c[2 * t + c][e];
+      }
+    }
+    // ---- dL/dz1 = (W2^T dz2) masked by layer 1's ReLU ----
+#pragma unroll
+    for (int t = 0; t < T1; ++t) {
+      f32x16 acc = {};
+#pragma unroll
+      for (int c = 0; c < 2 * T2; ++c) acc = mfma_bf16(A2T[t][c], D2c[c], acc);
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float gv = ((m1[t] >> (8 * c + e)) & 1u) ? acc[8 * c + e] : 0.0f;
+          row(S::rD1 + 32 * t + 16 * c + 8 * h + e)[sc] = static_cast<__bf16>(gv);
+        }
+    }
+  }
+#pragma unroll
+  for (int k = 32; k >= 1; k >>= 1) lsum += __shfl_xor(lsum, k);
+  if (l == 0) sLoss[wave] = lsum;
+  __syncthreads();
+
+  // ---- the block's gradient: K = its 256 samples ----
+  float* out = a.partial + (size_t)blockIdx.x * NP;
+  constexpr int kTiles = T2 * T1 + T1 + T2;
+  const bf16x8 zero8 = {};
+  for (int tile = wave; tile < kTiles; tile += kMWaves) {
+    // which product: dW2 (t2, t1), dW1 (t1) or dW3 (t2); A rows / B columns
+    const __bf16* arow;
+    const __bf16* brow;
+    bool alive, blive;
+    if (tile < T2 * T1) {
+      const int t2 = tile / T1, t1 = tile % T1;
+      arow = row(S::rD2 + 32 * t2 + col); alive = true;
+      brow = row(S::rH1 + 32 * t1 + col); blive = true;
+    } else if (tile < T2 * T1 + T1) {
+      const int t1 = tile - T2 * T1;
+      arow = row(S::rD1 + 32 * t1 + col); alive = true;
+      brow = row(S::rX + min(col, kIn - 1)); blive = col < kIn;
+    } else {
+      const int t2 = tile - T2 * T1 - T1;
+      arow = row(S::rD3 + min(col, 3)); alive = col < 4;
+      brow = row(S::rH2 + 32 * t2 + col); blive = true;
+    }
+    // two accumulators over alternating K steps, added at the end
+    f32x16 acc0 = {}, acc1 = {};
+#pragma unroll
+    for (int ks = 0; ks < kMSamples / 16; ks += 2) {
+      acc0 = mfma_bf16(alive ? lds8(arow + 16 * ks + 8 * h) : zero8, blive ? lds8(brow + 16 * ks + 8 * h) : zero8,
+                       acc0);
+      acc1 = mfma_bf16(alive ? lds8(arow + 16 * ks + 16 + 8 * h) : zero8,
+                       blive ? lds8(brow + 16 * ks + 16 + 8 * h) : zero8, acc1);
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const float gsum = acc0[v] + acc1[v];
+      const int r = 8 * (v >> 2) + 4 * h + (v & 3);  // accumulator row of register v
+      if (tile < T2 * T1) {
+        const int t2 = tile / T1, t1 = tile % T1;
+        out[S::oW2 + (32 * t2 + r) * H1 + 32 * t1 + col] = gsum;
+      } else if (tile < T2 * T1 + T1) {
+        const int t1 = tile - T2 * T1;
+        if (col < kIn) out[S::oW1 + (32 * t1 + r) * kIn + col] = gsum;
+      } else {
+        const int t2 = tile - T2 * T1 - T1;
+        if (r < 3) out[S::oW3 + r * H2 + 32 * t2 + col] = gsum;
+      }
+    }
+  }
+  // bias gradients: thread i sums one dz row over the block's samples in order
+  {
+    int r = -1, o = 0;
+    if (tid < H1) { r = S::rD1 + tid; o = S::ob1 + tid; }
+    else if (tid < H1 + H2) { r = S::rD2 + tid - H1; o = S::ob2 + tid - H1; }
+    else if (tid < H1 + H2 + 3) { r = S::rD3 + tid - H1 - H2; o = S::ob3 + tid - H1 - H2; }
+    if (r >= 0) {
+      float sum = 0.0f;
+      for (int k = 0; k < kMSamples; k += 8) {
+        const bf16x8 v = lds8(row(r) + k);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) sum += static_cast<float>(v[e]);
+      }
+      out[o] = sum;
+    }
+  }
+  if (tid == 0) a.partial_loss[blockIdx.x] = ((sLoss[0] + sLoss[1]) + sLoss[2]) + sLoss[3];
+}
+
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 template <bool BF, int H1, int H2>
@@ -235,11 +555,23 @@ int launch_train(const starnt_train& tr, const float* x, const float* y, int bat
   t.out_act = tr.out_act;
   const bool bf = tr.dtype == STARNT_BF16;
   bool ok = true;
+  int nblocks = nb;
+  // BF16 with hidden widths 32 or 64: the matrix-core kernel, kMSamples
+  // samples per block
+  const bool mf = bf && (tr.h1 == 32 || tr.h1 == 64) && (tr.h2 == 32 || tr.h2 == 64);
+  if (mf) {
+    nblocks = (batch + kMSamples - 1) / kMSamples;
+    const dim3 grid((unsigned)nblocks), block(64 * kMWaves);
+    if (tr.h1 == 32 && tr.h2 == 32) hipLaunchKernelGGL((train_mfma_kernel<1, 1>), grid, block, 0, s, t);
+    else if (tr.h1 == 32) hipLaunchKernelGGL((train_mfma_kernel<1, 2>), grid, block, 0, s, t);
+    else if (tr.h2 == 32) hipLaunchKernelGGL((train_mfma_kernel<2, 1>), grid, block, 0, s, t);
+    else hipLaunchKernelGGL((train_mfma_kernel<2, 2>), grid, block, 0, s, t);
+  }
 #define TCASE(A, B)                                                        \
   else if (tr.h1 == A && tr.h2 == B) {                                     \
     if (bf) launch_fb<true, A, B>(t, nb, s); else launch_fb<false, A, B>(t, nb, s); \
   }
-  if (false) {}
+  if (mf) {}
   TCASE(16, 16) TCASE(32, 16) TCASE(16, 32) TCASE(32, 32) TCASE(64, 64) TCASE(32, 64) TCASE(64, 32)
   else ok = false;
 #undef TCASE
@@ -247,7 +579,7 @@ int launch_train(const starnt_train& tr, const float* x, const float* y, int bat
   STARNT_LAUNCH_CHECK("starnt_train_step forward/backward launch");
   AdamArgs ad;
   ad.nparam = np;
-  ad.nblocks = nb;
+  ad.nblocks = nblocks;
   ad.partial = t.partial;
   ad.partial_loss = t.partial_loss;
   ad.params = tr.params;

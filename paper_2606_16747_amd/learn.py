@@ -13,7 +13,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import (BF16, F32, NET_DFAOIT, WS_TRAIN, Adam, DeviceFrags, DeviceMlp, FeatBuffers, Train,
+from . import (BF16, NET_DFAOIT, WS_TRAIN, Adam, DeviceFrags, FeatBuffers, Train,
                starnt_dfa_inputs, starnt_features, starnt_train_step, starnt_workspace_size, workspace)
 from .frames import exact_frame
 

@@ -126,7 +126,6 @@ def test_ablation_ten_versus_five_features(starnt, gpu, sg, capsys):
     predicts the exact two-layer part too, so its errors reach it; measured
     about 34 and 25 dB here)."""
     from paper_2606_16747_amd import learn
-    from paper_2606_16747_amd import frames as fm
     xs5, ys5, xs10, ys10 = [], [], [], []
     for k in range(32):
         fr = sg.Scene("c3_512", seed=sg.BASE_SEED + 3 + 1000 * (k + 1)).frame(0)

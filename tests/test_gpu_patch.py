@@ -8,7 +8,7 @@ import pytest
 import torch
 
 from csr_util import make_csr
-from gpu_util import run_features, sync, to_np
+from gpu_util import sync, to_np
 
 pytestmark = pytest.mark.gpu
 

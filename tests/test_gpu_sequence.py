@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import sync, to_np
+from gpu_util import sync
 
 pytestmark = pytest.mark.gpu
 

@@ -143,3 +143,117 @@ def test_config5_1440p_sequence(starnt, gpu, sg, oracle_mod):
         psnr = 10 * np.log10(1.0 / (d * d).mean())
         assert np.isfinite(to_np(out[t])).all()
         assert psnr > (26.0 if t % 2 == 0 else 20.0), (t, psnr)
+
+
+def test_config2_1080p_bench_workload(starnt, gpu, sg, oracle_mod):
+    """The benchmark's own workload at full size (1920x1080, 2000 triangles),
+    in the launch configuration the bench times, against the oracle on every
+    pixel:
+    * frame 0 at full resolution and frame 2 with pass 3 at 0.79 (the scale
+      the quadtree picks on this sequence): counts, selected layers and d1
+      bit-exact, layer and tail records within the FP32 bars;
+    * the FP32 learned composite at those grids within 1e-4 per channel;
+    * the BF16 network (16-32-32-3) on the matrix cores against the FP64
+      network on bf16-rounded operands of the oracle's upscaled inputs, on
+      200,000 seeded pixels (99.5% within 2e-4, all within 2e-2 (1 + |f|)), and the
+      bench's fused BF16 call equal to network plus composite within 1e-6;
+    * the quadtree update and the reprojection gather, fed the oracle's
+      composite and depth of frame 0: masks, levels and histogram bit-exact
+      away from nodes whose D is within 1e-6 of a threshold, source indices
+      bit-exact away from rounding boundaries."""
+    sc = sg.Scene("c2_1080p")
+    W, H = sc.params.width, sc.params.height
+    assert (W, H) == (1920, 1080)
+    P = W * H
+    Ws, bs = sg.init_mlp((16, 32, 32, 3), seed=sg.BASE_SEED + 100, out_bias=0.05)
+    om = oracle_mod.Mlp(Ws, bs)
+    bg = (1.0, 1.0, 1.0)
+    o0 = None
+    for t, s3 in ((0, 1.0), (2, 0.79)):
+        fr = sc.frame(t)
+        df = starnt.DeviceFrags.from_frame(fr, max_per_pixel=64)
+        sched = starnt.new_sched(W, H, 1.0, s3)
+        fb = starnt.FeatBuffers(W, H, with_sel=True)
+        starnt.starnt_features(df, sched, fb)
+        sync()
+        o = oracle_mod.frame_of(fr, bg=bg)
+        if t == 0:
+            o0 = o
+        np.testing.assert_array_equal(to_np(fb.count).view(np.uint32), o["lay"][:, 0].astype(np.uint32))
+        np.testing.assert_array_equal(to_np(fb.sel).view(np.uint32), o["sel"])
+        np.testing.assert_array_equal(to_np(fb.d1), o["lay"][:, 1].astype(np.float32))
+        L1 = to_np(fb.layer1)
+        np.testing.assert_allclose(L1[:, 3], o["lay"][:, 2], atol=1e-7)
+        assert int(to_np(fb.err)[0]) == 0
+        grids = (oracle_mod.grid_dim(W, 1.0), oracle_mod.grid_dim(H, 1.0), oracle_mod.grid_dim(W, s3),
+                 oracle_mod.grid_dim(H, s3))
+        s = starnt.read_sched(sched)
+        assert (s["w2"], s["h2"], s["w3"], s["h3"]) == grids
+        want, xf, _ = oracle_mod.learned(o["lay"], o["tail"], W, H, grids, om, oracle_mod.MODE_LEARNED, bg=bg)
+        # FP32 network: the per-channel bar
+        rgb32 = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+        starnt.starnt_infer_composite(starnt.DeviceMlp(Ws, bs, starnt.F32), fb, sched, bg, rgb32)
+        sync()
+        assert np.abs(to_np(rgb32) - want).max() <= TOL
+        # BF16 network on the matrix cores
+        mlp = starnt.DeviceMlp(Ws, bs, starnt.BF16)
+        tail = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+        starnt.starnt_infer(mlp, fb.tail, fb.count, sched, W, H, tail)
+        fused = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+        starnt.starnt_infer_composite(mlp, fb, sched, bg, fused)
+        two = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+        starnt.starnt_composite(df, fb, tail, sched, bg, starnt.MODE_LEARNED, two)
+        sync()
+        # (the bf16-operand oracle network on 200,000 seeded pixels)
+        pick = np.random.default_rng(t).choice(P, 200000, replace=False)
+        live = o["lay"][pick, 0] >= 3
+        fq = np.zeros((len(pick), 3))
+        fq[live] = om.forward_q(xf[pick][live], 1)
+        err = np.abs(to_np(tail)[pick] - fq).max(axis=1)
+        assert np.mean(err <= 2e-4) >= 0.995, np.mean(err <= 2e-4)
+        # a rounding flip of one operand moves it by a bf16 step (2^-8 of its
+        # size), so the rare outliers scale with the output
+        bound = 2e-2 * (1.0 + np.abs(fq).max(axis=1))
+        k = int(np.argmax(err - bound))
+        assert (err <= bound).all(), (err[k], fq[k])
+        assert np.abs(to_np(fused) - to_np(two)).max() <= 1e-6
+    # quadtree and reprojection on the oracle's frame-0 composite and depth
+    img = o0["rgb"].astype(np.float32)
+    Nc = o0["lay"][:, 0].astype(np.uint32)
+    base = 64
+    T = ((W + base - 1) // base) * ((H + base - 1) // base)
+    cs = base // 8
+    Cw, Ch = (W + cs - 1) // cs, (H + cs - 1) // cs
+    ws = starnt.workspace(starnt.starnt_workspace_size(starnt.WS_QUADTREE, W, H, base))
+    mask = torch.zeros(T, dtype=torch.int32, device="cuda")
+    level = torch.zeros(Cw * Ch, dtype=torch.uint8, device="cuda")
+    sched = starnt.new_sched(W, H)
+    starnt.starnt_quadtree(torch.from_numpy(img).cuda(), torch.from_numpy(Nc.view(np.int32)).cuda(), W, H,
+                           starnt.QtParams(base, 0.10, 0.05, 2), None, mask, level, sched, ws)
+    sync()
+    m, lv, hist, D = oracle_mod.quadtree(img, Nc, W, H, base=base, tau_split=0.10, tau_merge=0.05, k_relax=2)
+    # decisions are exact except where D lies within 1e-6 of a threshold;
+    # such a node can change levels up to two tiles away (two relaxations),
+    # so those tiles are left out (and the histogram, which counts them all)
+    Tw, Th = (W + base - 1) // base, (H + base - 1) // base
+    near = ((np.abs(D - 0.10) < 1e-6) | (np.abs(D - 0.05) < 1e-6)).any(axis=1).reshape(Th, Tw)
+    keep = np.ones((Th, Tw), bool)
+    for ty, tx in zip(*np.nonzero(near)):
+        keep[max(ty - 2, 0):ty + 3, max(tx - 2, 0):tx + 3] = False
+    assert keep.mean() > 0.9
+    np.testing.assert_array_equal(to_np(mask).view(np.uint32)[keep.ravel()], m[keep.ravel()])
+    cell_keep = np.repeat(np.repeat(keep, 8, axis=0), 8, axis=1)[:Ch, :Cw]
+    np.testing.assert_array_equal(to_np(level).reshape(Ch, Cw)[cell_keep], lv[cell_keep])
+    if not near.any():
+        assert starnt.read_sched(sched)["hist"] == list(hist)
+    d1 = o0["lay"][:, 1].astype(np.float32)
+    mmi = oracle_mod.m_minus_i(sc.camera(0), sc.camera(1)).astype(np.float32)
+    out = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+    src = torch.empty(P, dtype=torch.int32, device="cuda")
+    starnt.starnt_reproject(torch.from_numpy(img).cuda(), torch.from_numpy(d1).cuda(), W, H, mmi, out, src)
+    sync()
+    want_rgb, want_src, margin = oracle_mod.reproject(img, d1, mmi.astype(np.float64), W, H)
+    ok = margin >= 1e-4
+    assert ok.mean() > 0.999
+    np.testing.assert_array_equal(to_np(src)[ok], want_src[ok])
+    np.testing.assert_array_equal(to_np(out)[ok], want_rgb[ok])

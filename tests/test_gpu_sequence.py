@@ -53,3 +53,56 @@ def test_adaptive_sequence_follows_policy_and_reprojects(starnt, gpu, sg, oracle
             assert torch.equal(outs[t], want), t
             checked += 1
     assert checked == 6
+
+
+def test_adaptive_sequence_with_patched_interpolated_frames(starnt, gpu, sg):
+    """AdaptiveSequence(patch=True): every interpolated frame is the trusted
+    gather with its untrusted pixels rendered afresh from that frame's own
+    lists (the same as a renderer asked for that frame directly), and real
+    frames are unchanged by the option."""
+    from paper_2606_16747_amd import frames as fm
+    sc = sg.Scene("c2_1080p", width=256, height=144, num_tris=300)
+    n = 8
+    frames = [sc.frame(t) for t in range(n)]
+    W, H = 256, 144
+    P = W * H
+    costs = [(50.0, 2.0)] * n
+    Ws, bs = sg.init_mlp((16, 32, 32, 3), out_bias=0.05)
+    mlp = starnt.DeviceMlp(Ws, bs, starnt.BF16)
+    dfs = [starnt.DeviceFrags.from_frame(f, max_per_pixel=64) for f in frames]
+    outs = {}
+    for patch in (False, True):
+        rend = fm.Renderer(W, H, mlp, depth_tol=0.01)
+        rend.reset()
+        seq = fm.AdaptiveSequence(rend, 16.7, 4, 0.5, cost=lambda t, real: costs[t][0 if real else 1], patch=patch)
+        res = []
+        for t in range(n):
+            o = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+            real = seq.frame(frames[t].vp, lambda: dfs[t], o)
+            res.append((real, o))
+        sync()
+        outs[patch] = (res, seq.kinds)
+    (plain, kinds0), (patched, kinds1) = outs[False], outs[True]
+    assert kinds0 == kinds1 and not all(kinds0)
+    ref = fm.Renderer(W, H, mlp, depth_tol=0.01)
+    ref.reset()
+    last = None
+    checked = relisted = 0
+    for t in range(n):
+        if kinds1[t]:
+            assert torch.equal(plain[t][1], patched[t][1]), t
+            r = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+            ref.real_frame(dfs[t], r)
+            last = t
+        else:
+            want = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+            ref.interpolated_frame(fm.m_minus_i(frames[last].vp, frames[t].vp), want, frags=dfs[t])
+            sync()
+            assert torch.equal(patched[t][1], want), t
+            listed = int(ref.list_count.item())
+            # re-rendered pixels differ from the plain gather; a frame one
+            # step from its source may have none
+            assert torch.equal(patched[t][1], plain[t][1]) == (listed == 0), t
+            checked += 1
+            relisted += listed
+    assert checked >= 3 and relisted > 0

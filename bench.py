@@ -459,12 +459,16 @@ def main():
     # quality of the last timed step against the exact composite
     star_step()
     torch.cuda.synchronize()
-    psnr, maxerr = [], []
+    psnr, maxerr, psnr_cov = [], [], []
     for t in range(NF):
         d = (outs[t] - exact[t]).double()
         mse = float((d * d).mean())
         psnr.append(10 * np.log10(1.0 / mse) if mse > 0 else float("inf"))
         maxerr.append(float(d.abs().max()))
+        # over the pixels the frame covers (at least one fragment)
+        cov = torch.from_numpy(host[t].counts() >= 1).to(dev)
+        mse_c = float((d[cov] * d[cov]).mean())
+        psnr_cov.append(10 * np.log10(1.0 / mse_c) if mse_c > 0 else float("inf"))
 
     # quality of the same path with f = f_avg and f = 0 (no network)
     def mode_psnr(mode):
@@ -738,6 +742,7 @@ def main():
         "psnr_db": {"min": round(min(psnr), 2), "mean": round(float(np.mean(psnr)), 2),
                     "per_frame": [round(v, 2) for v in psnr]},
         "max_abs_err": round(max(maxerr), 4),
+        "psnr_db_covered_pixels": round(float(np.mean(psnr_cov)), 2),
         "psnr_db_real_frames": round(float(np.mean(psnr[0::2])), 2),
         "psnr_db_interpolated_frames": round(float(np.mean(psnr[1::2])), 2),
         "psnr_db_without_network": {"favg_real": round(float(np.mean(psnr_favg[0::2])), 2),

@@ -108,9 +108,21 @@ def test_selective_inference_against_oracle(starnt, gpu, sg, oracle_mod, s2, s3)
              oracle_mod.grid_dim(H, s3))
     want = oracle_mod.selective(o["lay"], o["tail"], W, H, grids, oracle_mod.Mlp(Ws, bs), lv, base, BG)
     assert np.abs(to_np(rgb) - want).max() <= 1e-4
-    # BF16 runs the same selection (flat cells need no network at all)
+    # BF16 on the matrix cores with the same mixed map: pixels off the flat
+    # cells equal the fused BF16 call bit for bit (a column's network result
+    # does not depend on its neighbours), flat pixels are the f_avg composite
     mlp.set_dtype(starnt.BF16)
-    starnt.starnt_infer_composite_sel(mlp, fb, sched, torch.from_numpy(np.zeros_like(lv)).cuda(), base, BG, rgb)
+    starnt.starnt_infer_composite_sel(mlp, fb, sched, torch.from_numpy(lv).cuda(), base, BG, rgb)
+    full = torch.empty(W * H, 3, dtype=torch.float32, device="cuda")
+    starnt.starnt_infer_composite(mlp, fb, sched, BG, full)
     sync()
     favg, _, _ = oracle_mod.learned(o["lay"], o["tail"], W, H, grids, None, oracle_mod.MODE_FAVG, BG)
+    ys, xs = np.divmod(np.arange(W * H), W)
+    flat = lv[(ys // 8) * Cw + xs // 8] == 0
+    assert flat.any() and (~flat).any()
+    np.testing.assert_array_equal(to_np(rgb)[~flat], to_np(full)[~flat])
+    assert np.abs(to_np(rgb)[flat] - favg[flat]).max() <= 1e-4
+    # an all-flat map runs no network at all
+    starnt.starnt_infer_composite_sel(mlp, fb, sched, torch.from_numpy(np.zeros_like(lv)).cuda(), base, BG, rgb)
+    sync()
     assert np.abs(to_np(rgb) - favg).max() <= 1e-4

@@ -201,3 +201,25 @@ def test_dfa_composite_fp8_against_same_operands(starnt, gpu, sg, oracle_mod):
     err = np.abs(to_np(rgb) - want).max(axis=1)
     assert np.mean(err <= 2e-3) >= 0.99, np.mean(err <= 2e-3)
     assert (err <= 0.25 * (np.abs(want).max(axis=1) + 0.1)).all(), err.max()
+
+
+def test_tail_means_half_colour(starnt, gpu, sg, oracle_mod):
+    """FP16 colour (the 4K workload's format) through the fragment pass with
+    tail means: every pass-3 sample's means against the oracle."""
+    fr = sg.Scene("c1_256", half_rgba=True, width=200, height=90, num_tris=50).frame(0)
+    W, H = fr.width, fr.height
+    df = starnt.DeviceFrags.from_frame(fr, max_per_pixel=64)
+    assert df.rgba_dtype == starnt.F16
+    sched = starnt.new_sched(W, H, 1.0, 0.6)
+    fb = starnt.FeatBuffers(W, H, with_avg=True)
+    starnt.starnt_features(df, sched, fb)
+    sync()
+    grids = _grids(oracle_mod, W, H, 1.0, 0.6)
+    o = oracle_mod.frame_of(fr, want=("lay", "tail", "tavg"))
+    W3, H3 = grids[2], grids[3]
+    ys = np.array([oracle_mod.sample_pos(H, H3, j) for j in range(H3)])
+    xs = np.array([oracle_mod.sample_pos(W, W3, i) for i in range(W3)])
+    pix = (ys[:, None] * W + xs[None, :]).ravel()
+    np.testing.assert_allclose(to_np(fb.tail_avg)[:W3 * H3], o["tavg"][pix], rtol=0, atol=2e-6)
+    np.testing.assert_array_equal(to_np(fb.count).view(np.uint32), o["lay"][:, 0].astype(np.uint32))
+    assert int(to_np(fb.err)[0]) == 0

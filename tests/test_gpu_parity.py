@@ -386,7 +386,7 @@ def test_train_step_bf16_gradient_direction(starnt, gpu, sg, oracle_mod):
     assert np.linalg.norm(gg - gw) / np.linalg.norm(gw) < 0.05
 
 
-@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
 @pytest.mark.parametrize("s2,s3", [(1.0, 1.0), (0.6, 0.35)])
 def test_infer_composite_equals_two_calls(starnt, gpu, sg, dtype, s2, s3):
     """The fused call gives the same image as starnt_infer + starnt_composite."""
@@ -395,7 +395,11 @@ def test_infer_composite_equals_two_calls(starnt, gpu, sg, dtype, s2, s3):
     sched = starnt.new_sched(W, H, s2, s3)
     df, fb = run_features(starnt, fr, sched=sched, max_per_pixel=64)
     Ws, bs = sg.init_mlp((16, 32, 32, 3), out_bias=0.05)
-    mlp = starnt.DeviceMlp(Ws, bs, starnt.F32 if dtype == "f32" else starnt.BF16)
+    kw = {}
+    if dtype == "fp8":
+        kw["fp8_scales"] = [1.0 / 16, float(np.abs(Ws[0]).max()) / 448, 4.0 / 448, float(np.abs(Ws[1]).max()) / 448,
+                            4.0 / 448, float(np.abs(Ws[2]).max()) / 448]
+    mlp = starnt.DeviceMlp(Ws, bs, {"f32": starnt.F32, "bf16": starnt.BF16, "fp8": starnt.FP8}[dtype], **kw)
     two, _ = run_learned(starnt, df, fb, mlp, sched, bg=(0.1, 0.5, 0.9))
     rgb = torch.empty(W * H, 3, dtype=torch.float32, device="cuda")
     starnt.starnt_infer_composite(mlp, fb, sched, (0.1, 0.5, 0.9), rgb)

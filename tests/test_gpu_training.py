@@ -105,13 +105,15 @@ def test_training_resume_from_checkpoint_is_bitwise(starnt, gpu, sg, oracle_mod)
 
 
 @pytest.mark.parametrize("dims,batch,act", [((16, 32, 32, 3), 1000, 0), ((16, 64, 32, 3), 4097, 0),
-                                            ((16, 32, 64, 3), 300, 1), ((16, 64, 64, 3), 65536, 0)])
+                                            ((16, 32, 64, 3), 300, 1), ((16, 64, 64, 3), 65536, 0),
+                                            ((16, 16, 32, 3), 777, 0)])
 def test_bf16_step_on_matrix_cores(starnt, gpu, sg, oracle_mod, dims, batch, act):
-    """The BF16 step for hidden widths 32/64 runs on the matrix cores: its
-    gradient points where the FP64 oracle's does (cosine > 0.999, relative L2
-    < 0.05, the bar of bf16 operands), its loss matches within 2%, batches
-    that fill no whole block are handled, and a step repeated on the same state
-    is bit-identical."""
+    """The BF16 step (hidden widths 32/64 on the matrix cores; a 16-wide layer
+    takes the vector-unit kernel with the same rounding points): its gradient
+    points where the FP64 oracle's does (cosine > 0.999, relative L2 < 0.05,
+    the bar of bf16 operands), its loss matches within 2%, batches that fill no
+    whole block are handled, and a step repeated on the same state is
+    bit-identical."""
     fr = sg.Scene("c3_512", width=128, height=128, num_tris=200).frame(0)
     o = oracle_mod.frame_of(fr)
     x = oracle_mod.features(o["lay"], o["tail"])

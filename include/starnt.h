@@ -13,7 +13,10 @@
  *                     grid (Sec. 3.2-3.3)
  *   starnt_infer      tail-colour network f(x) at full resolution over the
  *                     bilinearly upscaled pass-3 features (Sec. 3.2-3.3);
- *                     starnt_infer_composite fuses it with eq (3)
+ *                     starnt_infer_composite fuses it with eq (3), and with a
+ *                     DFAOIT network (eq (2)); starnt_infer_composite_sel runs
+ *                     the network only off the flat quadtree leaves
+ *   starnt_dfa_inputs the ten-feature DFAOIT input (Sec. 3.3)
  *   starnt_composite  eq (3), C = C_exact,2 + T2 f(x) + prod(1-a) C_b, with the
  *                     upscaled pass-2 layer; or the exact A-buffer composite
  *                     (eq (1) after a per-pixel sort; the paper's ground truth)
@@ -23,6 +26,10 @@
  *   starnt_reproject_check, starnt_patch
  *                     its trust test and the re-rendering of untrusted pixels
  *   starnt_train_step one MSE + Adam step of the tail network (Sec. 3.3)
+ *   starnt_baseline   weighted blended OIT or over in stored order (Sec. 4)
+ *   starnt_interval_init / _next / _report
+ *                     host policy choosing real or interpolated frames from
+ *                     measured frame costs (Sec. 3.3)
  *
  * Conventions for every call:
  *  - Memory: all array arguments are DEVICE pointers owned by the caller unless
@@ -333,7 +340,10 @@ int starnt_patch(const starnt_frags* frags, const starnt_mlp* mlp, const uint32_
  * the FP32 masters with bias correction for step hp->step.
  * x [batch][16] float features, y [batch][3] float targets, loss [1] float
  * written on the device. Gradient sums over the batch use a fixed reduction
- * order, so a step is bitwise reproducible.
+ * order, so a step is bitwise reproducible. dtype STARNT_BF16 rounds every
+ * product operand (weights, inputs, activations, output gradients) to bf16
+ * with FP32 accumulation; with h1 and h2 in {32, 64} the products run on the
+ * matrix cores. dtype STARNT_F32 computes in FP32.
  * Workspace: starnt_workspace_size(STARNT_WS_TRAIN, batch, h1, h2). */
 int starnt_train_step(const starnt_train* t, const float* x, const float* y, int32_t batch,
                       const starnt_adam* hp, float* loss, void* workspace, size_t workspace_bytes,

@@ -167,6 +167,8 @@ __device__ __forceinline__ uint64_t tile_occupancy(const QtArgs& a, int tx, int 
   return om;
 }
 
+__device__ void write_final(const QtArgs& a, int tile, int t, uint32_t m, int Lf, bool live, int gx, int gy);
+
 __global__ __launch_bounds__(64) void qt_pass_kernel(QtArgs a) {
   __shared__ float s_rgb[64][3];
   const int tile = blockIdx.x;
@@ -262,12 +264,17 @@ __global__ __launch_bounds__(64) void qt_pass_kernel(QtArgs a) {
   }
   const uint32_t m = derive_mask(L, live);
   const int Lf = leaf_of(m, cx, cy);
-  if (live) {
-    const size_t c = (size_t)gy * a.Cw + gx;
-    if (a.final_pass) a.level[c] = (uint8_t)Lf;
-    else a.Lout[c] = (uint8_t)Lf;
+  if (a.final_pass) {
+    write_final(a, tile, t, m, Lf, live, gx, gy);
+  } else if (live) {
+    a.Lout[(size_t)gy * a.Cw + gx] = (uint8_t)Lf;
   }
-  if (!a.final_pass) return;
+}
+
+// the last pass's outputs for one tile: leaf levels, the mask and the
+// tile's occupied-leaf counts per level (lane t = cell t)
+__device__ void write_final(const QtArgs& a, int tile, int t, uint32_t m, int Lf, bool live, int gx, int gy) {
+  if (live) a.level[(size_t)gy * a.Cw + gx] = (uint8_t)Lf;
   if (t == 0) a.mask[tile] = m;
   const uint64_t om = a.tile_occ[tile];
   if (t == 0) {
@@ -288,6 +295,56 @@ __global__ __launch_bounds__(64) void qt_pass_kernel(QtArgs a) {
     }
     for (int l = 0; l < 4; ++l) a.tile_hist[4 * (size_t)tile + l] = h[l];
   }
+}
+
+// Both relaxations (k = 2) in one launch. A block of nine waves takes one
+// tile: wave w runs the first relaxation for tile (tx + w % 3 - 1,
+// ty + w / 3 - 1) of its 3 x 3 neighbourhood from the top-down levels, into
+// LDS; the centre wave then runs the second relaxation, whose cells' 4
+// neighbours all lie in that neighbourhood, and writes the outputs. The first
+// relaxation of a tile depends only on the top-down levels, so each block's
+// copies equal what a separate pass would write. Integer work, identical.
+__global__ __launch_bounds__(576) void qt_relax2_kernel(QtArgs a) {
+  __shared__ uint8_t s_lv[9][64];
+  const int tile = blockIdx.x;
+  const int tx = tile % a.Tw, ty = tile / a.Tw;
+  const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
+  const int cx = t & 7, cy = t >> 3;
+  // ---- first relaxation, one neighbourhood tile per wave ----
+  {
+    const int nx = tx + w % 3 - 1, ny = ty + w / 3 - 1;
+    if (nx >= 0 && nx < a.Tw && ny >= 0 && ny < a.Th) {  // uniform over the wave
+      const int gx = nx * 8 + cx, gy = ny * 8 + cy;
+      const bool live = gx < a.Cw && gy < a.Ch;
+      const int cxl = min(gx, a.Cw - 1), cyl = min(gy, a.Ch - 1);
+      const int own = a.Lin[(size_t)cyl * a.Cw + cxl];
+      const int l = a.Lin[(size_t)cyl * a.Cw + max(cxl - 1, 0)];
+      const int rr = a.Lin[(size_t)cyl * a.Cw + min(cxl + 1, a.Cw - 1)];
+      const int u = a.Lin[(size_t)max(cyl - 1, 0) * a.Cw + cxl];
+      const int d = a.Lin[(size_t)min(cyl + 1, a.Ch - 1) * a.Cw + cxl];
+      const int L = live ? max(max(own, max(l, rr) - 1), max(u, d) - 1) : 0;
+      s_lv[w][t] = (uint8_t)leaf_of(derive_mask(L, live), cx, cy);
+    }
+  }
+  __syncthreads();
+  if (w != 4) return;
+  // ---- second relaxation of the centre tile ----
+  const int gx = tx * 8 + cx, gy = ty * 8 + cy;
+  const bool live = gx < a.Cw && gy < a.Ch;
+  const int cxl = min(gx, a.Cw - 1), cyl = min(gy, a.Ch - 1);
+  // level of in-grid cell (x, y), which lies in the neighbourhood
+  auto at = [&](int x, int y) -> int {
+    const int sw = (x >> 3) - tx + 1, sh = (y >> 3) - ty + 1;
+    return s_lv[sh * 3 + sw][(y & 7) * 8 + (x & 7)];
+  };
+  const int own = at(cxl, cyl);
+  const int l = at(max(cxl - 1, 0), cyl);
+  const int rr = at(min(cxl + 1, a.Cw - 1), cyl);
+  const int u = at(cxl, max(cyl - 1, 0));
+  const int d = at(cxl, min(cyl + 1, a.Ch - 1));
+  const int L = live ? max(max(own, max(l, rr) - 1), max(u, d) - 1) : 0;
+  const uint32_t m = derive_mask(L, live);
+  write_final(a, tile, t, m, leaf_of(m, cx, cy), live, gx, gy);
 }
 
 // one block: the schedule of the next frame from all tiles' counts
@@ -345,12 +402,20 @@ int launch_quadtree(const float* rgb, const uint32_t* count, int W, int H, const
   const int T = a.Tw * a.Th;
   a.tile_occ = reinterpret_cast<uint64_t*>(reinterpret_cast<uint8_t*>(a.tile_hist) + align256((size_t)T * 16));
   uint8_t* bufs[2] = {L0, L1};
-  for (int it = 0; it <= qp.k_relax; ++it) {
+  // k = 2 (the usual setting): the top-down pass, then both relaxations in
+  // one launch; otherwise one launch per pass
+  const int passes = qp.k_relax == 2 ? 1 : qp.k_relax;
+  for (int it = 0; it <= passes; ++it) {
     a.mode = it == 0 ? 0 : 1;
     a.final_pass = it == qp.k_relax;
     a.Lin = bufs[(it + 1) & 1];
     a.Lout = bufs[it & 1];
-    hipLaunchKernelGGL(qt_pass_kernel, dim3(T), dim3(64), 0, s, a);
+    if (qp.k_relax == 2 && it == 1) {
+      a.final_pass = 1;
+      hipLaunchKernelGGL(qt_relax2_kernel, dim3(T), dim3(576), 0, s, a);
+    } else {
+      hipLaunchKernelGGL(qt_pass_kernel, dim3(T), dim3(64), 0, s, a);
+    }
     STARNT_LAUNCH_CHECK("starnt_quadtree pass launch");
   }
   hipLaunchKernelGGL(qt_finish_kernel, dim3(1), dim3(64), 0, s, a.tile_hist, T, W, H, sched);

@@ -135,7 +135,8 @@ typedef struct {
  * any h1, h2 <= 64 with in = 16, out = 3 here). Weights are FP32 masters in
  * the layout W_l[out][in] row-major; `dtype` selects the arithmetic:
  * STARNT_F32 (VALU FP32), STARNT_BF16 (bf16 operands on the matrix cores, FP32
- * accumulate), STARNT_FP8 (E4M3 operands with per-layer scales, FP32
+ * accumulate; the hidden-layer biases join that sum exactly, as three bf16
+ * parts each), STARNT_FP8 (E4M3 operands with per-layer scales, FP32
  * accumulate). Input x = (N, t_tail, Ct_rgb) padded with 11 zeros. */
 typedef struct {
   int32_t in, h1, h2, out;

@@ -107,9 +107,16 @@ __device__ __forceinline__ Full full_grids(const InferArgs& a, const Grids& g) {
   if constexpr (MODE == kPatch) return Full{true, true};
   return Full{g.w2 == a.W && g.h2 == a.H, g.w3 == a.W && g.h3 == a.H};
 }
+// The same choice fixed at compile time, for loops specialised per case: with
+// no merge of the two load paths inside the loop, a prefetched step's loads
+// stay in flight in their own registers until the step is used.
+template <bool G2, bool G3>
+struct FullC {
+  static constexpr bool g2 = G2, g3 = G3;
+};
 
-template <int MODE>
-__device__ __forceinline__ void issue_loads(const InferArgs& a, const Grids& g, const Full& f, int p, PixRaw& r) {
+template <int MODE, class F>
+__device__ __forceinline__ void issue_loads(const InferArgs& a, const Grids& g, const F& f, int p, PixRaw& r) {
   r.n = a.count[p];
   if constexpr (MODE == kPatch) {
     // slot p holds its own full-resolution features
@@ -164,8 +171,8 @@ __device__ __forceinline__ float blend4(float p0, float p1, float p2, float p3, 
   return lerp1(lerp1(p0, p1, wx), lerp1(p2, p3, wx), wy);
 }
 
-template <int MODE>
-__device__ __forceinline__ PixIn blend(const PixRaw& r, const Full& f) {
+template <int MODE, class F>
+__device__ __forceinline__ PixIn blend(const PixRaw& r, const F& f) {
   PixIn in;
   in.n = r.n;
   in.flat = MODE == kSel && r.lvl == 0;
@@ -348,6 +355,16 @@ __device__ __forceinline__ uint32_t e4m3_pack4(float a, float b, float c, float 
 }
 __device__ __forceinline__ float sat448(float v) { return fminf(fmaxf(v, -448.0f), 448.0f); }
 
+// b = p[0] + p[1] + p[2] exactly, each part a bf16 value: p[0] is b rounded
+// to bf16 (8 significant bits), p[1] the remainder (at most 16 significant
+// bits, exact in FP32) rounded likewise, p[2] what is left (at most 8 bits)
+__device__ __forceinline__ void bias_parts(float b, float* p) {
+  p[0] = (float)static_cast<__bf16>(b);
+  const float r = b - p[0];
+  p[1] = (float)static_cast<__bf16>(r);
+  p[2] = r - p[1];
+}
+
 template <bool FP8>
 struct Op {
   using vec = typename std::conditional<FP8, fp8x8, bf16x8>::type;
@@ -411,7 +428,7 @@ constexpr int kMaxParams = 64 * 16 + 64 + 64 * 64 + 64 + 3 * 64 + 3;
 // 32-pixel group's inputs cross to lane half 0 with one xor-32 shuffle, and
 // its outputs cross back the same way.
 template <int T1, int T2, bool FP8, int MODE>
-__global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T1 * T2 == 1 ? 3 : 1))) void infer_mfma_kernel(InferArgs a) {
   __shared__ float s_w[kMaxParams];
   using V = typename Op<FP8>::vec;
   // stage weights: W1 [h1][16], b1, W2 [h2][h1], b2, W3 [3][h2], b3
@@ -449,6 +466,12 @@ __global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
   const float dq2 = FP8 ? a.sa[2] * a.sw[2] : 1.0f;
 
   // ---- weights into registers, in operand layout ----
+  // BF16: the hidden layers' FP32 biases enter the matrix-core accumulation
+  // as three bf16 parts that sum to them exactly, one per K slot, against
+  // inputs of 1 (layer 1: the free K slots after the inputs; layer 2: one
+  // extra K chunk). FP8 adds them after the dequantisation.
+  constexpr int NIN = n_inputs<MODE>();
+  constexpr int NB = FP8 ? 0 : 3;
   // layer 1: tile t, physical row `col` = hidden unit 32 t + perm_row(col)
   V A1[T1];
   f32x16 B1v[T1];
@@ -456,10 +479,12 @@ __global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
   for (int t = 0; t < T1; ++t) {
     const int u = 32 * t + perm_row(col);
     float w[8];
+    float bp[3] = {0.0f, 0.0f, 0.0f};
+    if (NB && u < a.h1) bias_parts(sb1[u], bp);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int k = 8 * half + e;
-      w[e] = (u < a.h1 && k < n_inputs<MODE>()) ? sW1[u * 16 + k] : 0.0f;
+      w[e] = (u < a.h1 && k < NIN) ? sW1[u * 16 + k] : (k >= NIN && k < NIN + NB ? bp[k - NIN < 3 ? k - NIN : 0] : 0.0f);
     }
     set8<FP8>(A1[t], w, iw0);
 #pragma unroll
@@ -472,10 +497,16 @@ __global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
   // runs over layer-1 units 16 c + 8 half + e
   constexpr int C2 = 2 * T1;
   V A2[T2][C2];
+  V A2b[T2];  // BF16: bias parts of unit u in K slots 0..2 of lane half 0
   f32x16 B2v[T2];
 #pragma unroll
   for (int t = 0; t < T2; ++t) {
     const int u = 32 * t + perm_row(col);
+    {
+      float bp[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+      if (NB && half == 0 && u < a.h2) bias_parts(sb2[u], bp);
+      set8<FP8>(A2b[t], bp, 1.0f);
+    }
 #pragma unroll
     for (int c = 0; c < C2; ++c) {
       float w[8];
@@ -506,6 +537,11 @@ __global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
     set8<FP8>(A3[c], w, iw2);
   }
   const float b30 = sb3[0], b31 = sb3[1], b32 = sb3[2];
+  V ONES;  // B operand of the layer-2 bias chunk
+  {
+    const float one[8] = {1.0f, 1.0f, 1.0f, 1.0f, 1.0f, 1.0f, 1.0f, 1.0f};
+    set8<FP8>(ONES, one, 1.0f);
+  }
 
   // the network on one 32-pixel group; xv holds this lane's half of the
   // group's K inputs (half 0: inputs 0..7, half 1: inputs 8..15)
@@ -526,7 +562,7 @@ __global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
       for (int c = 0; c < 2; ++c) {
         float hv[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) hv[e] = fmaf(acc[8 * c + e], dq0, B1v[t][8 * c + e]);
+        for (int e = 0; e < 8; ++e) hv[e] = NB ? acc[8 * c + e] : fmaf(acc[8 * c + e], dq0, B1v[t][8 * c + e]);
         set8_relu<FP8>(Hb[2 * t + c], hv, ia1);
       }
     }
@@ -534,13 +570,14 @@ __global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
 #pragma unroll
     for (int t = 0; t < T2; ++t) {
       f32x16 acc = {};
+      if constexpr (NB != 0) acc = mfma<FP8>(A2b[t], ONES, acc);
 #pragma unroll
       for (int c = 0; c < C2; ++c) acc = mfma<FP8>(A2[t][c], Hb[c], acc);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         float hv[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) hv[e] = fmaf(acc[8 * c + e], dq1, B2v[t][8 * c + e]);
+        for (int e = 0; e < 8; ++e) hv[e] = NB ? acc[8 * c + e] : fmaf(acc[8 * c + e], dq1, B2v[t][8 * c + e]);
         set8_relu<FP8>(Hb2[2 * t + c], hv, ia2);
       }
     }
@@ -554,32 +591,38 @@ __global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
 
   // software pipeline: the loads of the wave's next step are in flight while
   // the network runs on the current one
+  // The loads are unconditional (a branch around them would merge register
+  // sets and wait on the loads there): a lane past the end loads pixel P - 1,
+  // and the wave's last step prefetches its own pixels again (cache hits);
+  // neither is used.
+  auto run = [&](auto full) {
+  if (wave >= nsteps) return;
   PixRaw r;
-  r.n = 0;
   int pn = wave * 64 + lane;
-  const Full full = full_grids<MODE>(a, g);
-  if (wave < nsteps && pn < P) issue_loads<MODE>(a, g, full, pn, r);
+  issue_loads<MODE>(a, g, full, pn < P ? pn : P - 1, r);
   for (int st = wave; st < nsteps; st += nwaves) {
     const int p = pn;
     const bool live = p < P;
     const PixIn in = blend<MODE>(r, full);
     const int sn = st + nwaves;
     pn = sn * 64 + lane;
-    r.n = 0;
-    if (sn < nsteps && pn < P) issue_loads<MODE>(a, g, full, pn, r);
+    const int q = sn < nsteps ? pn : p;
+    issue_loads<MODE>(a, g, full, q < P ? q : P - 1, r);
     // group A is the pixels of lanes 0..31, group B those of lanes 32..63; a
     // group's inputs 0..7 go to half 0 and 8..15 to half 1 of the same
     // column, so each lane exchanges one half with its xor-32 partner
     const bool need = live && in.n >= 3 && !in.flat;
+    // K slots past the inputs: 1 in the layer-1 bias slots, else 0
+    auto cst = [](int k) { return k >= NIN && k < NIN + NB ? 1.0f : 0.0f; };
     float own[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) own[e] = (e < n_inputs<MODE>() && need) ? in.x[e < 11 ? e : 0] : 0.0f;
+    for (int e = 0; e < 16; ++e) own[e] = e < NIN ? (need ? in.x[e < 11 ? e : 0] : 0.0f) : cst(e);
     float xa[8], xb[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const float lo = own[e], hi = own[8 + e];
-      const float lo_x = e < n_inputs<MODE>() ? __shfl_xor(lo, 32) : 0.0f;
-      const float hi_x = 8 + e < n_inputs<MODE>() ? __shfl_xor(hi, 32) : 0.0f;
+      const float lo_x = e < NIN ? __shfl_xor(lo, 32) : cst(e);
+      const float hi_x = 8 + e < NIN ? __shfl_xor(hi, 32) : cst(8 + e);
       xa[e] = half == 0 ? lo : hi_x;
       xb[e] = half == 0 ? lo_x : hi;
     }
@@ -597,6 +640,14 @@ __global__ __launch_bounds__(256) void infer_mfma_kernel(InferArgs a) {
       else store_pixel<MODE>(a, p, in, b0, b1, b2);
     }
   }
+  };
+  // one loop per case (wave-uniform). A full-resolution pass-3 grid under a
+  // reduced pass-2 grid takes the general loop: its taps are the sample
+  // itself and its second tap has weight 0, which the blend returns exactly.
+  const Full full = full_grids<MODE>(a, g);
+  if (full.g2 && full.g3) run(FullC<true, true>{});
+  else if (full.g2) run(FullC<true, false>{});
+  else run(FullC<false, false>{});
 }
 
 template <int H1, int H2, int MODE>

@@ -62,6 +62,7 @@ def feature_pass_bytes(fr, grids):
 
 FEATURE_SOURCES = ("paper_2606_16747_amd/csrc/features.hip", "paper_2606_16747_amd/csrc/internal.h")
 COUNTERS_RECORD = "profiles/features_c2_1080p_counters.json"
+EVENT_EVERY = 4  # timed-region steps whose features launches carry events
 PROFILE_SUMMARY = "profiles/features_c2_1080p.md"
 PROFILE_COMMANDS = (
     "rocprofv3 --kernel-trace --stats -d $PROF_DIR/trace -o trace -- "
@@ -113,13 +114,15 @@ def profile_summary(d, calib_mb):
 
     bench = {n: bench_line(os.path.join(d, n + ".json")) for n in ("trace", "fetch", "write")}
     i0, i1 = bench["trace"]["roofline"]["dispatch_range"]
+    ids = bench["trace"]["roofline"]["timed_dispatches"]
     for n in ("fetch", "write"):
-        if bench[n]["roofline"]["dispatch_range"] != [i0, i1]:
+        if (bench[n]["roofline"]["dispatch_range"] != [i0, i1]
+                or bench[n]["roofline"]["timed_dispatches"] != ids):
             raise SystemExit("profiled runs launched different sequences")
     con = db("trace")
     feat = con.execute("select dispatch_id, duration from kernels where name like '%features_kernel%' "
                        "order by dispatch_id").fetchall()
-    timed = [dur for _, dur in feat[i0:i1]]
+    timed = [feat[i][1] for i in ids]
     # every kernel from the first timed features launch to the end of the
     # step's last frame (the reprojection after the last timed features
     # launch): the whole timed region's mix
@@ -139,7 +142,7 @@ def profile_summary(d, calib_mb):
                          "group by dispatch_id order by dispatch_id", (counter,)).fetchall()
         f = [v for _, k, v in rows if "features_kernel" in k]
         cp = [v for _, k, v in rows if "copyBuffer" in k]
-        return f[i0:i1], max(cp)
+        return [f[i] for i in ids], max(cp)
 
     fk, fcal = per_dispatch("fetch", "FETCH_SIZE")
     wk, wcal = per_dispatch("write", "WRITE_SIZE")
@@ -151,7 +154,9 @@ def profile_summary(d, calib_mb):
         "kernel": "starnt_features (features_kernel<false, false>), 1080p sequence, timed region",
         "sources": list(FEATURE_SOURCES),
         "source_sha256": feature_sources_sha256(),
-        "launches": i1 - i0,
+        "launches": len(ids),
+        "dispatches": "the features launches timed with events in the bench's timed region (every %d. step)"
+                      % EVENT_EVERY,
         "fetch_kib_per_launch_raw": round(float(np.mean(fk)), 1),
         "write_kib_per_launch_raw": round(float(np.mean(wk)), 1),
         "copy_calibration_mib": calib_mb,
@@ -176,7 +181,8 @@ def profile_summary(d, calib_mb):
     for name, calls, tot, avg, pct in top:
         short = name.replace("(anonymous namespace)::", "").split("(")[0][:90]
         lines.append("| %s | %d | %.2f | %.2f | %.1f |" % (short, calls, tot / 1e3, avg, pct))
-    lines += ["", "## Features launches of the timed region (dispatches %d..%d of the kernel)" % (i0, i1 - 1), "",
+    lines += ["", "## Features launches timed with events (%d of the timed region's dispatches %d..%d of the kernel: "
+              "those of every %d. step)" % (len(ids), i0, i1 - 1, EVENT_EVERY), "",
               "* rocprofv3 average duration: %.2f us (min %.2f, max %.2f, %d launches)"
               % (np.mean(timed) / 1e3, np.min(timed) / 1e3, np.max(timed) / 1e3, len(timed)),
               "* HIP-event average inside bench.py (same run): %.2f us" % bench["trace"]["roofline"]["avg_launch_us"],
@@ -366,13 +372,20 @@ def main():
     log("grids per real frame: %s" % grids)
 
     # ---- timed region -----------------------------------------------------
-    # events around every features launch, on the stream the launches use
+    # events around the features launches of every EVENT_EVERY-th step, on the
+    # stream the launches use. A timing event's record leaves the GPU idle for
+    # about 6 us (two per launch), so timing every launch would add ~6% to the
+    # step; the sampled launches' dispatch ids go into the bench line so the
+    # profile summary averages exactly those launches.
     ev = []
+    ev_ids = []
+    sample = [False]
 
     def timer(name, fn):
-        if name == "features":
+        if name == "features" and sample[0]:
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
+            ev_ids.append(st.features_launches)
             a.record()
             fn()
             b.record()
@@ -391,7 +404,8 @@ def main():
     w0 = time.perf_counter()
     fl0 = st.features_launches
     e0.record()
-    for _ in range(args.steps):
+    for i in range(args.steps):
+        sample[0] = i % EVENT_EVERY == 0
         star_step()
     e1.record()
     torch.cuda.synchronize()
@@ -489,8 +503,15 @@ def main():
     psnr_favg = mode_psnr(st.MODE_FAVG)
     psnr_f0 = mode_psnr(st.MODE_F0)
 
-    # per-call breakdown (one extra step with events around every call)
+    # per-call breakdown (extra steps with events around every call)
     names = {}
+
+    def gpu_lead():
+        # The GPU spins for a few ms first, so the whole step is queued
+        # before it reaches the step's calls: each event pair then brackets
+        # its call's kernels back to back, not the host's time to launch them
+        # (a call's host side can outlast a 15-40 us kernel).
+        torch.cuda._sleep(10_000_000)
 
     def timer_all(name, fn):
         a = torch.cuda.Event(enable_timing=True)
@@ -502,8 +523,9 @@ def main():
 
     rend.timer = timer_all
     for _ in range(3):
+        gpu_lead()
         star_step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
     rend.timer = None
     breakdown = {k: round(1e3 * float(np.mean([a.elapsed_time(b) for a, b in v])), 2) for k, v in names.items()}
 
@@ -612,6 +634,7 @@ def main():
         pnames.setdefault(name, []).append((a, b))
 
     patr.timer = timer_patch
+    gpu_lead()
     patch_step(record=True)
     torch.cuda.synchronize()
     patr.timer = None
@@ -704,10 +727,11 @@ def main():
     mlp_flops = float(np.mean([flop_px * int((np.diff(host[t].offsets) >= 3).sum()) for t in real_ts]))
     mlp_s = breakdown["infer_composite"] * 1e-6
     per_step = [feature_pass_bytes(host[t], grids[t]) for t in real_ts]
-    alg_bytes = sum(b for b, _ in per_step) * args.steps
+    timed_steps = len(range(0, args.steps, EVENT_EVERY))
+    alg_bytes = sum(b for b, _ in per_step) * timed_steps
     feat_total_s = sum(feat_ms) / 1e3
     achieved = alg_bytes / feat_total_s / 1e9
-    frags_read = sum(host[t].num_frags for t in real_ts) * args.steps
+    frags_read = sum(host[t].num_frags for t in real_ts) * timed_steps
     traffic = counters_traffic(os.path.join(ROOT, COUNTERS_RECORD), feature_sources_sha256())
 
     total_frags = sum(f.num_frags for f in host)
@@ -781,9 +805,12 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "kernel": "starnt_features (passes 1-3)",
-                     "algorithmic_bytes_per_launch": int(alg_bytes / args.steps / len(real_ts)),
+                     "algorithmic_bytes_per_launch": int(alg_bytes / timed_steps / len(real_ts)),
                      "avg_launch_us": round(1e3 * float(np.mean(feat_ms)), 2),
-                     "dispatch_range": [fl0, fl1]},
+                     "timed_launches": "events around the features launches of every %d. step of the "
+                                       "timed region (%d of %d launches)" % (EVENT_EVERY, len(feat_ms), fl1 - fl0),
+                     "dispatch_range": [fl0, fl1],
+                     "timed_dispatches": ev_ids},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

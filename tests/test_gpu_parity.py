@@ -387,9 +387,12 @@ def test_train_step_bf16_gradient_direction(starnt, gpu, sg, oracle_mod):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
-@pytest.mark.parametrize("s2,s3", [(1.0, 1.0), (0.6, 0.35)])
+@pytest.mark.parametrize("s2,s3", [(1.0, 1.0), (0.6, 0.35), (1.0, 0.5), (0.6, 1.0)])
 def test_infer_composite_equals_two_calls(starnt, gpu, sg, dtype, s2, s3):
-    """The fused call gives the same image as starnt_infer + starnt_composite."""
+    """The fused call gives the same image as starnt_infer + starnt_composite,
+    for each case of which grids are at full resolution (the fused kernel
+    runs one loop per case; a full pass-3 grid under a reduced pass-2 grid
+    takes the general loop, whose weight-0 taps must return the sample)."""
     fr = _frame(sg, width=301, height=97, num_tris=50)
     W, H = fr.width, fr.height
     sched = starnt.new_sched(W, H, s2, s3)
@@ -405,6 +408,33 @@ def test_infer_composite_equals_two_calls(starnt, gpu, sg, dtype, s2, s3):
     starnt.starnt_infer_composite(mlp, fb, sched, (0.1, 0.5, 0.9), rgb)
     sync()
     assert np.abs(to_np(rgb) - two).max() <= 1e-6
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_infer_full_pass3_grid_independent_of_pass2_grid(starnt, gpu, sg, dtype):
+    """The tail network reads only the pass-3 grid. With that grid at full
+    resolution, a reduced pass-2 grid sends the matrix-core kernel through its
+    general loop (bilinear taps, weight 0) instead of the full-resolution one;
+    the tail colours must be bitwise the same either way."""
+    fr = _frame(sg, width=301, height=97, num_tris=50)
+    W, H = fr.width, fr.height
+    sched_a = starnt.new_sched(W, H, 0.6, 1.0)
+    sched_b = starnt.new_sched(W, H, 1.0, 1.0)
+    df, fb = run_features(starnt, fr, sched=sched_a, max_per_pixel=64)
+    Ws, bs = sg.init_mlp((16, 32, 32, 3), out_bias=0.05)
+    kw = {}
+    if dtype == "fp8":
+        kw["fp8_scales"] = [1.0 / 16, float(np.abs(Ws[0]).max()) / 448, 4.0 / 448, float(np.abs(Ws[1]).max()) / 448,
+                            4.0 / 448, float(np.abs(Ws[2]).max()) / 448]
+    mlp = starnt.DeviceMlp(Ws, bs, {"bf16": starnt.BF16, "fp8": starnt.FP8}[dtype], **kw)
+    outs = []
+    for sched in (sched_a, sched_b):
+        out = torch.full((W * H, 3), -1.0, dtype=torch.float32, device="cuda")
+        starnt.starnt_infer(mlp, fb.tail, fb.count, sched, W, H, out)
+        outs.append(out)
+    sync()
+    assert torch.equal(outs[0], outs[1])
+    assert float(outs[0].abs().sum()) > 0.0
 
 
 def _fp8_scales(oracle_mod, Ws, bs, x):

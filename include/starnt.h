@@ -300,7 +300,7 @@ int starnt_quadtree(const float* rgb, const uint32_t* count, int32_t width, int3
  * frame the source is clamped to the nearest edge pixel and src[p] = -1; when
  * h_w <= 0, src[p] = -1 and rgb_out[p] = rgb_prev[p].
  * m_minus_i is a host float[16], row-major, acting on column vectors.
- * src may be NULL. */
+ * src may be NULL. rgb_out must not overlap rgb_prev or d1_prev (EINVAL). */
 int starnt_reproject(const float* rgb_prev, const float* d1_prev, int32_t width, int32_t height,
                      const float* m_minus_i, float* rgb_out, int32_t* src, void* stream);
 
@@ -312,7 +312,7 @@ int starnt_reproject(const float* rgb_prev, const float* d1_prev, int32_t width,
  * written to list (device uint32 [width*height], the caller's) in increasing
  * pixel order, and *list_count (device uint32) receives their number; the
  * compaction is deterministic (no atomics). src may be NULL; depth_tol must
- * be finite and >= 0.
+ * be finite and >= 0; rgb_out must not overlap rgb_prev or d1_prev (EINVAL).
  * Workspace: starnt_workspace_size(STARNT_WS_REPROJECT, W, H, 0) bytes,
  * 256-byte aligned (EINVAL otherwise; ENOMEM when smaller). */
 int starnt_reproject_check(const float* rgb_prev, const float* d1_prev, int32_t width, int32_t height,

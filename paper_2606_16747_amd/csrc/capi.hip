@@ -197,12 +197,24 @@ int starnt_quadtree(const float* rgb, const uint32_t* count, int32_t width, int3
                          as_stream(stream));
 }
 
+// [a, a + na) and [b, b + nb) share a byte (addresses compared as integers)
+static bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + nb && y < x + na;
+}
+// the gather's output [P][3] against its inputs rgb [P][3] and d1 [P]
+static bool gather_overlaps(const float* rgb, const float* d1, const float* out, int32_t w, int32_t h) {
+  const size_t P = (size_t)w * (size_t)h;
+  return ranges_overlap(out, 12 * P, rgb, 12 * P) || ranges_overlap(out, 12 * P, d1, 4 * P);
+}
+
 int starnt_reproject(const float* rgb_prev, const float* d1_prev, int32_t width, int32_t height,
                      const float* m_minus_i, float* rgb_out, int32_t* src, void* stream) {
   int rc = check_frame(width, height, "starnt_reproject");
   if (rc) return rc;
   if (!rgb_prev || !d1_prev || !m_minus_i || !rgb_out) return fail(STARNT_EINVAL, "starnt_reproject: NULL argument");
-  if (rgb_prev == rgb_out) return fail(STARNT_EINVAL, "starnt_reproject: rgb_out aliases rgb_prev");
+  if (gather_overlaps(rgb_prev, d1_prev, rgb_out, width, height))
+    return fail(STARNT_EINVAL, "starnt_reproject: rgb_out overlaps rgb_prev or d1_prev");
   for (int i = 0; i < 16; ++i)
     if (!std::isfinite(m_minus_i[i])) return fail(STARNT_EINVAL, "starnt_reproject: non-finite matrix");
   return launch_reproject(rgb_prev, d1_prev, width, height, m_minus_i, rgb_out, src, as_stream(stream));
@@ -215,7 +227,8 @@ int starnt_reproject_check(const float* rgb_prev, const float* d1_prev, int32_t 
   if (rc) return rc;
   if (!rgb_prev || !d1_prev || !m_minus_i || !rgb_out || !list || !list_count)
     return fail(STARNT_EINVAL, "starnt_reproject_check: NULL argument");
-  if (rgb_prev == rgb_out) return fail(STARNT_EINVAL, "starnt_reproject_check: rgb_out aliases rgb_prev");
+  if (gather_overlaps(rgb_prev, d1_prev, rgb_out, width, height))
+    return fail(STARNT_EINVAL, "starnt_reproject_check: rgb_out overlaps rgb_prev or d1_prev");
   for (int i = 0; i < 16; ++i)
     if (!std::isfinite(m_minus_i[i])) return fail(STARNT_EINVAL, "starnt_reproject_check: non-finite matrix");
   if (!std::isfinite(depth_tol) || depth_tol < 0.0f)

@@ -79,9 +79,13 @@ __global__ __launch_bounds__(kBlock) void reproject_kernel(ReprojArgs a) {
       const int cy = (int)(qy < 0 ? 0 : (qy > a.H - 1 ? a.H - 1 : qy));
       s = cy * a.W + cx;
     }
-    a.out[3 * (size_t)p + 0] = a.rgb[3 * (size_t)s + 0];
-    a.out[3 * (size_t)p + 1] = a.rgb[3 * (size_t)s + 1];
-    a.out[3 * (size_t)p + 2] = a.rgb[3 * (size_t)s + 2];
+    // all three loads before any store: stores ahead of a load to memory that
+    // might alias would each wait for the load (three round trips, not one);
+    // the entry points reject an output that overlaps an input
+    const float c0 = a.rgb[3 * (size_t)s + 0], c1 = a.rgb[3 * (size_t)s + 1], c2 = a.rgb[3 * (size_t)s + 2];
+    a.out[3 * (size_t)p + 0] = c0;
+    a.out[3 * (size_t)p + 1] = c1;
+    a.out[3 * (size_t)p + 2] = c2;
     if (a.src) a.src[p] = q;
   }
   if (a.mask) {  // uniform over the launch

@@ -79,7 +79,8 @@ def test_host_validation_rejects_bad_arguments(starnt):
     qp = starnt.QtParams(64, 0.05, 0.1, 2)  # merge above split
     assert lib.starnt_quadtree(16, 16, 64, 64, ctypes.byref(qp), None, 16, 16, 16, 16, 1 << 20, None) == 1
     m = (ctypes.c_float * 16)(*([0.0] * 15 + [float("nan")]))
-    assert lib.starnt_reproject(16, 32, 8, 8, m, 48, None, None) == 1
+    assert lib.starnt_reproject(1 << 20, 2 << 20, 8, 8, m, 3 << 20, None, None) == 1
+    assert b"non-finite" in lib.starnt_last_error()
     mlp = starnt.Mlp(5, 32, 32, 3, 0, 16, 16, 16, 16, 16, 16, None)  # in must be 16
     assert lib.starnt_infer(ctypes.byref(mlp), 16, 16, None, 8, 8, 16, None) == 1
     mlp = starnt.Mlp(16, 32, 32, 3, 3, 16, 16, 16, 16, 16, 16, None)  # FP8 without scales
@@ -103,15 +104,31 @@ def test_host_validation_rejects_bad_arguments(starnt):
                    ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     need = starnt.starnt_workspace_size(starnt.WS_REPROJECT, 8, 8)
     assert need >= 8 + 2 * 4
-    assert rc(16, 32, 8, 8, m, -0.5, 48, None, 64, 80, 256, need, None) == 1  # negative tolerance
+    # fake device addresses (never dereferenced): rgb [64][3], d1 [64], out
+    # [64][3] in disjoint ranges
+    RGB, D1, OUT = 1 << 20, 2 << 20, 3 << 20
+    assert rc(RGB, D1, 8, 8, m, -0.5, OUT, None, 64, 80, 256, need, None) == 1  # negative tolerance
     assert b"depth_tol" in lib.starnt_last_error()
-    assert rc(16, 32, 8, 8, m, float("inf"), 48, None, 64, 80, 256, need, None) == 1
-    assert rc(16, 32, 8, 8, m, 0.01, 48, None, None, 80, 256, need, None) == 1  # no list
-    assert rc(16, 16, 8, 8, m, 0.01, 16, None, 64, 80, 256, need, None) == 1    # output aliases input
-    assert rc(16, 32, 8, 8, m, 0.01, 48, None, 64, 80, 256, need - 1, None) == 3  # workspace too small
-    assert rc(16, 32, 8, 8, m, 0.01, 48, None, 64, 80, 272, need, None) == 1      # misaligned workspace
+    assert rc(RGB, D1, 8, 8, m, float("inf"), OUT, None, 64, 80, 256, need, None) == 1
+    assert rc(RGB, D1, 8, 8, m, 0.01, OUT, None, None, 80, 256, need, None) == 1  # no list
+    assert rc(RGB, D1, 8, 8, m, 0.01, RGB, None, 64, 80, 256, need, None) == 1    # output aliases input
+    assert b"overlaps" in lib.starnt_last_error()
+    assert rc(RGB, D1, 8, 8, m, 0.01, RGB + 764, None, 64, 80, 256, need, None) == 1  # last float shared
+    assert rc(RGB, D1, 8, 8, m, 0.01, D1 - 767, None, 64, 80, 256, need, None) == 1   # first d1 byte shared
+    assert rc(RGB, D1, 8, 8, m, 0.01, OUT, None, 64, 80, 256, need - 1, None) == 3  # workspace too small
+    assert rc(RGB, D1, 8, 8, m, 0.01, OUT, None, 64, 80, 272, need, None) == 1      # misaligned workspace
     assert b"aligned" in lib.starnt_last_error()
-    assert rc(16, 32, 8, 8, m, 0.01, 48, None, 64, 80, None, need, None) == 1
+    assert rc(RGB, D1, 8, 8, m, 0.01, OUT, None, 64, 80, None, need, None) == 1
+    # an output right after the colour range and right before d1 overlaps nothing
+    assert rc(RGB, D1, 8, 8, m, -1.0, RGB + 768, None, 64, 80, 256, need, None) == 1
+    assert b"depth_tol" in lib.starnt_last_error()
+    assert rc(RGB, D1, 8, 8, m, -1.0, D1 - 768, None, 64, 80, 256, need, None) == 1
+    assert b"depth_tol" in lib.starnt_last_error()
+    rp = lib.starnt_reproject
+    rp.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    assert rp(RGB, D1, 8, 8, m, D1 + 100, None, None) == 1
+    assert b"overlaps" in lib.starnt_last_error()
     fr = starnt.Frags(8, 8, 16, 16, 16, 0, 16, 10, 1)
     slots = starnt.Feats(4, 1, 16, 16, 16, 16, 16, None, 16, None)
     mlp = starnt.Mlp(16, 32, 32, 3, 0, 16, 16, 16, 16, 16, 16, None)

@@ -175,20 +175,41 @@ __global__ __launch_bounds__(kRP * kRG) void train_reduce_adam(AdamArgs a) {
   const int c = threadIdx.x % kRP, r = threadIdx.x / kRP;
   const int i = blockIdx.x * kRP + c;
   float g = 0.0f;
-  if (i < a.nparam)
-    for (int b = r; b < a.nblocks; b += kRG) g += a.partial[(size_t)b * a.nparam + i];
+  if (i < a.nparam) {
+    // four loads in flight per step, added in the same order as one by one
+    int b = r;
+    for (; b + 3 * kRG < a.nblocks; b += 4 * kRG) {
+      const float p0 = a.partial[(size_t)b * a.nparam + i];
+      const float p1 = a.partial[(size_t)(b + kRG) * a.nparam + i];
+      const float p2 = a.partial[(size_t)(b + 2 * kRG) * a.nparam + i];
+      const float p3 = a.partial[(size_t)(b + 3 * kRG) * a.nparam + i];
+      g += p0;
+      g += p1;
+      g += p2;
+      g += p3;
+    }
+    for (; b < a.nblocks; b += kRG) g += a.partial[(size_t)b * a.nparam + i];
+  }
   s_part[r][c] = g;
+  // the optimiser state is read before any store (a store ahead of a load
+  // from a pointer that might alias it would wait for the load)
+  float m0 = 0.0f, v0 = 0.0f, w0 = 0.0f;
+  if (r == 0 && i < a.nparam) {
+    m0 = a.m[i];
+    v0 = a.v[i];
+    w0 = a.params[i];
+  }
   __syncthreads();
   if (r == 0 && i < a.nparam) {
     float t = 0.0f;
     for (int k = 0; k < kRG; ++k) t += s_part[k][c];
+    const float m = fmaf(a.b1, m0, (1.0f - a.b1) * t);
+    const float v = fmaf(a.b2, v0, (1.0f - a.b2) * t * t);
+    const float mh = m / a.c1, vh = v / a.c2;
     a.grad[i] = t;
-    const float m = fmaf(a.b1, a.m[i], (1.0f - a.b1) * t);
-    const float v = fmaf(a.b2, a.v[i], (1.0f - a.b2) * t * t);
     a.m[i] = m;
     a.v[i] = v;
-    const float mh = m / a.c1, vh = v / a.c2;
-    a.params[i] -= a.lr * mh / (sqrtf(vh) + a.eps);
+    a.params[i] = w0 - a.lr * mh / (sqrtf(vh) + a.eps);
   }
   if (blockIdx.x == 0) {
     // loss: per-thread strided sums, then a fixed-order tree

@@ -470,6 +470,49 @@ def main():
     torch.cuda.synchronize()
     step_each = np.array([a.elapsed_time(b) for a, b in sev])
 
+    # the same step replayed from a HIP graph captured once, so the host's
+    # launch work leaves the loop; every replay (eager work in between) must
+    # reproduce an eager step's frames bitwise. Informational: the headline
+    # above is the eager step.
+    try:
+        star_step()
+        torch.cuda.synchronize()
+        ref = [o.clone() for o in outs]
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            star_step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        cg = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(cg):
+            star_step()
+        torch.cuda.synchronize()
+        same = True
+        for _ in range(3):
+            for o in outs:
+                o.fill_(-1.0)
+            cg.replay()
+            torch.cuda.synchronize()
+            same = same and all(torch.equal(o, r) for o, r in zip(outs, ref))
+            star_step()
+            torch.cuda.synchronize()
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        g0.record()
+        for _ in range(args.steps):
+            cg.replay()
+        g1.record()
+        torch.cuda.synchronize()
+        graph_ms = g0.elapsed_time(g1) / args.steps
+        graph = {"step_ms": round(graph_ms, 4), "replays_equal_eager": bool(same), "steps": args.steps,
+                 "gfrag_per_s": round(sum(f.num_frags for f in host) / (graph_ms * 1e-3) / 1e9, 2) if same else None}
+        del cg
+        log("graph-replayed step %.3f ms (replays equal eager: %s)" % (graph_ms, same))
+    except RuntimeError as exc:
+        graph = {"step_ms": None, "error": str(exc)[:300]}
+        log("graph capture failed: %s" % exc)
+
     # quality of the last timed step against the exact composite
     star_step()
     torch.cuda.synchronize()
@@ -775,6 +818,7 @@ def main():
         "baselines": {k: {"ms_per_frame": round(base_ms[k], 4), "psnr_db_mean": round(base_psnr[k][0], 2),
                           "mse_mean": round(base_psnr[k][1], 8)} for k in base_ms},
         "kernel_gfrag_per_s": round(frags_read / feat_total_s / 1e9, 2),
+        "graph_replay": graph,
         "step_ms": {"p5": round(float(np.percentile(step_each, 5)), 4),
                     "p50": round(float(np.percentile(step_each, 50)), 4),
                     "p95": round(float(np.percentile(step_each, 95)), 4), "n": int(len(step_each)),

@@ -268,7 +268,7 @@ def main():
         profile_summary(args.profile_summary, args.calib_copy_mb or 512)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
+        print("bench.py measures one GPU: the library has no multi-GPU path (--gpus %d refused)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 

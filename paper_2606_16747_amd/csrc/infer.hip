@@ -427,8 +427,12 @@ constexpr int kMaxParams = 64 * 16 + 64 + 64 * 64 + 64 + 3 * 64 + 3;
 // A wave step covers 64 pixels: every lane loads its own pixel, the second
 // 32-pixel group's inputs cross to lane half 0 with one xor-32 shuffle, and
 // its outputs cross back the same way.
+// The 32-wide networks are held to 3 waves per SIMD (at most 168 VGPRs; a few
+// variants spill a few dwords for it); at 4 waves (128 VGPRs) the BF16
+// composite measured slower.
 template <int T1, int T2, bool FP8, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T1 * T2 == 1 ? 3 : 1))) void infer_mfma_kernel(InferArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(T1 * T2 == 1 ? 3 : 1)))
+void infer_mfma_kernel(InferArgs a) {
   __shared__ float s_w[kMaxParams];
   using V = typename Op<FP8>::vec;
   // stage weights: W1 [h1][16], b1, W2 [h2][h1], b2, W3 [3][h2], b3

@@ -60,6 +60,17 @@ def feature_pass_bytes(fr, grids):
     return reads + writes, int(n[s3].sum())
 
 
+def infer_pass_bytes(W, H, grids):
+    """Algorithmic HBM bytes of one starnt_infer_composite launch on these
+    grids: count and layer 1 per pixel, each pass-2 sample and each 32-byte
+    pass-3 record once, and the composite written per pixel."""
+    w2, h2, w3, h3 = grids
+    P = W * H
+    return (4 + 16 + 12) * P + 16 * w2 * h2 + 32 * w3 * h3
+
+
+INFER_KERNEL = "infer_mfma_kernel<1, 1, false, 1>"  # BF16 16-32-32-3 with the eq (3) composite
+
 FEATURE_SOURCES = ("paper_2606_16747_amd/csrc/features.hip", "paper_2606_16747_amd/csrc/internal.h")
 COUNTERS_RECORD = "profiles/features_c2_1080p_counters.json"
 EVENT_EVERY = 4  # timed-region steps whose features launches carry events
@@ -67,9 +78,9 @@ PROFILE_SUMMARY = "profiles/features_c2_1080p.md"
 PROFILE_COMMANDS = (
     "rocprofv3 --kernel-trace --stats -d $PROF_DIR/trace -o trace -- "
     "python3 $REPO/bench.py --no-cpu-baseline --calib-copy-mb 512 > $PROF_DIR/trace.json",
-    "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'features_kernel|copyBuffer' -d $PROF_DIR/fetch -o fetch "
+    "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'features_kernel|infer_mfma|copyBuffer' -d $PROF_DIR/fetch -o fetch "
     "-- python3 $REPO/bench.py --no-cpu-baseline --calib-copy-mb 512 > $PROF_DIR/fetch.json",
-    "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex 'features_kernel|copyBuffer' -d $PROF_DIR/write -o write "
+    "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex 'features_kernel|infer_mfma|copyBuffer' -d $PROF_DIR/write -o write "
     "-- python3 $REPO/bench.py --no-cpu-baseline --calib-copy-mb 512 > $PROF_DIR/write.json",
     "python3 $REPO/bench.py --profile-summary $PROF_DIR --calib-copy-mb 512",
 )
@@ -146,6 +157,18 @@ def profile_summary(d, calib_mb):
 
     fk, fcal = per_dispatch("fetch", "FETCH_SIZE")
     wk, wcal = per_dispatch("write", "WRITE_SIZE")
+    # inference launches inside the timed region, by their order among the
+    # process's launches of that kernel (the same in every profiled run)
+    inf = con.execute("select dispatch_id, start, duration from kernels where name like ? order by dispatch_id",
+                      ("%" + INFER_KERNEL + "%",)).fetchall()
+    iord = [j for j, (_, st0, _) in enumerate(inf) if t0 <= st0 < t1]
+
+    def infer_counter(name, counter):
+        c = db(name)
+        rows = c.execute("select dispatch_id, kernel_name, sum(value) from counters_collection where counter_name = ? "
+                         "group by dispatch_id order by dispatch_id", (counter,)).fetchall()
+        v = [x for _, k, x in rows if INFER_KERNEL in k]
+        return [v[j] for j in iord if j < len(v)]
     ffac, wfac = calib_mb * 1024.0 / fcal, calib_mb * 1024.0 / wcal
     fetch_b = float(np.mean(fk)) * 1024 * ffac
     write_b = float(np.mean(wk)) * 1024 * wfac
@@ -200,6 +223,20 @@ def profile_summary(d, calib_mb):
     for name, calls, avg, tot in region:
         short = name.replace("(anonymous namespace)::", "").split("(")[0][:90]
         lines.append("| %s | %d | %.2f | %.2f |" % (short, calls, avg / 1e3, tot / 1e6))
+    ri = bench["trace"].get("roofline_infer")
+    fi, wi = infer_counter("fetch", "FETCH_SIZE"), infer_counter("write", "WRITE_SIZE")
+    if ri and iord and fi and wi:
+        idur = float(np.mean([inf[j][2] for j in iord])) / 1e3
+        ialg = ri["algorithmic_bytes_per_launch"]
+        ifb, iwb = float(np.mean(fi)) * 1024 * ffac, float(np.mean(wi)) * 1024 * wfac
+        lines += ["", "## Inference launches of the timed region (%s, %d launches)" % (INFER_KERNEL, len(iord)), "",
+                  "* rocprofv3 average duration: %.2f us; bench per-call average (events): %.2f us"
+                  % (idur, ri["avg_launch_us"]),
+                  "* algorithmic bytes per launch: %d (count, layer 1, each pass-2 sample and 32-byte pass-3 record "
+                  "once, the composite out); %.2f TB/s over the rocprofv3 duration = %.3f of 8 TB/s"
+                  % (ialg, ialg / idur / 1e6, ialg / idur / 1e6 / 8.0),
+                  "* FETCH_SIZE %.1f KiB x %.3f = %d B; WRITE_SIZE %.1f KiB x %.3f = %d B; traffic / algorithmic: %.3f"
+                  % (float(np.mean(fi)), ffac, int(ifb), float(np.mean(wi)), wfac, int(iwb), (ifb + iwb) / ialg)]
     lines.append("")
     with open(os.path.join(ROOT, PROFILE_SUMMARY), "w") as f:
         f.write("\n".join(lines))
@@ -769,6 +806,7 @@ def main():
     flop_px = 2 * (5 * h1 + h1 * h2 + h2 * 3)
     mlp_flops = float(np.mean([flop_px * int((np.diff(host[t].offsets) >= 3).sum()) for t in real_ts]))
     mlp_s = breakdown["infer_composite"] * 1e-6
+    infer_bytes = float(np.mean([infer_pass_bytes(W, H, grids[t]) for t in real_ts]))
     per_step = [feature_pass_bytes(host[t], grids[t]) for t in real_ts]
     timed_steps = len(range(0, args.steps, EVENT_EVERY))
     alg_bytes = sum(b for b, _ in per_step) * timed_steps
@@ -819,6 +857,12 @@ def main():
                           "mse_mean": round(base_psnr[k][1], 8)} for k in base_ms},
         "kernel_gfrag_per_s": round(frags_read / feat_total_s / 1e9, 2),
         "graph_replay": graph,
+        "roofline_infer": {"kernel": "starnt_infer_composite (BF16 16-32-32-3, eq (3))", "bound": "hbm",
+                           "achieved": round(infer_bytes / mlp_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(infer_bytes / mlp_s / 1e9 / HBM_PEAK_GBS, 4),
+                           "algorithmic_bytes_per_launch": int(infer_bytes),
+                           "avg_launch_us": breakdown["infer_composite"],
+                           "note": "per-call breakdown timing (events behind a GPU spin)"},
         "step_ms": {"p5": round(float(np.percentile(step_each, 5)), 4),
                     "p50": round(float(np.percentile(step_each, 50)), 4),
                     "p95": round(float(np.percentile(step_each, 95)), 4), "n": int(len(step_each)),

@@ -9,6 +9,12 @@ and the quadtree update; odd frames are reprojected from the last real frame.
 The same 8 frames are also rendered by the exact sort-and-over path on the
 same GPU, which is the reference for PSNR and the time to beat.
 
+Beside the headline the line carries the fragment pass's roofline (events on
+the features launches of every 4th timed step) and the network call's
+(`roofline_infer`), the step replayed from a HIP graph, the WBOIT and
+stored-order baselines, the selective and patched variants, the 10-feature
+ablation, the training step and the CPU oracle's rate on a sample.
+
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations

@@ -556,6 +556,39 @@ def main():
         graph = {"step_ms": None, "error": str(exc)[:300]}
         log("graph capture failed: %s" % exc)
 
+    # f1: the adaptive interval (Sec. 3.3) on the same sequence: frame costs
+    # measured with events (reported one frame late), at most 4 frames per
+    # real render, for two frame-time targets between a reprojection's cost
+    # and a real frame's (a target out of reach makes every frame real)
+    adr = fm.Renderer(W, H, mlp, base=64, bg=bg)
+    ad_out = [torch.empty(P, 3, dtype=torch.float32, device=dev) for _ in range(NF)]
+    adaptive = []
+    for target in (0.12, 0.09):
+        ad_ms, ad_kinds = [], None
+        for rep in range(6):
+            adr.reset()
+            seq = fm.AdaptiveSequence(adr, target, 4)
+            torch.cuda.synchronize()
+            q0 = torch.cuda.Event(enable_timing=True)
+            q1 = torch.cuda.Event(enable_timing=True)
+            q0.record()
+            for t in range(NF):
+                seq.frame(host[t].vp, lambda t=t: frags[t], ad_out[t])
+            q1.record()
+            torch.cuda.synchronize()
+            if rep > 0:
+                ad_ms.append(q0.elapsed_time(q1) / NF)
+            ad_kinds = list(seq.kinds)
+        ad_psnr = []
+        for t in range(NF):
+            d = (ad_out[t] - exact[t]).double()
+            ad_psnr.append(10 * np.log10(1.0 / float((d * d).mean())))
+        adaptive.append({"target_ms": target, "max_interval": 4,
+                         "kinds": "".join("R" if k else "i" for k in ad_kinds),
+                         "ms_per_frame": round(float(np.mean(ad_ms)), 4),
+                         "psnr_db_mean": round(float(np.mean(ad_psnr)), 2)})
+    log("adaptive interval (R = real, i = reprojected): %s" % adaptive)
+
     # quality of the last timed step against the exact composite
     star_step()
     torch.cuda.synchronize()
@@ -863,6 +896,7 @@ def main():
                           "mse_mean": round(base_psnr[k][1], 8)} for k in base_ms},
         "kernel_gfrag_per_s": round(frags_read / feat_total_s / 1e9, 2),
         "graph_replay": graph,
+        "adaptive_interval": adaptive,
         "roofline_infer": {"kernel": "starnt_infer_composite (BF16 16-32-32-3, eq (3))", "bound": "hbm",
                            "achieved": round(infer_bytes / mlp_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(infer_bytes / mlp_s / 1e9 / HBM_PEAK_GBS, 4),

@@ -11,9 +11,10 @@ same GPU, which is the reference for PSNR and the time to beat.
 
 Beside the headline the line carries the fragment pass's roofline (events on
 the features launches of every 4th timed step) and the network call's
-(`roofline_infer`), the step replayed from a HIP graph, the WBOIT and
-stored-order baselines, the selective and patched variants, the 10-feature
-ablation, the training step and the CPU oracle's rate on a sample.
+(`roofline_infer`), the step replayed from a HIP graph, the adaptive interval
+at two frame-time targets, the WBOIT and stored-order baselines, the
+selective and patched variants, the 10-feature ablation, the training step
+and the CPU oracle's rate on a sample.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """

@@ -201,7 +201,8 @@ class Mlp:
         return y
 
     def forward_q(self, x, qmode, sa=None, sw=None):
-        """Forward with narrow operands: qmode 1 = bf16, 2 = e4m3 with scales."""
+        """Forward with narrow operands: qmode 1 = bf16, 2 = e4m3 with scales
+        (pinned by hand-computed examples in test_oracle_pins_quant_mixed)."""
         x = _c(x, np.float64)
         n = x.shape[0]
         y = np.empty((n, self.dims[3]), np.float64)
@@ -509,7 +510,8 @@ def dfa_learned(lay, tail, tavg, width, height, grids, mlp, bg=(1.0, 1.0, 1.0)):
     upscaled bilinearly (upsample), the full-resolution N gates them (no
     layer 2 where N < 2, no tail where N < 3), the input is dfa_features of
     the upscaled values, and eq (2) composites. mlp is None for the inputs
-    alone. Returns (rgb [P,3], x [P,16], f [P,3])."""
+    alone. Returns (rgb [P,3], x [P,16], f [P,3]). Pinned at s < 1 by
+    hand-computed upscale weights (test_oracle_pins_quant_mixed)."""
     W, H = int(width), int(height)
     P = W * H
     W2, H2, W3, H3 = [int(v) for v in grids]

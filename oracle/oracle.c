@@ -307,6 +307,11 @@ double orc_round_e4m3(double v) { return round_e4m3(v); }
  * bias added in FP64, ReLU, and the next layer's input rounded again.
  * For e4m3, layer l uses activation scale sa[l] and weight scale sw[l]:
  *   y = (sum_i q(x_i / sa) q(W_oi / sw)) * sa * sw + b.
+ * Biases are not rounded (a matrix engine adds them in its FP32 sum).
+ * Pins (tests/test_oracle_pins_quant_mixed.py): hand-computed bf16 and e4m3
+ * examples that separate a rounded bias, an unrounded layer input and scales
+ * applied before the bias; equality with the FP64 forward on operands that
+ * are exact in the narrow format.
  */
 int orc_mlp_forward_q_act(const orc_mlp* m, const double* x, int64_t n, int32_t qmode, const double* sa,
                           const double* sw, int32_t act, double* y) {
@@ -416,6 +421,9 @@ int orc_upsample(int32_t W, int32_t H, int32_t Ws, int32_t Hs, int32_t C, const 
  *           T2 = (1 - a1)(1 - a2).
  * Outputs: rgb [P][3]; optional xf [P][16] network input (5 features + zeros),
  * optional f [P][3] tail colour used.
+ * Pins at s < 1 (tests/test_oracle_pins_quant_mixed.py): identical lists give
+ * the full-resolution result on any grids; hand-computed bilinear weights on a
+ * 6 x 1 frame with pass-2 and pass-3 grids of different widths.
  */
 int orc_learned(int32_t W, int32_t H, const double* lay, const double* tail, int32_t W2, int32_t H2, int32_t W3,
                 int32_t H3, const orc_mlp* m, int32_t mode, const double* bg, double* rgb, double* xf,

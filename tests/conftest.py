@@ -38,7 +38,13 @@ def starnt():
     import os
     lib = os.path.join(ROOT, "paper_2606_16747_amd", "libstarnt.so")
     if not os.path.exists(lib):
-        from paper_2606_16747_amd import build as b
+        # the build script is loaded by its path: importing it through the
+        # package would run __init__, which needs the library
+        import importlib.util
+        spec = importlib.util.spec_from_file_location(
+            "_starnt_build", os.path.join(ROOT, "paper_2606_16747_amd", "build.py"))
+        b = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(b)
         b.build()
     import paper_2606_16747_amd as m
     return m

@@ -4,19 +4,36 @@
 // This is the ground truth the learned path is judged against, the source of
 // training targets, and the baseline it must beat on time.
 //
-// Block layout: 256 threads own a window of 256 consecutive pixels. The
-// window's fragments are staged in LDS in batches of at most kCap with
-// coalesced loads. Each fragment's rank within its pixel is counted in LDS
-// (all lanes of a pixel read the same keys, so reads broadcast), the rank
-// scatters it into sorted order, and one thread per pixel walks its sorted
-// list. The transmittance is a compensated FP32 product (value + error term).
+// Main kernel: one wave owns 64 consecutive pixels and works alone (a block
+// is one wave, so no wave waits on another). It takes its pixels in batches
+// of whole lists holding at most kCapW fragments:
+//   1. the batch's fragments are loaded with one lane per fragment (every
+//      load instruction covers a contiguous run of the CSR arrays); depths go
+//      to LDS, RGBA stays in the loading lane's registers;
+//   2. each lane ranks its fragments within their list by counting the
+//      smaller depths there, eight per LDS round trip (depth bits compare as
+//      unsigned integers, which orders valid depths in [0, 1] as numbers); the
+//      pixel lanes first mark every fragment with its list's range, so no
+//      lane searches for its fragment's list;
+//   3. each fragment writes its index at its sorted slot and reads it back: a
+//      slot claimed twice means equal depths in a list, and only then are the
+//      ranks recounted with primitive ids (read from HBM for that batch);
+//   4. RGBA is scattered to its sorted slot in LDS and one lane per pixel
+//      walks its list front to back.
+// The transmittance is a compensated FP32 product (value + error term).
+// Lists longer than kCapW are left to a block-wide kernel (launched only when
+// the declared maximum list length allows them), which stages up to kCapL
+// fragments of a 256-pixel window in LDS.
 #include "internal.h"
 
 namespace starnt {
 namespace {
 
-constexpr int kPB = 256;     // pixels per window
-constexpr int kCap = 2048;   // fragments per LDS batch
+constexpr int kCapW = 384;   // fragments per wave batch (main kernel)
+constexpr int kSlots = kCapW / 64;
+constexpr int kPB = 256;     // pixels per window (long-list kernel)
+constexpr int kCapL = 2048;  // fragments per LDS batch (long-list kernel)
+constexpr uint32_t kOneBits = 0x3F800000u;  // bits of 1.0f
 
 struct ExactArgs {
   int W, H;
@@ -43,119 +60,287 @@ __device__ __forceinline__ void trans_mul(float& th, float& tl, float a) {
   th = s;
 }
 
-template <bool HALF>
-__global__ __launch_bounds__(256) void exact_kernel(ExactArgs a) {
+// Front-to-back state of one pixel: colour C, transmittance T = th + tl, and
+// the tail alone (sorted positions 3..N) F with its transmittance uh + ul.
+struct Walk {
+  float C0 = 0.f, C1 = 0.f, C2 = 0.f, th = 1.0f, tl = 0.0f;
+  float F0 = 0.f, F1 = 0.f, F2 = 0.f, uh = 1.0f, ul = 0.0f;
+};
+
+template <bool FSTAR>
+__device__ __forceinline__ void walk_step(Walk& w, float4 c, bool tail) {
+  const float al = fminf(fmaxf(c.w, 0.0f), 1.0f);
+  const float t = w.th + w.tl;
+  w.C0 = fmaf(t * al, c.x, w.C0);
+  w.C1 = fmaf(t * al, c.y, w.C1);
+  w.C2 = fmaf(t * al, c.z, w.C2);
+  trans_mul(w.th, w.tl, al);
+  if (FSTAR && tail) {
+    const float u = w.uh + w.ul;
+    w.F0 = fmaf(u * al, c.x, w.F0);
+    w.F1 = fmaf(u * al, c.y, w.F1);
+    w.F2 = fmaf(u * al, c.z, w.F2);
+    trans_mul(w.uh, w.ul, al);
+  }
+}
+
+__device__ __forceinline__ void write_pixel(const ExactArgs& a, int p, const Walk& w) {
+  const float T = w.th + w.tl;
+  a.rgb[3 * (size_t)p + 0] = fmaf(T, a.bg0, w.C0);
+  a.rgb[3 * (size_t)p + 1] = fmaf(T, a.bg1, w.C1);
+  a.rgb[3 * (size_t)p + 2] = fmaf(T, a.bg2, w.C2);
+  if (a.fstar) {
+    a.fstar[3 * (size_t)p + 0] = w.F0;
+    a.fstar[3 * (size_t)p + 1] = w.F1;
+    a.fstar[3 * (size_t)p + 2] = w.F2;
+  }
+}
+
+template <bool HALF, bool FSTAR>
+__global__ __launch_bounds__(64) void exact_wave_kernel(ExactArgs a) {
+  __shared__ uint32_t s_z[kCapW + 8];  // depth bits in staging order (+8: the 8-wide reads' overrun)
+  __shared__ float4 s_c[kCapW];        // list ranges, then prim ids (tie recount), then sorted RGBA
+  __shared__ uint16_t s_idx[kCapW];    // slot claims
+  uint32_t* s_rng = reinterpret_cast<uint32_t*>(s_c);  // [kCapW]: (list start << 16) | list end
+
+  const int l = (int)threadIdx.x;
+  const int P = a.W * a.H;
+  const int p0 = (int)blockIdx.x * 64;
+  const int np = min(64, P - p0);
+  const int p = p0 + l;
+  const bool valid = l < np;
+  const uint32_t b = a.off[valid ? p : P];
+  const uint32_t e = a.off[valid ? p + 1 : P];
+  const uint32_t n = e - b;
+  uint32_t errf = (valid && n > a.max_n) ? STARNT_DERR_COUNT : 0u;
+  const bool lng = valid && n > (uint32_t)kCapW;  // left to the long-list kernel
+  const uint64_t longmask = __builtin_amdgcn_ballot_w64(lng);
+  Walk w;
+
+  int cur = 0;
+  while (cur < np) {
+    if ((longmask >> cur) & 1ull) {
+      ++cur;
+      continue;
+    }
+    // the batch: lanes cur .. end-1, whole lists, at most kCapW fragments,
+    // no long list inside (ends are increasing, so the fitting lanes form a
+    // prefix; lane cur always fits)
+    const uint32_t bcur = (uint32_t)__builtin_amdgcn_readlane((int)b, cur);
+    const bool fit = valid && l >= cur && e - bcur <= (uint32_t)kCapW;
+    const uint64_t stop = ~(__builtin_amdgcn_ballot_w64(fit) >> cur) | (longmask >> cur);
+    const int cnt = min(stop ? (int)__builtin_ctzll(stop) : 64 - cur, np - cur);
+    const int end = cur + cnt;
+    const int m = (int)((uint32_t)__builtin_amdgcn_readlane((int)e, end - 1) - bcur);
+    const bool mine = l >= cur && l < end;
+    const int s0 = (int)(b - bcur);  // this lane's list in the batch (when mine)
+    if (m > 0) {
+      // 1. loads: clamped indices keep every load in the batch, so all of
+      // them are issued before the first use
+      uint32_t zb[kSlots];
+      float4 c[kSlots];
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k) {
+        const int i = min(l + 64 * k, m - 1);
+        zb[k] = __float_as_uint(a.depth[bcur + i]);
+        c[k] = load_rgba<HALF>(a.rgba, bcur + i);
+      }
+      // each pixel lane marks its fragments with its list's range
+      if (mine) {
+        const uint32_t rng = ((uint32_t)s0 << 16) | (uint32_t)(s0 + (int)n);
+        for (int t = 0; t < (int)n; ++t) s_rng[s0 + t] = rng;
+      }
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k) {
+        const int i = l + 64 * k;
+        if (i < m) {
+          s_z[i] = zb[k];
+          errf |= zb[k] > kOneBits ? STARNT_DERR_DEPTH : 0u;  // negatives, -0 and NaN too
+          errf |= (c[k].w >= 0.0f && c[k].w <= 1.0f) ? 0u : STARNT_DERR_ALPHA;
+        }
+      }
+      __syncthreads();
+      // 2. ranks by counting the smaller depths of the list, eight per LDS
+      // round trip (reads past the list's end are masked off)
+      int sb[kSlots], se[kSlots], pos[kSlots];
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k) {
+        const int i = l + 64 * k;
+        sb[k] = se[k] = pos[k] = 0;
+        if (i < m) {
+          const uint32_t rng = s_rng[i];
+          sb[k] = (int)(rng >> 16);
+          se[k] = (int)(rng & 0xFFFFu);
+          int r = 0;
+          for (int j = sb[k]; j < se[k]; j += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = s_z[j + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) r += (j + u < se[k] && v[u] < zb[k]) ? 1 : 0;
+          }
+          pos[k] = sb[k] + r;
+        }
+      }
+      __syncthreads();  // every range is read before the claims and RGBA reuse s_c
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k) {
+        const int i = l + 64 * k;
+        if (i < m) s_idx[pos[k]] = (uint16_t)i;
+      }
+      __syncthreads();
+      // 3. every slot claimed once, or equal depths somewhere in the batch
+      bool clash = false;
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k) {
+        const int i = l + 64 * k;
+        if (i < m) clash |= s_idx[pos[k]] != (uint16_t)i;
+      }
+      if (__builtin_amdgcn_ballot_w64(clash)) {
+        uint32_t* s_pr = reinterpret_cast<uint32_t*>(s_c);
+        uint32_t pr[kSlots];
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) {
+          const int i = l + 64 * k;
+          pr[k] = 0;
+          if (i < m) {
+            pr[k] = a.prim[bcur + i];
+            s_pr[i] = pr[k];
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) {
+          const int i = l + 64 * k;
+          if (i < m) {
+            // the full key (depth, prim); equal keys (outside the input
+            // contract) keep their staging order, so the ranks always form a
+            // permutation of the list's slots
+            int r = 0;
+            for (int j = sb[k]; j < se[k]; ++j) {
+              const uint32_t zj = s_z[j], pj = s_pr[j];
+              r += (zj < zb[k]) | ((zj == zb[k]) & ((pj < pr[k]) | ((pj == pr[k]) & (j < i))));
+            }
+            pos[k] = sb[k] + r;
+          }
+        }
+        __syncthreads();  // prim ids are read before RGBA overwrites them
+      }
+      // 4. RGBA to sorted slots, then one lane per pixel walks its list (the
+      // next colour is read before the current one is blended)
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k) {
+        if (l + 64 * k < m) s_c[pos[k]] = c[k];
+      }
+      __syncthreads();
+      if (mine && n > 0) {
+        float4 cn = s_c[s0];
+        for (int t = 0; t < (int)n; ++t) {
+          const float4 cc = cn;
+          if (t + 1 < (int)n) cn = s_c[s0 + t + 1];
+          walk_step<FSTAR>(w, cc, t >= 2);
+        }
+      }
+      __syncthreads();  // the next batch reuses the LDS arrays
+    }
+    cur = end;
+  }
+  if (valid && !lng) write_pixel(a, p, w);
+  if (errf && a.err) atomicOr(a.err, errf);
+}
+
+// Lists longer than kCapW (up to kCapL): a block owns a window of 256 pixels
+// and returns at once unless one of them is long. The window's fragments are
+// staged in LDS in batches of at most kCapL with coalesced loads, each
+// fragment's rank within its list is counted there on the full key, the rank
+// scatters it into sorted order, and one thread per long pixel walks its list.
+template <bool HALF, bool FSTAR>
+__global__ __launch_bounds__(256) void exact_long_kernel(ExactArgs a) {
   __shared__ uint32_t s_off[kPB + 1];
-  __shared__ float s_z[kCap];
-  __shared__ uint32_t s_pr[kCap];
-  __shared__ float4 s_c[kCap];
-  __shared__ uint16_t s_ord[kCap];
+  __shared__ float s_z[kCapL];
+  __shared__ uint32_t s_pr[kCapL];
+  __shared__ float4 s_c[kCapL];
+  __shared__ uint16_t s_ord[kCapL];
 
   const int P = a.W * a.H;
   const int p0 = blockIdx.x * kPB;
   const int npix = min(kPB, P - p0);
   const int tid = threadIdx.x;
+  const uint32_t n_me = tid < npix ? a.off[p0 + tid + 1] - a.off[p0 + tid] : 0u;
+  const bool lng = n_me > (uint32_t)kCapW;
+  if (!__syncthreads_or(lng)) return;
   for (int i = tid; i <= npix; i += blockDim.x) s_off[i] = a.off[p0 + i];
   __syncthreads();
 
-  uint32_t errf = 0;
-  // per-thread pixel state (thread tid owns pixel p0 + tid)
-  float C0 = 0.f, C1 = 0.f, C2 = 0.f, th = 1.0f, tl = 0.0f;
-  float F0 = 0.f, F1 = 0.f, F2 = 0.f, uh = 1.0f, ul = 0.0f;
-  if (tid < npix) {
-    const uint32_t n = s_off[tid + 1] - s_off[tid];
-    if (n > a.max_n) errf |= STARNT_DERR_COUNT;
-  }
-
+  uint32_t errf = (lng && n_me > a.max_n) ? STARNT_DERR_COUNT : 0u;
+  Walk w;
   int bs = 0;
   while (bs < npix) {
     const uint32_t fs = s_off[bs];
-    // largest be in (bs, npix] with s_off[be] - fs <= kCap
+    // largest be in (bs, npix] with s_off[be] - fs <= kCapL
     int lo = bs + 1, hi = npix;
-    if (s_off[lo] - fs > (uint32_t)kCap) {
-      hi = lo;  // a single list longer than kCap: rejected on the host
+    if (s_off[lo] - fs > (uint32_t)kCapL) {
+      hi = lo;  // a single list longer than kCapL: rejected on the host
     } else {
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (s_off[mid] - fs <= (uint32_t)kCap) lo = mid; else hi = mid - 1;
+        if (s_off[mid] - fs <= (uint32_t)kCapL) lo = mid; else hi = mid - 1;
       }
     }
     const int be = lo;
-    const int cnt = (int)min(s_off[be] - fs, (uint32_t)kCap);
+    const int cnt = (int)min(s_off[be] - fs, (uint32_t)kCapL);
     for (int i = tid; i < cnt; i += blockDim.x) {
       const float z = a.depth[fs + i];
       const float4 c = load_rgba<HALF>(a.rgba, fs + i);
-      errf |= (z >= 0.0f && z <= 1.0f) ? 0u : STARNT_DERR_DEPTH;
-      errf |= (c.w >= 0.0f && c.w <= 1.0f) ? 0u : STARNT_DERR_ALPHA;
       s_z[i] = z;
       s_pr[i] = a.prim[fs + i];
       s_c[i] = c;
     }
     __syncthreads();
-    // rank of each fragment within its pixel
     for (int i = tid; i < cnt; i += blockDim.x) {
-      // pixel q of fragment i: last q in [bs, be) with s_off[q] - fs <= i
+      // list of fragment i: last q in [bs, be) with s_off[q] - fs <= i
       int ql = bs, qh = be - 1;
       while (ql < qh) {
         const int mid = (ql + qh + 1) >> 1;
         if ((int)(s_off[mid] - fs) <= i) ql = mid; else qh = mid - 1;
       }
       const int sb = (int)(s_off[ql] - fs), se = min((int)(s_off[ql + 1] - fs), cnt);
-      const float zi = s_z[i];
-      const uint32_t pi = s_pr[i];
+      if (se - sb <= kCapW) continue;  // short lists belong to the main kernel
+      const uint32_t zi = __float_as_uint(s_z[i]), pi = s_pr[i];
       int r = 0;
-      // ties of the whole key (not allowed by the input contract) fall back to
-      // staging order so the ranks always form a permutation
       for (int j = sb; j < se; ++j) {
-        const float zj = s_z[j];
-        const uint32_t pj = s_pr[j];
+        const uint32_t zj = __float_as_uint(s_z[j]), pj = s_pr[j];
         r += (zj < zi) | ((zj == zi) & ((pj < pi) | ((pj == pi) & (j < i))));
       }
       s_ord[sb + r] = (uint16_t)i;
+      errf |= zi > kOneBits ? STARNT_DERR_DEPTH : 0u;
+      errf |= (s_c[i].w >= 0.0f && s_c[i].w <= 1.0f) ? 0u : STARNT_DERR_ALPHA;
     }
     __syncthreads();
-    if (tid >= bs && tid < be) {
+    if (lng && tid >= bs && tid < be) {
       const int sb = (int)(s_off[tid] - fs), se = min((int)(s_off[tid + 1] - fs), cnt);
-      for (int r = sb; r < se; ++r) {
-        const float4 c = s_c[s_ord[r]];
-        const float al = fminf(fmaxf(c.w, 0.0f), 1.0f);
-        const float t = th + tl;
-        C0 = fmaf(t * al, c.x, C0);
-        C1 = fmaf(t * al, c.y, C1);
-        C2 = fmaf(t * al, c.z, C2);
-        trans_mul(th, tl, al);
-        if (r - sb >= 2) {
-          const float u = uh + ul;
-          F0 = fmaf(u * al, c.x, F0);
-          F1 = fmaf(u * al, c.y, F1);
-          F2 = fmaf(u * al, c.z, F2);
-          trans_mul(uh, ul, al);
-        }
-      }
+      for (int r = sb; r < se; ++r) walk_step<FSTAR>(w, s_c[s_ord[r]], r - sb >= 2);
     }
     __syncthreads();
     bs = be;
   }
-  if (tid < npix) {
-    const int p = p0 + tid;
-    const float T = th + tl;
-    a.rgb[3 * (size_t)p + 0] = fmaf(T, a.bg0, C0);
-    a.rgb[3 * (size_t)p + 1] = fmaf(T, a.bg1, C1);
-    a.rgb[3 * (size_t)p + 2] = fmaf(T, a.bg2, C2);
-    if (a.fstar) {
-      a.fstar[3 * (size_t)p + 0] = F0;
-      a.fstar[3 * (size_t)p + 1] = F1;
-      a.fstar[3 * (size_t)p + 2] = F2;
-    }
-  }
+  if (lng) write_pixel(a, p0 + tid, w);
   if (errf && a.err) atomicOr(a.err, errf);
+}
+
+template <bool HALF, bool FSTAR>
+void launch_exact_t(const ExactArgs& a, bool with_long, hipStream_t s) {
+  const int P = a.W * a.H;
+  hipLaunchKernelGGL((exact_wave_kernel<HALF, FSTAR>), dim3((P + 63) / 64), dim3(64), 0, s, a);
+  if (with_long)
+    hipLaunchKernelGGL((exact_long_kernel<HALF, FSTAR>), dim3((P + kPB - 1) / kPB), dim3(256), 0, s, a);
 }
 
 }  // namespace
 
 int launch_exact(const starnt_frags& f, const float bg[3], float* rgb, float* fstar, uint32_t* err,
                  hipStream_t s) {
-  if (f.max_per_pixel > (uint32_t)kCap)
+  if (f.max_per_pixel > (uint32_t)kCapL)
     return fail(STARNT_EUNSUPPORTED, "exact composite: max_per_pixel above 2048 is not supported");
   ExactArgs a;
   a.W = f.width;
@@ -171,12 +356,16 @@ int launch_exact(const starnt_frags& f, const float bg[3], float* rgb, float* fs
   a.rgb = rgb;
   a.fstar = fstar;
   a.err = err;
-  const int P = f.width * f.height;
-  const dim3 block(256), grid((P + kPB - 1) / kPB);
-  if (f.rgba_dtype == STARNT_F16)
-    hipLaunchKernelGGL(exact_kernel<true>, grid, block, 0, s, a);
-  else
-    hipLaunchKernelGGL(exact_kernel<false>, grid, block, 0, s, a);
+  // the long-list kernel only where the declared maximum allows such lists
+  const bool with_long = f.max_per_pixel > (uint32_t)kCapW;
+  const bool half = f.rgba_dtype == STARNT_F16;
+  if (half) {
+    if (fstar) launch_exact_t<true, true>(a, with_long, s);
+    else launch_exact_t<true, false>(a, with_long, s);
+  } else {
+    if (fstar) launch_exact_t<false, true>(a, with_long, s);
+    else launch_exact_t<false, false>(a, with_long, s);
+  }
   STARNT_LAUNCH_CHECK("starnt_composite (exact) launch");
   return STARNT_OK;
 }

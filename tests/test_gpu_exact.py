@@ -1,0 +1,111 @@
+"""Exact A-buffer path against the FP64 oracle at the shapes its kernels
+split on: lists at and around the per-wave batch capacity (384 fragments),
+runs of long lists next to short ones, equal depths inside short and long
+lists, waves whose pixels are all empty, and the call without the tail
+output. Bar: <= 1e-4 per channel against FP64 (eq (1), the A-buffer of
+Sec. 4); the colour is bitwise the same with and without the tail output
+and under permutation of every list."""
+import numpy as np
+import pytest
+import torch
+
+from csr_util import make_csr
+from gpu_util import run_exact, sync, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def _lists(rng, lengths, ties_every=0):
+    lists = []
+    for n in lengths:
+        n = int(n)
+        if ties_every and n > 1:
+            # depths drawn from a small set: many equal depths in the list
+            z = rng.integers(0, max(2, n // ties_every), size=n).astype(np.float32) / max(2, n // ties_every)
+        else:
+            z = rng.permutation(n).astype(np.float32) / max(n, 1)
+        prims = rng.permutation(4 * n + 4)[:n]
+        lists.append([(float(z[k]), int(prims[k]), *rng.random(3), float(rng.uniform(0.01, 0.3)))
+                      for k in range(n)])
+    return lists
+
+
+def _check(starnt, oracle_mod, lists, W, H, max_n, bg=(0.3, 0.6, 0.9)):
+    csr = make_csr(lists, W, H)
+    df = starnt.DeviceFrags(*csr, W, H, max_n)
+    rgb, fstar = run_exact(starnt, df, bg=bg)
+    o = oracle_mod.frame(*csr, W, H, bg=bg)
+    assert np.abs(rgb - o["rgb"]).max() <= TOL
+    assert np.abs(fstar - o["fstar"]).max() <= TOL
+    # the colour alone (no tail output) is the same colour, bit for bit
+    P = W * H
+    rgb_only = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+    starnt.starnt_composite(df, None, None, None, bg, starnt.MODE_EXACT, rgb_only, None)
+    sync()
+    assert np.array_equal(to_np(rgb_only), rgb)
+    return csr, rgb, fstar
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_exact_lists_around_the_batch_capacity(starnt, gpu, oracle_mod, seed):
+    rng = np.random.default_rng(seed)
+    W, H = 64, 3
+    lengths = rng.choice([0, 1, 2, 5, 17, 63, 200], size=W * H)
+    # a wave of 64 pixels: lists at, below and above the batch capacity, a
+    # run of long lists, a long list first and last in the wave
+    lengths[0] = 385
+    lengths[3:6] = (383, 384, 385)
+    lengths[10:13] = (600, 700, 385)
+    lengths[63] = 1000
+    lengths[64 + 7] = 384
+    lengths[64 + 8] = 384
+    lengths[128:192] = 0  # a wave of empty pixels
+    _check(starnt, oracle_mod, _lists(rng, lengths), W, H, 1024)
+
+
+def test_exact_ties_in_short_and_long_lists(starnt, gpu, oracle_mod):
+    rng = np.random.default_rng(5)
+    W, H = 40, 4
+    lengths = rng.choice([0, 3, 9, 30, 90], size=W * H)
+    lengths[7] = 500
+    lengths[50] = 384
+    lists = _lists(rng, lengths, ties_every=4)
+    csr, rgb, fstar = _check(starnt, oracle_mod, lists, W, H, 512)
+    # permuting every list leaves both outputs bitwise unchanged
+    perm = []
+    for l in lists:
+        idx = rng.permutation(len(l))
+        perm.append([l[k] for k in idx])
+    csr2 = make_csr(perm, W, H)
+    df2 = starnt.DeviceFrags(*csr2, W, H, 512)
+    rgb2, fstar2 = run_exact(starnt, df2, bg=(0.3, 0.6, 0.9))
+    assert np.array_equal(rgb, rgb2) and np.array_equal(fstar, fstar2)
+
+
+def test_exact_declared_maximum_below_the_capacity(starnt, gpu, oracle_mod):
+    """With every list at most 384 long only the per-wave kernel runs; a frame
+    wider than one wave with ragged tails (P not a multiple of 64)."""
+    rng = np.random.default_rng(11)
+    W, H = 97, 5
+    lengths = rng.choice([0, 1, 4, 8, 32, 120, 384], size=W * H)
+    _check(starnt, oracle_mod, _lists(rng, lengths), W, H, 384)
+
+
+def test_exact_flags_lists_longer_than_declared(starnt, gpu):
+    """A list longer than the declared maximum sets the count flag (the call
+    itself is not an error; the flag is read after the stream)."""
+    rng = np.random.default_rng(2)
+    W, H = 8, 1
+    lengths = [3, 400, 2, 0, 5, 6, 7, 8]
+    lists = _lists(rng, lengths)
+    csr = make_csr(lists, W, H)
+    df = starnt.DeviceFrags(*csr, W, H, 64)
+    fb = starnt.FeatBuffers(W, H)
+    rgb = torch.empty(W * H, 3, dtype=torch.float32, device="cuda")
+    fb.err.zero_()
+    starnt.starnt_composite(df, fb, None, None, (1, 1, 1), starnt.MODE_EXACT, rgb, None)
+    sync()
+    e = int(to_np(fb.err)[0])
+    assert e & starnt.DERR_COUNT

@@ -62,9 +62,14 @@ def _load():
             lib.orc_mlp_forward_act.restype = ctypes.c_int
             lib.orc_mlp_forward_act.argtypes = [ctypes.POINTER(_Mlp), _P, ctypes.c_int64, ctypes.c_int32, _P]
             lib.orc_mlp_forward_q_act.restype = ctypes.c_int
+            lib.orc_mlp_forward_q_amb.restype = ctypes.c_int
+            lib.orc_mlp_forward_q_amb.argtypes = [ctypes.POINTER(_Mlp), _P, ctypes.c_int64, ctypes.c_int32, _P, _P,
+                                                  ctypes.c_int32, ctypes.c_double, ctypes.c_double, _P, _P]
             lib.orc_mlp_forward_q_act.argtypes = [ctypes.POINTER(_Mlp), _P, ctypes.c_int64, ctypes.c_int32, _P, _P,
                                                   ctypes.c_int32, _P]
             lib.orc_mlp_loss_grad_act.restype = ctypes.c_double
+            lib.orc_mlp_loss_grad_wt.restype = ctypes.c_double
+            lib.orc_mlp_loss_grad_wt.argtypes = [_P, _P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32, _P]
             lib.orc_mlp_loss_grad_act.argtypes = [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32, _P]
             lib.orc_mlp_forward_q.restype = ctypes.c_int
             lib.orc_mlp_forward_q.argtypes = [ctypes.POINTER(_Mlp), _P, ctypes.c_int64, ctypes.c_int32, _P, _P, _P]
@@ -213,6 +218,22 @@ class Mlp:
             raise RuntimeError("orc_mlp_forward_q failed")
         return y
 
+    def forward_q_amb(self, x, qmode, sa=None, sw=None, tol_in=0.0, tol_h=0.0):
+        """forward_q plus, per sample, which rounded operands are ambiguous:
+        bit 0 when an input moved by tol_in |v| rounds differently, bit 1 when
+        a hidden activation moved by tol_h times the sum of the absolute terms
+        (and bias) that produce it does."""
+        x = _c(x, np.float64)
+        n = x.shape[0]
+        y = np.empty((n, self.dims[3]), np.float64)
+        amb = np.zeros(n, np.uint8)
+        sa_ = _c(sa if sa is not None else np.ones(3), np.float64)
+        sw_ = _c(sw if sw is not None else np.ones(3), np.float64)
+        if _load().orc_mlp_forward_q_amb(ctypes.byref(self._s), _ptr(x), n, int(qmode), _ptr(sa_), _ptr(sw_),
+                                         self.act, float(tol_in), float(tol_h), _ptr(y), _ptr(amb)) != 0:
+            raise RuntimeError("orc_mlp_forward_q_amb failed")
+        return y, amb
+
     def params(self):
         """Flat FP64 parameter vector: W1, b1, W2, b2, W3, b3."""
         return np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in zip(self.Ws, self.bs)]).astype(np.float64)
@@ -352,15 +373,18 @@ def reproject_full(d1_r, vp_r, vp_t, width, height):
 # ---------------------------------------------------------------------------
 # training
 
-def loss_grad(dims, params, x, y, act=0):
+def loss_grad(dims, params, x, y, act=0, wt=None):
     """MSE loss and its gradient for the flat parameter vector (FP64); act
-    selects the output activation (0 ReLU, 1 sigmoid)."""
+    selects the output activation (0 ReLU, 1 sigmoid); wt the optional
+    per-sample loss weights."""
     d = np.asarray(dims, np.int32)
     w = _c(params, np.float64)
     x = _c(x, np.float64)
     y = _c(y, np.float64)
+    wt_ = _c(wt, np.float64) if wt is not None else None
     g = np.empty_like(w)
-    loss = _load().orc_mlp_loss_grad_act(_ptr(d), _ptr(w), _ptr(x), _ptr(y), x.shape[0], int(act), _ptr(g))
+    loss = _load().orc_mlp_loss_grad_wt(_ptr(d), _ptr(w), _ptr(x), _ptr(y), _ptr(wt_), x.shape[0], int(act),
+                                        _ptr(g))
     return loss, g
 
 

@@ -313,39 +313,86 @@ double orc_round_e4m3(double v) { return round_e4m3(v); }
  * applied before the bias; equality with the FP64 forward on operands that
  * are exact in the narrow format.
  */
-int orc_mlp_forward_q_act(const orc_mlp* m, const double* x, int64_t n, int32_t qmode, const double* sa,
-                          const double* sw, int32_t act, double* y) {
+/* Narrow operand of layer l: bf16 (qmode 1) or e4m3 of v / scale (qmode 2). */
+static double narrow(double v, int32_t qmode, double scale) {
+  return qmode == 1 ? round_bf16(v) : round_e4m3(v / scale);
+}
+
+/* Forward with narrow operands. Optional amb[k]: bit 0 when an input of
+ * sample k lies so close to a rounding boundary of its narrow type that
+ * moving it by d = tol_in |v| changes its rounding by more than 4 d (a step of
+ * the type, not a rounding of the move itself); bit 1 the same for a hidden
+ * activation moved by tol_h times the sum of the absolute terms (and the
+ * bias) that produce it. A computation in another precision that stays
+ * within those distances rounds every operand of an unflagged sample to the
+ * same value as this one, or to one within 4 d of it. */
+int orc_mlp_forward_q_amb(const orc_mlp* m, const double* x, int64_t n, int32_t qmode, const double* sa,
+                          const double* sw, int32_t act, double tol_in, double tol_h, double* y, uint8_t* amb) {
   if (m->h1 > 1024 || m->h2 > 1024 || m->out > 64 || m->in > 64) return -1;
   const int dims[4] = {m->in, m->h1, m->h2, m->out};
   const float* Ws[3] = {m->W1, m->W2, m->W3};
   const float* bs[3] = {m->b1, m->b2, m->b3};
   for (int64_t k = 0; k < n; ++k) {
-    double a[1024], o[1024];
-    for (int i = 0; i < m->in; ++i) a[i] = x[(size_t)k * m->in + i];
+    /* a: this layer's inputs; mag: the size each input is known to (its own
+       size for the network input, the sum of absolute terms for an activation) */
+    double a[1024], o[1024], mag[1024], omag[1024];
+    uint8_t flag = 0;
+    for (int i = 0; i < m->in; ++i) {
+      a[i] = x[(size_t)k * m->in + i];
+      mag[i] = fabs(a[i]);
+    }
     for (int l = 0; l < 3; ++l) {
       int nin = dims[l], nout = dims[l + 1];
+      if (amb && qmode != 0) {
+        const double tol = l == 0 ? tol_in : tol_h;
+        const double scale = qmode == 2 ? sa[l] : 1.0;
+        for (int i = 0; i < nin; ++i) {
+          /* two roundings farther apart than the move itself: a step of the
+             narrow type (operands of the size of the move, such as an
+             activation at the ReLU's kink, round within it) */
+          const double d = tol * mag[i];
+          const double lo = narrow(a[i] - d, qmode, scale) * scale, hi = narrow(a[i] + d, qmode, scale) * scale;
+          if (hi - lo > 4.0 * d) flag |= l == 0 ? 1 : 2;
+        }
+      }
       for (int j = 0; j < nout; ++j) {
-        double s = 0.0;
+        double s = 0.0, sabs = 0.0;
         for (int i = 0; i < nin; ++i) {
           double w = Ws[l][(size_t)j * nin + i];
           double av = a[i];
+          double t;
           if (qmode == 1) {
-            s += round_bf16(av) * round_bf16(w);
+            t = round_bf16(av) * round_bf16(w);
           } else if (qmode == 2) {
-            s += round_e4m3(av / sa[l]) * round_e4m3(w / sw[l]);
+            t = round_e4m3(av / sa[l]) * round_e4m3(w / sw[l]);
           } else {
-            s += av * w;
+            t = av * w;
           }
+          s += t;
+          sabs += fabs(t);
         }
-        if (qmode == 2) s *= sa[l] * sw[l];
+        if (qmode == 2) {
+          s *= sa[l] * sw[l];
+          sabs *= sa[l] * sw[l];
+        }
         s += bs[l][j];
         o[j] = l == 2 ? out_act(s, act) : (s > 0.0 ? s : 0.0);
+        omag[j] = sabs + fabs((double)bs[l][j]);
       }
-      for (int j = 0; j < nout; ++j) a[j] = o[j];
+      for (int j = 0; j < nout; ++j) {
+        a[j] = o[j];
+        mag[j] = omag[j];
+      }
     }
     for (int j = 0; j < m->out; ++j) y[(size_t)k * m->out + j] = a[j];
+    if (amb) amb[k] = flag;
   }
   return 0;
+}
+
+int orc_mlp_forward_q_act(const orc_mlp* m, const double* x, int64_t n, int32_t qmode, const double* sa,
+                          const double* sw, int32_t act, double* y) {
+  return orc_mlp_forward_q_amb(m, x, n, qmode, sa, sw, act, 0.0, 0.0, y, NULL);
 }
 
 int orc_mlp_forward_q(const orc_mlp* m, const double* x, int64_t n, int32_t qmode, const double* sa,
@@ -455,7 +502,16 @@ int orc_learned(int32_t W, int32_t H, const double* lay, const double* tail, int
   orc_upsample(W, H, W2, H2, 4, g2, u2);
   orc_upsample(W, H, W3, H3, 5, g3, u3);
   int in = m ? m->in : 16;
+  /* pixels are independent: the loop runs in parallel, each pixel's
+     arithmetic unchanged */
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+  {
   double* xin = (double*)calloc((size_t)(in > 5 ? in : 5), sizeof(double));
+#ifdef _OPENMP
+#pragma omp for schedule(static, 4096)
+#endif
   for (int64_t p = 0; p < P; ++p) {
     const double* L = lay + 10 * p;
     double N = L[0];
@@ -488,6 +544,7 @@ int orc_learned(int32_t W, int32_t H, const double* lay, const double* tail, int
       rgb[3 * p + c] = a1 * c1[c] + (1.0 - a1) * pc2[c] + T2 * f[c] + T2 * tt * bg[c];
   }
   free(xin);
+  }
   free(g2); free(g3); free(u2); free(u3);
   return 0;
 }
@@ -863,11 +920,13 @@ int orc_reproject_full(int32_t W, int32_t H, const float* d1_r, const double* vp
 
 /*
  * Parameter vector layout: W1[h1][in], b1[h1], W2[h2][h1], b2[h2], W3[out][h2], b3[out].
- * Loss = mean over B*out of (f(x) - y)^2. grad receives dLoss/dparams.
- * ReLU derivative at 0 is taken as 0.
+ * Loss = mean over B*out of wt_k (f(x_k) - y_k)^2, with per-sample weights wt
+ * (NULL: all 1, the plain MSE of Sec. 3.3). With wt_k = T2_k^2 this is the
+ * mean squared error of the composite, since eq (3) scales f by T2.
+ * grad receives dLoss/dparams. ReLU derivative at 0 is taken as 0.
  */
-double orc_mlp_loss_grad_act(const int32_t* dims, const double* w, const double* x, const double* y, int64_t B,
-                             int32_t act, double* grad) {
+double orc_mlp_loss_grad_wt(const int32_t* dims, const double* w, const double* x, const double* y,
+                            const double* wt, int64_t B, int32_t act, double* grad) {
   const int in = dims[0], h1 = dims[1], h2 = dims[2], out = dims[3];
   const double* W1 = w;
   const double* b1 = W1 + (size_t)h1 * in;
@@ -909,12 +968,13 @@ double orc_mlp_loss_grad_act(const int32_t* dims, const double* w, const double*
       for (int i = 0; i < h2; ++i) s += W3[(size_t)o * h2 + i] * (z2[i] > 0 ? z2[i] : 0.0);
       z3[o] = s;
     }
+    const double wk = wt ? wt[k] : 1.0;
     for (int o = 0; o < out; ++o) {
       double f = out_act(z3[o], act);
       double e = f - yk[o];
-      loss += e * e * scale;
+      loss += wk * e * e * scale;
       double df = act ? f * (1.0 - f) : (z3[o] > 0 ? 1.0 : 0.0);
-      d3[o] = 2.0 * e * scale * df;
+      d3[o] = 2.0 * wk * e * scale * df;
     }
     if (!grad) continue;
     for (int i = 0; i < h2; ++i) {
@@ -942,6 +1002,11 @@ double orc_mlp_loss_grad_act(const int32_t* dims, const double* w, const double*
   }
   free(z1);
   return loss;
+}
+
+double orc_mlp_loss_grad_act(const int32_t* dims, const double* w, const double* x, const double* y, int64_t B,
+                             int32_t act, double* grad) {
+  return orc_mlp_loss_grad_wt(dims, w, x, y, NULL, B, act, grad);
 }
 
 double orc_mlp_loss_grad(const int32_t* dims, const double* w, const double* x, const double* y, int64_t B,

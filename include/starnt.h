@@ -68,7 +68,13 @@ extern "C" {
 
 /* device error word flags (OR-ed by kernels) */
 #define STARNT_DERR_DEPTH 1u  /* a depth outside [0,1] or NaN                  */
-#define STARNT_DERR_ALPHA 2u  /* an alpha outside [0,1] or NaN                 */
+#define STARNT_DERR_ALPHA 2u  /* an alpha outside [0,1] or NaN, among the
+                                 fragments whose colour the call reads: every
+                                 fragment in the exact composite; in
+                                 starnt_features the two selected layers of
+                                 every pixel and every fragment of a pass-3
+                                 sample (the colour of other fragments is never
+                                 loaded, which is what a reduced pass 3 saves) */
 #define STARNT_DERR_COUNT 4u  /* a list longer than max_per_pixel              */
 #define STARNT_DERR_LIST 8u   /* starnt_patch: a listed pixel outside the frame
                                  or a list longer than its capacity           */
@@ -118,9 +124,11 @@ typedef struct {
   float* layer2;      /* [P][4] capacity; (a2 c2, a2) at pass-2 grid samples,
                          row-major over the w2 x h2 grid                        */
   float* tail;        /* [P][8] capacity; per pass-3 grid sample:
-                         x = (N, t_tail, Ct_r, Ct_g, Ct_b), then A, 0, 0, where
+                         x = (N, t_tail, Ct_r, Ct_g, Ct_b), then A, T2, 0, where
                          over sorted positions 3..N: A = sum a,
-                         t_tail = prod (1 - a), Ct = sum a c / A (0 if A = 0)   */
+                         t_tail = prod (1 - a), Ct = sum a c / A (0 if A = 0),
+                         and T2 = (1 - a1)(1 - a2) of the sample's two
+                         selected layers (1 where it has none)                 */
   uint32_t* sel;      /* optional [P][2]: global index of layers 1 and 2
                          (0xFFFFFFFF when absent); NULL to skip                 */
   uint32_t* err;      /* device error word (flags OR-ed in; caller zeroes it)   */
@@ -178,6 +186,10 @@ typedef struct {
   float* grad;              /* [n] written: gradient of this step's loss        */
   int32_t out_act;          /* output activation: 0 ReLU (STAR-NT), 1 logistic
                                sigmoid (DFAOIT); hidden layers are ReLU         */
+  const float* weight;      /* [batch] optional per-sample loss weight w_k
+                               (NULL: 1): loss = sum_k w_k |f(x_k) - y_k|^2 /
+                               (3 batch); w = T2^2 gives the squared error of
+                               eq (3)'s tail term T2 f                          */
 } starnt_train;
 
 typedef struct {

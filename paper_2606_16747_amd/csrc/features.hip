@@ -20,8 +20,9 @@
 // list together, so every load instruction of a quad covers a contiguous run
 // of the CSR arrays (16 B of depth, 64 B of RGBA) that is consumed at once;
 // a wave streams 16 neighbouring pixels, whose lists are adjacent in memory.
-// Pixels outside the pass-3 grid skip the RGBA loads inside the same loop
-// (their terms are zero), so a wave never runs two loop variants.
+// A row off the pass-3 grid streams depths only (no colour loads, no sums);
+// on a row of the grid, pixels off it skip their RGBA loads inside the same
+// loop (their terms are zero), so a wave never runs two loop variants.
 // No LDS and no barriers: the per-lane partial state (top-2 keys, fixed-point
 // sums) is merged across the quad with DPP quad permutations; after the
 // merge each lane of the quad finishes one colour channel.
@@ -173,6 +174,24 @@ __device__ __forceinline__ void add_terms(Part& p, uint64_t& lg, const Terms& q,
   }
 }
 
+// Depth-only stream for rows off the pass-3 grid: the top-2 keys and the
+// depth check, with no colour loads and no sums.
+__device__ __forceinline__ void stream_depth(const FeatArgs& a, uint32_t b, uint32_t e, int q, Top2& t,
+                                             uint32_t& zmax) {
+  uint32_t k = b + q;
+  for (; k + kG < e; k += 2 * kG) {
+    const float z0 = a.depth[k], z1 = a.depth[k + kG];
+    zmax = max(zmax, max(__float_as_uint(z0), __float_as_uint(z1)));
+    top2_push(t, z0, k, a.prim);
+    top2_push(t, z1, k + kG, a.prim);
+  }
+  if (k < e) {
+    const float z = a.depth[k];
+    zmax = max(zmax, __float_as_uint(z));
+    top2_push(t, z, k, a.prim);
+  }
+}
+
 // One lane's share of a list: fragments b+q, b+q+4, ..., two per step so both
 // loads are in flight together. RGBA is loaded only when `rgba` (pass-3
 // pixels); otherwise the colour is zero and so are its terms.
@@ -224,17 +243,19 @@ __device__ __forceinline__ float tail_transmittance(uint64_t lg) {
   return hi >= 16u ? 0.0f : __builtin_amdgcn_exp2f(-e);
 }
 
-template <bool HALF, bool WIDE, bool AVG>
+// SUMS = false: the pixel's row is off the pass-3 grid (depth-only stream).
+template <bool HALF, bool WIDE, bool AVG, bool SUMS>
 __device__ __forceinline__ void pixel(const FeatArgs& a, const Grids& g, int p, int q, uint32_t b, uint32_t e,
                                       int i2, int j2, int i3, int j3) {
   using V = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
   const bool pass2 = i2 >= 0 && j2 >= 0;
-  const bool pass3 = i3 >= 0 && j3 >= 0;
+  const bool pass3 = SUMS && i3 >= 0 && j3 >= 0;
   const uint32_t n = e - b;
   Top2 t;
   Sums<V> s;
   uint32_t zmax = 0, amax = 0;
-  stream<HALF, WIDE, AVG>(a, b, e, q, pass3, t, s, zmax, amax);
+  if constexpr (SUMS) stream<HALF, WIDE, AVG>(a, b, e, q, pass3, t, s, zmax, amax);
+  else stream_depth(a, b, e, q, t, zmax);
 
   // merge the quad's top-2 keys: two butterfly rounds
   {
@@ -255,6 +276,7 @@ __device__ __forceinline__ void pixel(const FeatArgs& a, const Grids& g, int p, 
   float4 c1 = make_float4(0.f, 0.f, 0.f, 0.f), c2 = c1;
   if (t.k1 != kNone) c1 = load_rgba<HALF>(a.rgba, t.k1);
   if (t.k2 != kNone && want2) c2 = load_rgba<HALF>(a.rgba, t.k2);
+  amax = max(amax, max(__float_as_uint(c1.w), __float_as_uint(c2.w)));
 
   // layer outputs (premultiplied): lane 0 -> layer 1, lane 1 -> layer 2
   {
@@ -272,7 +294,7 @@ __device__ __forceinline__ void pixel(const FeatArgs& a, const Grids& g, int p, 
   }
   if (a.sel && q == 0) a.sel[p] = make_uint2(t.k1, t.k2);
 
-  if (pass3) {
+  if (SUMS && pass3) {
     // reduce-scatter of the channel sums (alpha, r, g, b): lane q ends with
     // the quad total of channel q; the log-transmittance sum is all-reduced
     const bool hi = q & 2, odd = q & 1;
@@ -296,10 +318,11 @@ __device__ __forceinline__ void pixel(const FeatArgs& a, const Grids& g, int p, 
     const float inv = (tail && A > 0.0f) ? __builtin_amdgcn_rcpf(A) : 0.0f;
     const float o = q == 0 ? (tail ? A * (1.0f / kQ24) : 0.0f) : tv * inv;
     const float tt = tail ? tail_transmittance(lg) : 1.0f;
-    // record [N, t_tail, Cr, Cg | Cb, A, 0, 0] as one float2 per lane
+    // record [N, t_tail, Cr, Cg | Cb, A, T2, 0] as one float2 per lane, with
+    // T2 = (1 - a1)(1 - a2) the transmittance behind the two selected layers
     const float nx = qperm<kRot1>(o), oa = qperm<kBc0>(o);
     float2 rec;
-    rec.x = q == 0 ? (float)n : (q == 1 ? o : (q == 2 ? nx : 0.0f));
+    rec.x = q == 0 ? (float)n : (q == 1 ? o : (q == 2 ? nx : (1.0f - a1) * (1.0f - a2)));
     rec.y = q == 0 ? tt : (q == 1 ? nx : (q == 2 ? oa : 0.0f));
     reinterpret_cast<float2*>(a.tail + 2 * (size_t)(j3 * g.w3 + i3))[q] = rec;
     if (AVG) {
@@ -327,7 +350,8 @@ __device__ __forceinline__ void pixel(const FeatArgs& a, const Grids& g, int p, 
 }
 
 // A block covers 64 pixels of one row (x from the thread, y = blockIdx.y), so
-// no lane divides to find its pixel and y-dependent values are wave-uniform.
+// no lane divides to find its pixel and y-dependent values are
+// block-uniform: a row off the pass-3 grid streams depths only.
 template <bool HALF, bool AVG>
 __global__ __launch_bounds__(256) void features_kernel(FeatArgs a) {
   const int q = threadIdx.x & (kG - 1);
@@ -337,13 +361,18 @@ __global__ __launch_bounds__(256) void features_kernel(FeatArgs a) {
   const int p = y * a.W + x;
   const Grids g = load_grids(a.sched, a.W, a.H);
   const int i2 = grid_index_of(x, a.W, g.w2), j2 = grid_index_of(y, a.H, g.h2);
-  const int i3 = grid_index_of(x, a.W, g.w3), j3 = grid_index_of(y, a.H, g.h3);
+  const int j3 = grid_index_of(y, a.H, g.h3);
   const uint32_t b = a.off[p], e = a.off[p + 1];
+  if (j3 < 0) {
+    pixel<HALF, false, AVG, false>(a, g, p, q, b, e, i2, j2, -1, j3);
+    return;
+  }
+  const int i3 = grid_index_of(x, a.W, g.w3);
   // the 64-bit variant only where the wave holds a list longer than kNarrow
   if (__builtin_amdgcn_ballot_w64(e - b > kNarrow) != 0)
-    pixel<HALF, true, AVG>(a, g, p, q, b, e, i2, j2, i3, j3);
+    pixel<HALF, true, AVG, true>(a, g, p, q, b, e, i2, j2, i3, j3);
   else
-    pixel<HALF, false, AVG>(a, g, p, q, b, e, i2, j2, i3, j3);
+    pixel<HALF, false, AVG, true>(a, g, p, q, b, e, i2, j2, i3, j3);
 }
 
 // Features of a list of pixels (re-rendering of untrusted interpolated
@@ -372,9 +401,9 @@ __global__ __launch_bounds__(256) void features_list_kernel(FeatArgs a) {
     }
     const uint32_t b = a.off[p], e = a.off[p + 1];
     if (__builtin_amdgcn_ballot_w64(e - b > kNarrow) != 0)
-      pixel<HALF, true, false>(a, g, (int)i, q, b, e, (int)i, 0, (int)i, 0);
+      pixel<HALF, true, false, true>(a, g, (int)i, q, b, e, (int)i, 0, (int)i, 0);
     else
-      pixel<HALF, false, false>(a, g, (int)i, q, b, e, (int)i, 0, (int)i, 0);
+      pixel<HALF, false, false, true>(a, g, (int)i, q, b, e, (int)i, 0, (int)i, 0);
   }
 }
 

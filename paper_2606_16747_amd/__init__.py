@@ -67,7 +67,7 @@ class QtParams(ctypes.Structure):
 class Train(ctypes.Structure):
     _fields_ = [("in_", ctypes.c_int32), ("h1", ctypes.c_int32), ("h2", ctypes.c_int32), ("out", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("params", _P), ("m", _P), ("v", _P), ("grad", _P),
-                ("out_act", ctypes.c_int32)]
+                ("out_act", ctypes.c_int32), ("weight", _P)]
 
 
 class Adam(ctypes.Structure):

@@ -1,5 +1,6 @@
 // Training step of the tail-colour network (Sec. 3.3: MSE loss, Adam), on the
-// GPU with FP32 master weights.
+// GPU with FP32 master weights. The loss may weight each sample's squared
+// error (the composite-space error takes T2^2, since eq (3) scales f by T2).
 //
 // Kernel 1: one block per slice of kSB samples. Forward and backward run with
 //   the slice's activations in LDS; the block writes its partial loss and its
@@ -29,6 +30,7 @@ struct TrainArgs {
   const float* params;
   const float* x;
   const float* y;
+  const float* wt;      // [batch] per-sample loss weights (NULL: 1)
   float* partial;       // [nblocks][nparam]
   float* partial_loss;  // [nblocks]
   int nparam;
@@ -94,9 +96,10 @@ __global__ __launch_bounds__(256) void train_fwd_bwd(TrainArgs a) {
       for (int k = 0; k < H2; ++k) z = fmaf(q<BF>(W3[o * H2 + k]), s_h2[s][k], z);
       const float f = a.out_act ? 1.0f / (1.0f + expf(-z)) : fmaxf(z, 0.0f);
       const float e = f - a.y[(size_t)(s0 + s) * 3 + o];
-      lsum = fmaf(e * e, a.inv_count, lsum);
+      const float wk = a.wt ? a.wt[s0 + s] : 1.0f;
+      lsum = fmaf(wk * e * e, a.inv_count, lsum);
       const float df = a.out_act ? f * (1.0f - f) : (z > 0.0f ? 1.0f : 0.0f);
-      d = 2.0f * e * a.inv_count * df;
+      d = 2.0f * wk * e * a.inv_count * df;
     }
     s_d3[s][o] = q<BF>(d);
   }
@@ -350,6 +353,7 @@ __global__ __launch_bounds__(64 * kMWaves) void train_mfma_kernel(TrainArgs a) {
   float y[3];
 #pragma unroll
   for (int o = 0; o < 3; ++o) y[o] = valid ? a.y[(size_t)smp * 3 + o] : 0.0f;
+  const float wsmp = (valid && a.wt) ? a.wt[smp] : 1.0f;
 #pragma unroll
   for (int c = 0; c < kIn; ++c) row(S::rX + c)[c0 + l] = static_cast<__bf16>(x[c]);
   // B operands of the two groups: half 0 takes inputs 0..7 and half 1
@@ -420,6 +424,7 @@ __global__ __launch_bounds__(64 * kMWaves) void train_mfma_kernel(TrainArgs a) {
 #pragma unroll
     for (int c = 0; c < 2 * T2; ++c) acc3 = mfma_bf16(A3[c], H2c[c], acc3);
     const float yg0 = __shfl(y[0], sl), yg1 = __shfl(y[1], sl), yg2 = __shfl(y[2], sl);
+    const float wg = __shfl(wsmp, sl);
     const bool vg = blockIdx.x * kMSamples + sc < a.batch;
     float d3[3] = {0.0f, 0.0f, 0.0f};
     if (h == 0 && vg) {
@@ -429,9 +434,9 @@ __global__ __launch_bounds__(64 * kMWaves) void train_mfma_kernel(TrainArgs a) {
         const float z = acc3[o] + sB[H1 + H2 + o];
         const float f = a.out_act ? 1.0f / (1.0f + expf(-z)) : fmaxf(z, 0.0f);
         const float e = f - yy[o];
-        lsum = fmaf(e * e, a.inv_count, lsum);
+        lsum = fmaf(wg * e * e, a.inv_count, lsum);
         const float df = a.out_act ? f * (1.0f - f) : (z > 0.0f ? 1.0f : 0.0f);
-        d3[o] = q<true>(2.0f * e * a.inv_count * df);
+        d3[o] = q<true>(2.0f * wg * e * a.inv_count * df);
       }
     }
     if (h == 0) {
@@ -569,6 +574,7 @@ int launch_train(const starnt_train& tr, const float* x, const float* y, int bat
   t.params = tr.params;
   t.x = x;
   t.y = y;
+  t.wt = tr.weight;
   t.partial = static_cast<float*>(ws);
   t.partial_loss = reinterpret_cast<float*>(static_cast<char*>(ws) + align256((size_t)nb * np * 4));
   t.nparam = np;

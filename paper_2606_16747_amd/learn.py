@@ -4,9 +4,20 @@ Pairs (x, f*) come from the library itself: starnt_features gives the five
 features at full resolution and the exact A-buffer path gives the exact tail
 colour f* of every pixel with at least three fragments. For the DFAOIT
 network the input is starnt_dfa_inputs and the target the whole transparent
-colour C_t (the exact composite over a black background). Inputs are
-standardised for training; the affine map is folded into layer 1 afterwards,
-so inference sees raw features. Every gradient step is starnt_train_step.
+colour C_t (the exact composite over a black background). Every gradient step
+is starnt_train_step.
+
+Loss weights: eq (3) adds T2 f to the composite, so an error e in f costs
+T2 e in the image; weighting each sample's squared error by T2^2 trains on
+the composite's own error (pixels whose tail is hidden behind two nearly
+opaque layers count for little). The features pass writes each sample's T2
+into its tail record.
+
+Input scaling: each input is multiplied by a power of two for training (the
+count N spans hundreds, the other features [0, 1]); the scale is folded into
+layer 1 afterwards, so inference sees raw features. A power-of-two scale is
+exact under bf16 and e4m3 rounding, so the narrow-operand products at
+inference are bit for bit those of training.
 """
 from __future__ import annotations
 
@@ -18,8 +29,9 @@ from . import (BF16, NET_DFAOIT, WS_TRAIN, Adam, DeviceFrags, FeatBuffers, Train
 from .frames import exact_frame
 
 
-def pairs_from(frags: DeviceFrags, bg=(1.0, 1.0, 1.0)):
-    """(x [M, 16], f* [M, 3]) on the host for the pixels with N >= 3."""
+def pairs_from(frags: DeviceFrags, bg=(1.0, 1.0, 1.0), with_t2=False):
+    """(x [M, 16], f* [M, 3]) on the host for the pixels with N >= 3, and
+    their T2 [M] (from the tail records) when with_t2."""
     fb = FeatBuffers(frags.width, frags.height)
     starnt_features(frags, None, fb)
     P = frags.width * frags.height
@@ -29,8 +41,11 @@ def pairs_from(frags: DeviceFrags, bg=(1.0, 1.0, 1.0)):
     torch.cuda.synchronize()
     n = fb.count.cpu().numpy()
     keep = n >= 3
+    rec = fb.tail.cpu().numpy()[keep]
     x = np.zeros((int(keep.sum()), 16), np.float32)
-    x[:, :5] = fb.tail.cpu().numpy()[keep, :5]
+    x[:, :5] = rec[:, :5]
+    if with_t2:
+        return x, fstar.cpu().numpy()[keep], rec[:, 6].copy()
     return x, fstar.cpu().numpy()[keep]
 
 
@@ -49,35 +64,38 @@ def dfa_pairs_from(frags: DeviceFrags):
     return x.cpu().numpy()[keep], ct.cpu().numpy()[keep]
 
 
-class Standardiser:
+class Pow2Scaler:
+    """Per-input power-of-two scales 2^-k with 2^k the input's largest
+    magnitude rounded up to a power of two (1 for inputs in [0, 1])."""
+
     def __init__(self, x, n_in=5):
-        self.mu = np.zeros(16)
-        self.sd = np.ones(16)
-        self.mu[:n_in] = x[:, :n_in].mean(0)
-        self.sd[:n_in] = np.maximum(x[:, :n_in].std(0), 1e-6)
+        self.sc = np.ones(16)
+        amax = np.abs(x[:, :n_in]).max(0)
+        self.sc[:n_in] = np.exp2(-np.ceil(np.log2(np.maximum(amax, 1.0))))
 
     def apply(self, x):
-        return ((x - self.mu) / self.sd).astype(np.float32)
+        return (x * self.sc).astype(np.float32)
 
     def fold(self, W1, b1):
-        """Layer 1 on raw x equal to layer 1 on standardised x."""
-        W = W1 / self.sd[None, :]
-        b = b1 - (W1 * (self.mu / self.sd)[None, :]).sum(1)
-        return W.astype(np.float32), b.astype(np.float32)
+        """Layer 1 on raw x equal to layer 1 on scaled x (exact: the scales
+        are powers of two)."""
+        return (W1 * self.sc[None, :]).astype(np.float32), np.asarray(b1, np.float32)
 
 
 def train(x, y, Ws, bs, steps=3000, batch=65536, lr=2e-3, lr_min=1e-4, dtype=BF16, seed=0, log_every=0,
-          device="cuda", stream=None, variant=0):
+          device="cuda", stream=None, variant=0, weight=None):
     """Train from initial weights (Ws, bs); returns (Ws, bs, losses) with the
-    standardisation folded into layer 1. variant NET_DFAOIT trains the
-    sigmoid-output network on its eleven inputs."""
+    input scaling folded into layer 1. variant NET_DFAOIT trains the
+    sigmoid-output network on its eleven inputs; weight [M] gives per-sample
+    loss weights (None: plain MSE)."""
     dims = (Ws[0].shape[1], Ws[0].shape[0], Ws[1].shape[0], Ws[2].shape[0])
     dfa = variant == NET_DFAOIT
-    st = Standardiser(x, 11 if dfa else 5)
+    st = Pow2Scaler(x, 11 if dfa else 5)
     rng = np.random.default_rng(seed)
     order = rng.permutation(len(x))
     xs = torch.from_numpy(st.apply(x[order])).to(device)
     ys = torch.from_numpy(np.ascontiguousarray(y[order], np.float32)).to(device)
+    wts = None if weight is None else torch.from_numpy(np.ascontiguousarray(weight[order], np.float32)).to(device)
     M = len(x)
     batch = min(batch, M)
     nb = M // batch
@@ -97,6 +115,8 @@ def train(x, y, Ws, bs, steps=3000, batch=65536, lr=2e-3, lr_min=1e-4, dtype=BF1
         ad = Adam(lr_t, 0.9, 0.999, 1e-8, t + 1)
         xb = xs[b * batch:(b + 1) * batch]
         yb = ys[b * batch:(b + 1) * batch]
+        if wts is not None:
+            tr.weight = wts[b * batch:(b + 1) * batch].data_ptr()
         starnt_train_step(tr, xb, yb, batch, ad, loss[t:t + 1], ws, stream)
         if log_every and (t % log_every == 0 or t == steps - 1):
             torch.cuda.synchronize()

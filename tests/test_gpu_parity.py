@@ -426,6 +426,40 @@ def test_train_step_bf16_gradient_direction(starnt, gpu, sg, oracle_mod):
     assert np.linalg.norm(gg - gw) / np.linalg.norm(gw) < 0.05
 
 
+@pytest.mark.parametrize("dtype,dims,batch", [("f32", (16, 32, 32, 3), 1000), ("f32", (16, 64, 64, 3), 4096),
+                                               ("bf16", (16, 64, 64, 3), 8192), ("bf16", (16, 16, 32, 3), 777)])
+def test_train_step_weighted_loss(starnt, gpu, sg, oracle_mod, dtype, dims, batch):
+    """Per-sample loss weights (the T2^2 weighting of the composite error):
+    FP32 gradient and loss against the FP64 oracle's weighted loss within
+    rel-L2 1e-5; BF16 (matrix cores, and the vector kernel at a ragged batch)
+    by cosine > 0.999 and rel-L2 < 0.05 (stated, as for the plain loss)."""
+    x, y, params = _train_setup(sg, oracle_mod, dims, batch, seed=3)
+    wt = (np.random.default_rng(5).random(batch) ** 2).astype(np.float32)
+    wt[::7] = 0.0
+    n = params.size
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    p, m, v, g = dev(params.copy()), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    wd = dev(wt)
+    dt = starnt.F32 if dtype == "f32" else starnt.BF16
+    tr = starnt.Train(16, dims[1], dims[2], 3, dt, p.data_ptr(), m.data_ptr(), v.data_ptr(), g.data_ptr(), 0,
+                      wd.data_ptr())
+    loss = torch.zeros(1, device="cuda")
+    ws = starnt.workspace(starnt.starnt_workspace_size(starnt.WS_TRAIN, batch, dims[1], dims[2]))
+    starnt.starnt_train_step(tr, dev(x), dev(y), batch, starnt.Adam(1e-3, 0.9, 0.999, 1e-8, 1), loss, ws)
+    sync()
+    lw, gw = oracle_mod.loss_grad(dims, params.astype(np.float64), x, y, wt=wt.astype(np.float64))
+    l0, _ = oracle_mod.loss_grad(dims, params.astype(np.float64), x, y)
+    assert abs(lw - l0) > 1e-3 * l0  # the weights change the loss
+    gg = to_np(g).astype(np.float64)
+    rel = np.linalg.norm(gg - gw) / np.linalg.norm(gw)
+    if dtype == "f32":
+        assert rel <= 1e-5, rel
+        assert abs(float(to_np(loss)[0]) - lw) <= 1e-5 * lw + 1e-9
+    else:
+        cos = gg @ gw / (np.linalg.norm(gg) * np.linalg.norm(gw))
+        assert cos > 0.999 and rel < 0.05, (cos, rel)
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
 @pytest.mark.parametrize("s2,s3", [(1.0, 1.0), (0.6, 0.35), (1.0, 0.5), (0.6, 1.0)])
 def test_infer_composite_equals_two_calls(starnt, gpu, sg, dtype, s2, s3):

@@ -305,6 +305,21 @@ int starnt_quadtree(const float* rgb, const uint32_t* count, int32_t width, int3
                     const starnt_qt_params* params, const uint32_t* prev_mask, uint32_t* mask, uint8_t* level,
                     starnt_sched* sched, void* workspace, size_t workspace_bytes, void* stream);
 
+/* starnt_quadtree without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc). Same arguments, outputs and errors as
+ * starnt_quadtree, except that the scratch is a fixed 4 MiB array in device
+ * memory that the library holds per GPU until the process ends (enough for
+ * frames up to 8192 x 8192 at base 64). A frame and base whose scratch
+ * (starnt_workspace_size(STARNT_WS_QUADTREE, W, H, base)) exceeds 4 MiB is
+ * rejected with STARNT_ENOMEM. Allocates nothing; the first call on a device
+ * looks up that device's copy of the array. Every call on a GPU shares its
+ * array (no part of it needs to start at zero): calls that overlap in time
+ * on one GPU, on any streams, race and give undefined results. */
+int starnt_quadtree_noalloc(const float* rgb, const uint32_t* count, int32_t width, int32_t height,
+                            const starnt_qt_params* params, const uint32_t* prev_mask, uint32_t* mask,
+                            uint8_t* level, starnt_sched* sched, void* stream);
+
 /* Interpolated frame (Sec. 3.3): for each pixel p, X = (x_ndc, y_ndc, d1_prev[p],
  * 1) with x_ndc = (2px+1)/W - 1, y_ndc = 1 - (2py+1)/H; h = X + (M - I) X with
  * M = VP_prev VP_cur^-1; source q = (floor((u+1) W / 2), floor((1-v) H / 2)),

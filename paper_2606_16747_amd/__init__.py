@@ -26,6 +26,7 @@ BASE_WBOIT, BASE_OVER_LIST = 0, 1
 WS_QUADTREE, WS_TRAIN, WS_REPROJECT = 1, 2, 3
 DERR_DEPTH, DERR_ALPHA, DERR_COUNT, DERR_LIST = 1, 2, 4, 8
 STATUS = {0: "OK", 1: "EINVAL", 2: "ERANGE", 3: "ENOMEM", 4: "EHIP", 5: "EUNSUPPORTED"}
+EINVAL, ERANGE, ENOMEM, EHIP, EUNSUPPORTED = 1, 2, 3, 4, 5
 
 _P = ctypes.c_void_p
 
@@ -85,7 +86,7 @@ assert ctypes.sizeof(Sched) == 64
 
 EXPORTS = ("starnt_features", "starnt_infer", "starnt_infer_composite", "starnt_composite", "starnt_baseline",
            "starnt_dfa_inputs", "starnt_infer_composite_sel",
-           "starnt_quadtree", "starnt_reproject", "starnt_reproject_check", "starnt_patch", "starnt_interval_init", "starnt_interval_next",
+           "starnt_quadtree", "starnt_quadtree_noalloc", "starnt_reproject", "starnt_reproject_check", "starnt_patch", "starnt_interval_init", "starnt_interval_next",
            "starnt_interval_report",
            "starnt_train_step", "starnt_sched_init", "starnt_wbar", "starnt_pass_scales", "starnt_grid_dim",
            "starnt_workspace_size", "starnt_check", "starnt_last_error", "starnt_version")
@@ -110,6 +111,8 @@ def _load():
     lib.starnt_interval_report.argtypes = [ctypes.POINTER(Interval), ctypes.c_int32, ctypes.c_double]
     lib.starnt_quadtree.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(QtParams), _P, _P, _P,
                                     _P, _P, ctypes.c_size_t, _P]
+    lib.starnt_quadtree_noalloc.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(QtParams), _P,
+                                            _P, _P, _P, _P]
     lib.starnt_reproject.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), _P,
                                      _P, _P]
     lib.starnt_reproject_check.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_float),
@@ -327,6 +330,12 @@ def starnt_quadtree(rgb, count, width, height, params: QtParams, prev_mask, mask
     _check(lib.starnt_quadtree(_ptr(rgb), _ptr(count), int(width), int(height), ctypes.byref(params),
                                _ptr(prev_mask), _ptr(mask), _ptr(level), _ptr(sched), _ptr(workspace),
                                workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def starnt_quadtree_noalloc(rgb, count, width, height, params: QtParams, prev_mask, mask, level, sched,
+                            stream=None):
+    _check(lib.starnt_quadtree_noalloc(_ptr(rgb), _ptr(count), int(width), int(height), ctypes.byref(params),
+                                       _ptr(prev_mask), _ptr(mask), _ptr(level), _ptr(sched), _stream(stream)))
 
 
 def starnt_reproject(rgb_prev, d1_prev, width, height, m_minus_i, rgb_out, src=None, stream=None):

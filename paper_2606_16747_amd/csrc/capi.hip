@@ -175,26 +175,43 @@ int starnt_baseline(const starnt_frags* frags, int32_t method, const float* bg, 
   return launch_baseline(*frags, method, bg, rgb, as_stream(stream));
 }
 
+static int check_quadtree(const float* rgb, const uint32_t* count, int32_t width, int32_t height,
+                          const starnt_qt_params* params, const uint32_t* prev_mask, const uint32_t* mask,
+                          const uint8_t* level, const starnt_sched* sched, const char* who) {
+  const std::string w(who);
+  int rc = check_frame(width, height, who);
+  if (rc) return rc;
+  if (!rgb || !count || !params || !mask || !level || !sched) return fail(STARNT_EINVAL, w + ": NULL argument");
+  if (params->base < 8 || params->base % 8 || params->base > 4096)
+    return fail(STARNT_EINVAL, w + ": base must be a multiple of 8 in [8, 4096]");
+  if (params->k_relax < 0 || params->k_relax > 8) return fail(STARNT_EINVAL, w + ": k_relax must be in [0, 8]");
+  if (!(params->tau_merge <= params->tau_split))
+    return fail(STARNT_EINVAL, w + ": tau_merge must not exceed tau_split");
+  if (prev_mask && prev_mask == mask) return fail(STARNT_EINVAL, w + ": prev_mask aliases mask");
+  return STARNT_OK;
+}
+
 int starnt_quadtree(const float* rgb, const uint32_t* count, int32_t width, int32_t height,
                     const starnt_qt_params* params, const uint32_t* prev_mask, uint32_t* mask, uint8_t* level,
                     starnt_sched* sched, void* workspace, size_t workspace_bytes, void* stream) {
-  int rc = check_frame(width, height, "starnt_quadtree");
+  int rc = check_quadtree(rgb, count, width, height, params, prev_mask, mask, level, sched, "starnt_quadtree");
   if (rc) return rc;
-  if (!rgb || !count || !params || !mask || !level || !sched)
-    return fail(STARNT_EINVAL, "starnt_quadtree: NULL argument");
-  if (params->base < 8 || params->base % 8 || params->base > 4096)
-    return fail(STARNT_EINVAL, "starnt_quadtree: base must be a multiple of 8 in [8, 4096]");
-  if (params->k_relax < 0 || params->k_relax > 8)
-    return fail(STARNT_EINVAL, "starnt_quadtree: k_relax must be in [0, 8]");
-  if (!(params->tau_merge <= params->tau_split))
-    return fail(STARNT_EINVAL, "starnt_quadtree: tau_merge must not exceed tau_split");
-  if (prev_mask && prev_mask == mask) return fail(STARNT_EINVAL, "starnt_quadtree: prev_mask aliases mask");
   const size_t need = quadtree_ws_bytes(width, height, params->base);
   if (!workspace || workspace_bytes < need) return fail(STARNT_ENOMEM, "starnt_quadtree: workspace too small");
   if (reinterpret_cast<uintptr_t>(workspace) % 256)
     return fail(STARNT_EINVAL, "starnt_quadtree: workspace must be 256-byte aligned");
   return launch_quadtree(rgb, count, width, height, *params, prev_mask, mask, level, sched, workspace,
                          as_stream(stream));
+}
+
+int starnt_quadtree_noalloc(const float* rgb, const uint32_t* count, int32_t width, int32_t height,
+                            const starnt_qt_params* params, const uint32_t* prev_mask, uint32_t* mask,
+                            uint8_t* level, starnt_sched* sched, void* stream) {
+  int rc = check_quadtree(rgb, count, width, height, params, prev_mask, mask, level, sched,
+                          "starnt_quadtree_noalloc");
+  if (rc) return rc;
+  return launch_quadtree_noalloc(rgb, count, width, height, *params, prev_mask, mask, level, sched,
+                                 as_stream(stream));
 }
 
 // [a, a + na) and [b, b + nb) share a byte (addresses compared as integers)

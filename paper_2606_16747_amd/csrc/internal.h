@@ -149,6 +149,10 @@ int launch_quadtree(const float* rgb, const uint32_t* count, int W, int H, const
                     const uint32_t* prev_mask, uint32_t* mask, uint8_t* level, starnt_sched* sched, void* ws,
                     hipStream_t s);
 size_t quadtree_ws_bytes(int64_t W, int64_t H, int64_t base);
+int launch_quadtree_noalloc(const float* rgb, const uint32_t* count, int W, int H, const starnt_qt_params& qp,
+                            const uint32_t* prev_mask, uint32_t* mask, uint8_t* level, starnt_sched* sched,
+                            hipStream_t s);
+size_t quadtree_scratch_bytes();
 int launch_reproject(const float* rgb_prev, const float* d1_prev, int W, int H, const float mmi[16],
                      float* rgb_out, int32_t* src, hipStream_t s, float tol = 0.0f, uint32_t* list = nullptr,
                      uint32_t* list_n = nullptr, void* ws = nullptr);

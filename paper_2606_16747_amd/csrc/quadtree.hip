@@ -16,6 +16,8 @@
 //  The last pass writes masks, levels and per-tile occupied-leaf counts; a
 //  one-block kernel sums them and computes wbar, s2, s3 and the next grids on
 //  the device.
+#include <mutex>
+
 #include "internal.h"
 
 namespace starnt {
@@ -428,6 +430,47 @@ int launch_sched_init(starnt_sched* sched, int w2, int h2, int w3, int h3, hipSt
   hipLaunchKernelGGL(sched_init_kernel, dim3(1), dim3(1), 0, s, a);
   STARNT_LAUNCH_CHECK("starnt_sched_init launch");
   return STARNT_OK;
+}
+
+// Scratch of the allocation-free quadtree update: a fixed array in device
+// memory (each GPU the library runs on holds its own copy until the process
+// ends). Host code never passes the array's name to a kernel: in host code it
+// is only a handle, and the device address of the current GPU's copy comes
+// from hipGetSymbolAddress, resolved once per device.
+constexpr size_t kQtScratchBytes = size_t(4) << 20;
+static __device__ __align__(256) uint8_t scratch[kQtScratchBytes];
+
+size_t quadtree_scratch_bytes() { return kQtScratchBytes; }
+
+int launch_quadtree_noalloc(const float* rgb, const uint32_t* count, int W, int H, const starnt_qt_params& qp,
+                            const uint32_t* prev_mask, uint32_t* mask, uint8_t* level, starnt_sched* sched,
+                            hipStream_t s) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  const size_t need = quadtree_ws_bytes(W, H, qp.base);
+  if (need > kQtScratchBytes)
+    return fail(STARNT_ENOMEM, "starnt_quadtree_noalloc: this frame and base need " + std::to_string(need) +
+                                   " bytes of scratch; the allocation-free call holds " +
+                                   std::to_string(kQtScratchBytes) + " (use starnt_quadtree with a workspace)");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_status(e, "starnt_quadtree_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(STARNT_EUNSUPPORTED, "starnt_quadtree_noalloc: device index above 63");
+  void* ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+      // with `dev` current: the address of this GPU's copy of the array
+      e = hipGetSymbolAddress(&addr[dev], HIP_SYMBOL(scratch));
+      if (e != hipSuccess) {
+        addr[dev] = nullptr;
+        return hip_status(e, "starnt_quadtree_noalloc: hipGetSymbolAddress(scratch)");
+      }
+    }
+    ptr = addr[dev];
+  }
+  return launch_quadtree(rgb, count, W, H, qp, prev_mask, mask, level, sched, ptr, s);
 }
 
 }  // namespace starnt

@@ -177,8 +177,12 @@ typedef struct {
 
 /* ---- training (Sec. 3.3: MSE, Adam) -------------------------------------- */
 typedef struct {
-  int32_t in, h1, h2, out;  /* in = 16, out = 3, h1, h2 in {16, 32, 48, 64}    */
-  int32_t dtype;            /* STARNT_F32 (check mode) | STARNT_BF16            */
+  int32_t in, h1, h2, out;  /* in = 16, out = 3; h1, h2 in {16, 32, 64} with
+                               (h1, h2) one of (16,16) (16,32) (32,16) (32,32)
+                               (32,64) (64,32) (64,64); FP8: h1, h2 in {32, 64} */
+  int32_t dtype;            /* STARNT_F32 (check mode) | STARNT_BF16 |
+                               STARNT_FP8 (forward products on E4M3 operands,
+                               backward in bf16 on the same values)           */
   float* params;            /* [n] FP32 masters: W1[h1][in], b1[h1], W2[h2][h1],
                                b2[h2], W3[out][h2], b3[out]                     */
   float* m;                 /* [n] Adam first moment                            */
@@ -190,6 +194,13 @@ typedef struct {
                                (NULL: 1): loss = sum_k w_k |f(x_k) - y_k|^2 /
                                (3 batch); w = T2^2 gives the squared error of
                                eq (3)'s tail term T2 f                          */
+  float fp8_act_scale[3];   /* FP8: scale s_l of layer l's input (the network
+                               input, then the two hidden activations), each a
+                               positive power of two: the operand is the E4M3
+                               value of a / s_l (saturated at 448). Weight
+                               scales are derived from the masters each step:
+                               the smallest power of two s with max|W_l| / s
+                               <= 448. Ignored in the other modes.            */
 } starnt_train;
 
 typedef struct {
@@ -389,6 +400,13 @@ double starnt_wbar(const uint32_t* hist4);
 void starnt_pass_scales(double wbar, double* s2, double* s3);
 /* grid size max(1, min(n, ceil(s n))) */
 int32_t starnt_grid_dim(int32_t n, double s);
+/* The reprojection matrix of an interpolated frame (Sec. 3.3), in the form
+ * starnt_reproject takes: out = M - I with M = vp_prev vp_cur^-1, computed in
+ * FP64 (inverse by Gauss-Jordan elimination with partial pivoting) and
+ * rounded to FP32. vp_prev, vp_cur: host row-major 4x4 view-projection
+ * matrices of the last real frame and of the current frame; out: host
+ * float[16]. Returns STARNT_EINVAL for NULL arguments or a singular vp_cur. */
+int starnt_m_minus_i(const double* vp_prev, const double* vp_cur, float* out);
 
 /* Adaptive interpolation interval (Sec. 3.3, interpolated frames): one real
  * render is followed by interval - 1 interpolated frames, interval <= 4. The

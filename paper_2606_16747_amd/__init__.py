@@ -68,7 +68,7 @@ class QtParams(ctypes.Structure):
 class Train(ctypes.Structure):
     _fields_ = [("in_", ctypes.c_int32), ("h1", ctypes.c_int32), ("h2", ctypes.c_int32), ("out", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("params", _P), ("m", _P), ("v", _P), ("grad", _P),
-                ("out_act", ctypes.c_int32), ("weight", _P)]
+                ("out_act", ctypes.c_int32), ("weight", _P), ("fp8_act_scale", ctypes.c_float * 3)]
 
 
 class Adam(ctypes.Structure):
@@ -89,7 +89,7 @@ EXPORTS = ("starnt_features", "starnt_infer", "starnt_infer_composite", "starnt_
            "starnt_quadtree", "starnt_quadtree_noalloc", "starnt_reproject", "starnt_reproject_check", "starnt_patch", "starnt_interval_init", "starnt_interval_next",
            "starnt_interval_report",
            "starnt_train_step", "starnt_sched_init", "starnt_wbar", "starnt_pass_scales", "starnt_grid_dim",
-           "starnt_workspace_size", "starnt_check", "starnt_last_error", "starnt_version")
+           "starnt_workspace_size", "starnt_check", "starnt_last_error", "starnt_version", "starnt_m_minus_i")
 
 
 def _load():
@@ -130,6 +130,8 @@ def _load():
     lib.starnt_grid_dim.restype = ctypes.c_int32
     lib.starnt_grid_dim.argtypes = [ctypes.c_int32, ctypes.c_double]
     lib.starnt_workspace_size.restype = ctypes.c_size_t
+    lib.starnt_m_minus_i.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_float)]
     lib.starnt_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
     lib.starnt_check.argtypes = [ctypes.c_uint32]
     lib.starnt_last_error.restype = ctypes.c_char_p
@@ -370,6 +372,15 @@ def starnt_train_step(train: Train, x, y, batch, adam: Adam, loss, workspace, st
 
 def starnt_sched_init(sched, width, height, s2, s3, stream=None):
     _check(lib.starnt_sched_init(_ptr(sched), int(width), int(height), float(s2), float(s3), _stream(stream)))
+
+
+def starnt_m_minus_i(vp_prev, vp_cur):
+    """M - I, M = vp_prev vp_cur^-1, as float32[4, 4] (computed by the library)."""
+    a = (ctypes.c_double * 16)(*[float(v) for v in np.asarray(vp_prev, np.float64).ravel()])
+    b = (ctypes.c_double * 16)(*[float(v) for v in np.asarray(vp_cur, np.float64).ravel()])
+    out = (ctypes.c_float * 16)()
+    _check(lib.starnt_m_minus_i(a, b, out))
+    return np.array(out, np.float32).reshape(4, 4)
 
 
 def starnt_wbar(hist4):

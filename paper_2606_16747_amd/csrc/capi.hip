@@ -1,5 +1,6 @@
 // C ABI of libstarnt: argument validation on the host, then the launchers.
 // Every function enqueues on the caller's stream and returns without waiting.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -285,8 +286,16 @@ int starnt_train_step(const starnt_train* t, const float* x, const float* y, int
   if (!t || !x || !y || !hp || !loss) return fail(STARNT_EINVAL, "starnt_train_step: NULL argument");
   if (!t->params || !t->m || !t->v || !t->grad) return fail(STARNT_EINVAL, "starnt_train_step: NULL state array");
   if (t->in != 16 || t->out != 3) return fail(STARNT_EINVAL, "starnt_train_step: in must be 16 and out 3");
-  if (t->dtype != STARNT_F32 && t->dtype != STARNT_BF16)
-    return fail(STARNT_EINVAL, "starnt_train_step: dtype must be STARNT_F32 or STARNT_BF16");
+  if (t->dtype != STARNT_F32 && t->dtype != STARNT_BF16 && t->dtype != STARNT_FP8)
+    return fail(STARNT_EINVAL, "starnt_train_step: dtype must be STARNT_F32, STARNT_BF16 or STARNT_FP8");
+  if (t->dtype == STARNT_FP8) {
+    for (int l = 0; l < 3; ++l) {
+      int e = 0;
+      const float v = t->fp8_act_scale[l];
+      if (!(v > 0.0f) || !std::isfinite(v) || std::frexp(v, &e) != 0.5f)
+        return fail(STARNT_EINVAL, "starnt_train_step: FP8 activation scales must be positive powers of two");
+    }
+  }
   if (batch < 1 || batch > (1 << 24)) return fail(STARNT_EINVAL, "starnt_train_step: batch must be in [1, 2^24]");
   if (hp->step < 1) return fail(STARNT_EINVAL, "starnt_train_step: Adam step is 1-based");
   if (t->out_act != 0 && t->out_act != 1) return fail(STARNT_EINVAL, "starnt_train_step: out_act must be 0 or 1");
@@ -317,6 +326,39 @@ void starnt_pass_scales(double wbar, double* s2, double* s3) {
   const double a = std::exp2(wbar - 2.2), b = std::exp2(wbar - 3.0);
   if (s2) *s2 = std::fmin(1.0, std::fmax(0.25, a));
   if (s3) *s3 = std::fmin(1.0, std::fmax(0.25, b));
+}
+
+int starnt_m_minus_i(const double* vp_prev, const double* vp_cur, float* out) {
+  if (!vp_prev || !vp_cur || !out) return fail(STARNT_EINVAL, "starnt_m_minus_i: NULL argument");
+  // [vp_cur | I] reduced to [I | vp_cur^-1], largest pivot of each column
+  double a[4][8];
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 8; ++c) a[r][c] = c < 4 ? vp_cur[4 * r + c] : (c - 4 == r ? 1.0 : 0.0);
+  double scale = 0.0;
+  for (int i = 0; i < 16; ++i) scale = std::fmax(scale, std::fabs(vp_cur[i]));
+  for (int c = 0; c < 4; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 4; ++r)
+      if (std::fabs(a[r][c]) > std::fabs(a[piv][c])) piv = r;
+    if (!(std::fabs(a[piv][c]) > 1e-300 + 1e-14 * scale))
+      return fail(STARNT_EINVAL, "starnt_m_minus_i: vp_cur is singular");
+    if (piv != c)
+      for (int k = 0; k < 8; ++k) std::swap(a[c][k], a[piv][k]);
+    const double inv = 1.0 / a[c][c];
+    for (int k = 0; k < 8; ++k) a[c][k] *= inv;
+    for (int r = 0; r < 4; ++r) {
+      if (r == c) continue;
+      const double f = a[r][c];
+      for (int k = 0; k < 8; ++k) a[r][k] -= f * a[c][k];
+    }
+  }
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) {
+      double m = 0.0;
+      for (int k = 0; k < 4; ++k) m += vp_prev[4 * r + k] * a[k][4 + c];
+      out[4 * r + c] = (float)(m - (r == c ? 1.0 : 0.0));
+    }
+  return STARNT_OK;
 }
 
 int32_t starnt_grid_dim(int32_t n, double s) {

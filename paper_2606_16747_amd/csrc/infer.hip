@@ -345,16 +345,6 @@ __global__ __launch_bounds__(256) void infer_f32_kernel(InferArgs a) {
 // ---------------------------------------------------------------------------
 // matrix-core paths (BF16 and FP8)
 
-typedef long fp8x8;  // 8 E4M3 bytes
-
-// OCP E4M3 with round-to-nearest-even and saturation (hardware convert)
-__device__ __forceinline__ uint32_t e4m3_pack4(float a, float b, float c, float d) {
-  int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
-  w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
-  return (uint32_t)w;
-}
-__device__ __forceinline__ float sat448(float v) { return fminf(fmaxf(v, -448.0f), 448.0f); }
-
 // b = p[0] + p[1] + p[2] exactly, each part a bf16 value: p[0] is b rounded
 // to bf16 (8 significant bits), p[1] the remainder (at most 16 significant
 // bits, exact in FP32) rounded likewise, p[2] what is left (at most 8 bits)

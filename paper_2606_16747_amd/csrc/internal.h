@@ -92,6 +92,24 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
+// E4M3 operands of v_mfma_f32_32x32x16_fp8_fp8: the same lane layout as the
+// bf16 operands above, 8 one-byte values per lane.
+typedef long fp8x8;
+
+// OCP E4M3 of four values, round-to-nearest-even (hardware convert); callers
+// saturate to +-448 first
+__device__ __forceinline__ uint32_t e4m3_pack4(float a, float b, float c, float d) {
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+  w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+  return (uint32_t)w;
+}
+__device__ __forceinline__ float sat448(float v) { return fminf(fmaxf(v, -448.0f), 448.0f); }
+// the E4M3 value nearest to v (saturated), as a float
+__device__ __forceinline__ float e4m3_value(float v) {
+  const int w = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(v), 0.0f, 0, false);
+  return __builtin_amdgcn_cvt_f32_fp8(w, 0);
+}
+
 // Physical accumulator row r of a 32-row tile (lane half h = (r % 8) / 4,
 // block b = r / 8, element i = r % 4) holds logical hidden unit
 // 16 (b / 2) + 8 h + 4 (b % 2) + i, so that accumulator register v = 4 b + i

@@ -11,6 +11,13 @@
 // In BF16 mode every GEMM operand (weights, inputs, activations, output
 // gradients) is rounded to bf16 as the matrix cores would consume it; products
 // of two bf16 values are exact in FP32 and accumulation is FP32.
+// In FP8 mode the three forward products take OCP E4M3 operands on
+// v_mfma_f32_32x32x16_fp8_fp8: weights with a per-layer power-of-two scale
+// from the masters' largest magnitude, inputs and activations with the
+// caller's per-layer power-of-two scales. The backward products and weight
+// gradients run in bf16 on those same E4M3 values (a power-of-two multiple
+// of an E4M3 value is exact in bf16) and on bf16 output gradients, so the
+// gradient is that of the FP8 forward pass.
 //
 // BF16 with hidden widths 32 or 64 runs kernel 1 on the matrix cores
 // (train_mfma_kernel, below); FP32 and other widths use train_fwd_bwd on the
@@ -36,6 +43,7 @@ struct TrainArgs {
   int nparam;
   float inv_count;      // 1 / (batch * 3)
   int out_act;          // 0 ReLU, 1 logistic sigmoid
+  float sa[3];          // FP8: activation scale of each layer's input (powers of two)
 };
 
 template <bool BF>
@@ -263,6 +271,44 @@ __device__ __forceinline__ bf16x8 pack8(const float* w) {
 // 8 consecutive bf16 of an LDS row (16-byte aligned)
 __device__ __forceinline__ bf16x8 lds8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
 
+// Forward-pass operands: bf16, or E4M3 bytes of v * inv_s (FP8; every value
+// is already an E4M3 value times the scale, so the convert is exact)
+template <bool FP8>
+using FwdVec = typename std::conditional<FP8, fp8x8, bf16x8>::type;
+template <bool FP8>
+__device__ __forceinline__ FwdVec<FP8> pack_fwd(const float* w, float inv_s) {
+  if constexpr (FP8) {
+    const uint32_t lo = e4m3_pack4(sat448(w[0] * inv_s), sat448(w[1] * inv_s), sat448(w[2] * inv_s),
+                                   sat448(w[3] * inv_s));
+    const uint32_t hi = e4m3_pack4(sat448(w[4] * inv_s), sat448(w[5] * inv_s), sat448(w[6] * inv_s),
+                                   sat448(w[7] * inv_s));
+    return (long)(((unsigned long)hi << 32) | lo);
+  } else {
+    return pack8(w);
+  }
+}
+template <bool FP8>
+__device__ __forceinline__ f32x16 mfma_fwd(const FwdVec<FP8>& A, const FwdVec<FP8>& B, f32x16 c) {
+  if constexpr (FP8) return __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(A, B, c, 0, 0, 0);
+  else return mfma_bf16(A, B, c);
+}
+// The operand value a forward product sees: v rounded to bf16, or (FP8) to
+// the E4M3 grid of scale s (a power of two, so the result is also exact in
+// bf16 and the backward products and weight gradients take the same value)
+template <bool FP8>
+__device__ __forceinline__ float fwd_value(float v, float s, float inv_s) {
+  if constexpr (FP8) return e4m3_value(v * inv_s) * s;
+  else return q<true>(v);
+}
+// smallest power of two s with amax / s <= 448 (1 when amax is 0), by exact
+// comparisons on the exponent of amax
+__device__ __forceinline__ float e4m3_scale_for(float amax) {
+  if (!(amax > 0.0f)) return 1.0f;
+  int e;
+  const float m = frexpf(amax, &e);  // amax = m 2^e, m in [0.5, 1); 448 = 0.875 2^9
+  return ldexpf(1.0f, m <= 0.875f ? e - 9 : e - 8);
+}
+
 template <int T1, int T2>
 struct MfmaShape {
   static constexpr int H1 = 32 * T1, H2 = 32 * T2;
@@ -277,13 +323,14 @@ struct MfmaShape {
   static constexpr int lds_bytes = act_bytes > NP * 4 ? act_bytes : NP * 4;
 };
 
-template <int T1, int T2>
+template <int T1, int T2, bool FP8>
 __global__ __launch_bounds__(64 * kMWaves) void train_mfma_kernel(TrainArgs a) {
   using S = MfmaShape<T1, T2>;
   constexpr int H1 = S::H1, H2 = S::H2, NP = S::NP;
   __shared__ __attribute__((aligned(16))) unsigned char smem[S::lds_bytes];
   __shared__ __attribute__((aligned(16))) float sB[H1 + H2 + 4];
   __shared__ float sLoss[kMWaves];
+  __shared__ float sMax[3][kMWaves];
   float* sW = reinterpret_cast<float*>(smem);
   __bf16* sA = reinterpret_cast<__bf16*>(smem);
   auto row = [&](int r) { return sA + r * kRow; };
@@ -291,19 +338,60 @@ __global__ __launch_bounds__(64 * kMWaves) void train_mfma_kernel(TrainArgs a) {
 
   for (int i = tid; i < NP; i += 64 * kMWaves) sW[i] = a.params[i];
   __syncthreads();
+  // FP8: each layer's weight scale from the masters' largest magnitude, then
+  // the weights in LDS replaced by their E4M3 values (the masters in HBM stay
+  // FP32); activations use the caller's scales a.sa
+  float sw0 = 1.0f, sw1 = 1.0f, sw2 = 1.0f;
+  if constexpr (FP8) {
+    float m0 = 0.0f, m1 = 0.0f, m2 = 0.0f;
+    for (int i = tid; i < H1 * kIn; i += 64 * kMWaves) m0 = fmaxf(m0, fabsf(sW[S::oW1 + i]));
+    for (int i = tid; i < H2 * H1; i += 64 * kMWaves) m1 = fmaxf(m1, fabsf(sW[S::oW2 + i]));
+    for (int i = tid; i < 3 * H2; i += 64 * kMWaves) m2 = fmaxf(m2, fabsf(sW[S::oW3 + i]));
+#pragma unroll
+    for (int k = 32; k >= 1; k >>= 1) {
+      m0 = fmaxf(m0, __shfl_xor(m0, k));
+      m1 = fmaxf(m1, __shfl_xor(m1, k));
+      m2 = fmaxf(m2, __shfl_xor(m2, k));
+    }
+    if (l == 0) {
+      sMax[0][wave] = m0;
+      sMax[1][wave] = m1;
+      sMax[2][wave] = m2;
+    }
+    __syncthreads();
+    m0 = m1 = m2 = 0.0f;
+#pragma unroll
+    for (int w8 = 0; w8 < kMWaves; ++w8) {
+      m0 = fmaxf(m0, sMax[0][w8]);
+      m1 = fmaxf(m1, sMax[1][w8]);
+      m2 = fmaxf(m2, sMax[2][w8]);
+    }
+    sw0 = e4m3_scale_for(m0);
+    sw1 = e4m3_scale_for(m1);
+    sw2 = e4m3_scale_for(m2);
+    for (int i = tid; i < H1 * kIn; i += 64 * kMWaves) sW[S::oW1 + i] = fwd_value<true>(sW[S::oW1 + i], sw0, 1.0f / sw0);
+    for (int i = tid; i < H2 * H1; i += 64 * kMWaves) sW[S::oW2 + i] = fwd_value<true>(sW[S::oW2 + i], sw1, 1.0f / sw1);
+    for (int i = tid; i < 3 * H2; i += 64 * kMWaves) sW[S::oW3 + i] = fwd_value<true>(sW[S::oW3 + i], sw2, 1.0f / sw2);
+    __syncthreads();
+  }
+  const float iw0 = 1.0f / sw0, iw1 = 1.0f / sw1, iw2 = 1.0f / sw2;  // exact: powers of two
+  const float sa0 = FP8 ? a.sa[0] : 1.0f, sa1 = FP8 ? a.sa[1] : 1.0f, sa2 = FP8 ? a.sa[2] : 1.0f;
+  const float ia0 = 1.0f / sa0, ia1 = 1.0f / sa1, ia2 = 1.0f / sa2;
+  const float dq0 = sa0 * sw0, dq1 = sa1 * sw1, dq2 = sa2 * sw2;  // dequantisation of each layer's sums
   for (int i = tid; i < H1; i += 64 * kMWaves) sB[i] = sW[S::ob1 + i];
   for (int i = tid; i < H2; i += 64 * kMWaves) sB[H1 + i] = sW[S::ob2 + i];
   if (tid < 3) sB[H1 + H2 + tid] = sW[S::ob3 + tid];
 
   // ---- operands of the weights (every wave holds them) ----
-  bf16x8 A1[T1], A2[T2][2 * T1], A3[2 * T2], A3T[T2], A2T[T1][2 * T2];
+  FwdVec<FP8> A1[T1], A2[T2][2 * T1], A3[2 * T2];
+  bf16x8 A3T[T2], A2T[T1][2 * T2];
   float w[8];
 #pragma unroll
   for (int t = 0; t < T1; ++t) {
     const int u = 32 * t + perm_row(col);
 #pragma unroll
     for (int e = 0; e < 8; ++e) w[e] = sW[S::oW1 + u * kIn + 8 * h + e];
-    A1[t] = pack8(w);
+    A1[t] = pack_fwd<FP8>(w, iw0);
   }
 #pragma unroll
   for (int t = 0; t < T2; ++t) {
@@ -312,7 +400,7 @@ __global__ __launch_bounds__(64 * kMWaves) void train_mfma_kernel(TrainArgs a) {
     for (int c = 0; c < 2 * T1; ++c) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) w[e] = sW[S::oW2 + u * H1 + 16 * c + 8 * h + e];
-      A2[t][c] = pack8(w);
+      A2[t][c] = pack_fwd<FP8>(w, iw1);
     }
     // W3^T: row = layer-2 unit u, K = output 8 h + e (three live)
 #pragma unroll
@@ -323,7 +411,7 @@ __global__ __launch_bounds__(64 * kMWaves) void train_mfma_kernel(TrainArgs a) {
   for (int c = 0; c < 2 * T2; ++c) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) w[e] = col < 3 ? sW[S::oW3 + col * H2 + 16 * c + 8 * h + e] : 0.0f;
-    A3[c] = pack8(w);
+    A3[c] = pack_fwd<FP8>(w, iw2);
   }
   // W2^T: row = layer-1 unit j (permuted as layer 1), K = layer-2 unit 16 c + 8 h + e
 #pragma unroll
@@ -348,7 +436,10 @@ __global__ __launch_bounds__(64 * kMWaves) void train_mfma_kernel(TrainArgs a) {
   for (int c = 0; c < kIn; c += 4) {
     const float4 v = valid ? *reinterpret_cast<const float4*>(a.x + (size_t)smp * kIn + c)
                            : make_float4(0.f, 0.f, 0.f, 0.f);
-    x[c] = q<true>(v.x); x[c + 1] = q<true>(v.y); x[c + 2] = q<true>(v.z); x[c + 3] = q<true>(v.w);
+    x[c] = fwd_value<FP8>(v.x, sa0, ia0);
+    x[c + 1] = fwd_value<FP8>(v.y, sa0, ia0);
+    x[c + 2] = fwd_value<FP8>(v.z, sa0, ia0);
+    x[c + 3] = fwd_value<FP8>(v.w, sa0, ia0);
   }
   float y[3];
 #pragma unroll
@@ -369,60 +460,60 @@ __global__ __launch_bounds__(64 * kMWaves) void train_mfma_kernel(TrainArgs a) {
   float lsum = 0.0f;
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
-    const bf16x8 XB = pack8(g == 0 ? xa : xb);
+    const FwdVec<FP8> XB = pack_fwd<FP8>(g == 0 ? xa : xb, ia0);
     const int sl = 32 * g + col;   // the wave's sample this lane's column stands for
     const int sc = c0 + sl;        // its LDS column
     // ---- layer 1 ----
-    bf16x8 H1c[2 * T1];
+    FwdVec<FP8> H1c[2 * T1];
     uint32_t m1[T1];
 #pragma unroll
     for (int t = 0; t < T1; ++t) {
       f32x16 acc = {};
-      acc = mfma_bf16(A1[t], XB, acc);
+      acc = mfma_fwd<FP8>(A1[t], XB, acc);
       uint32_t m = 0;
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         float hv[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const float z = acc[8 * c + e] + sB[32 * t + 16 * c + 8 * h + e];
+          const float z = fmaf(acc[8 * c + e], dq0, sB[32 * t + 16 * c + 8 * h + e]);
           m |= (z > 0.0f ? 1u : 0u) << (8 * c + e);
-          hv[e] = fmaxf(z, 0.0f);
+          hv[e] = fwd_value<FP8>(fmaxf(z, 0.0f), sa1, ia1);
         }
-        H1c[2 * t + c] = pack8(hv);
+        H1c[2 * t + c] = pack_fwd<FP8>(hv, ia1);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) row(S::rH1 + 32 * t + 16 * c + 8 * h + e)[sc] = H1c[2 * t + c][e];
+        for (int e = 0; e < 8; ++e) row(S::rH1 + 32 * t + 16 * c + 8 * h + e)[sc] = static_cast<__bf16>(hv[e]);
       }
       m1[t] = m;
     }
     // ---- layer 2 ----
-    bf16x8 H2c[2 * T2];
+    FwdVec<FP8> H2c[2 * T2];
     uint32_t m2[T2];
 #pragma unroll
     for (int t = 0; t < T2; ++t) {
       f32x16 acc = {};
 #pragma unroll
-      for (int c = 0; c < 2 * T1; ++c) acc = mfma_bf16(A2[t][c], H1c[c], acc);
+      for (int c = 0; c < 2 * T1; ++c) acc = mfma_fwd<FP8>(A2[t][c], H1c[c], acc);
       uint32_t m = 0;
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         float hv[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const float z = acc[8 * c + e] + sB[H1 + 32 * t + 16 * c + 8 * h + e];
+          const float z = fmaf(acc[8 * c + e], dq1, sB[H1 + 32 * t + 16 * c + 8 * h + e]);
           m |= (z > 0.0f ? 1u : 0u) << (8 * c + e);
-          hv[e] = fmaxf(z, 0.0f);
+          hv[e] = fwd_value<FP8>(fmaxf(z, 0.0f), sa2, ia2);
         }
-        H2c[2 * t + c] = pack8(hv);
+        H2c[2 * t + c] = pack_fwd<FP8>(hv, ia2);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) row(S::rH2 + 32 * t + 16 * c + 8 * h + e)[sc] = H2c[2 * t + c][e];
+        for (int e = 0; e < 8; ++e) row(S::rH2 + 32 * t + 16 * c + 8 * h + e)[sc] = static_cast<__bf16>(hv[e]);
       }
       m2[t] = m;
     }
     // ---- output, loss and dL/dz3 (half 0 holds the three outputs) ----
     f32x16 acc3 = {};
 #pragma unroll
-    for (int c = 0; c < 2 * T2; ++c) acc3 = mfma_bf16(A3[c], H2c[c], acc3);
+    for (int c = 0; c < 2 * T2; ++c) acc3 = mfma_fwd<FP8>(A3[c], H2c[c], acc3);
     const float yg0 = __shfl(y[0], sl), yg1 = __shfl(y[1], sl), yg2 = __shfl(y[2], sl);
     const float wg = __shfl(wsmp, sl);
     const bool vg = blockIdx.x * kMSamples + sc < a.batch;
@@ -431,7 +522,7 @@ __global__ __launch_bounds__(64 * kMWaves) void train_mfma_kernel(TrainArgs a) {
       const float yy[3] = {yg0, yg1, yg2};
 #pragma unroll
       for (int o = 0; o < 3; ++o) {
-        const float z = acc3[o] + sB[H1 + H2 + o];
+        const float z = fmaf(acc3[o], dq2, sB[H1 + H2 + o]);
         const float f = a.out_act ? 1.0f / (1.0f + expf(-z)) : fmaxf(z, 0.0f);
         const float e = f - yy[o];
         lsum = fmaf(wg * e * e, a.inv_count, lsum);
@@ -585,14 +676,24 @@ int launch_train(const starnt_train& tr, const float* x, const float* y, int bat
   int nblocks = nb;
   // BF16 with hidden widths 32 or 64: the matrix-core kernel, kMSamples
   // samples per block
-  const bool mf = bf && (tr.h1 == 32 || tr.h1 == 64) && (tr.h2 == 32 || tr.h2 == 64);
+  const bool f8 = tr.dtype == STARNT_FP8;
+  const bool mf = (bf || f8) && (tr.h1 == 32 || tr.h1 == 64) && (tr.h2 == 32 || tr.h2 == 64);
+  if (f8 && !mf) return fail(STARNT_EUNSUPPORTED, "starnt_train_step: FP8 needs hidden widths of 32 or 64");
+  for (int l = 0; l < 3; ++l) t.sa[l] = tr.fp8_act_scale[l];
   if (mf) {
     nblocks = (batch + kMSamples - 1) / kMSamples;
     const dim3 grid((unsigned)nblocks), block(64 * kMWaves);
-    if (tr.h1 == 32 && tr.h2 == 32) hipLaunchKernelGGL((train_mfma_kernel<1, 1>), grid, block, 0, s, t);
-    else if (tr.h1 == 32) hipLaunchKernelGGL((train_mfma_kernel<1, 2>), grid, block, 0, s, t);
-    else if (tr.h2 == 32) hipLaunchKernelGGL((train_mfma_kernel<2, 1>), grid, block, 0, s, t);
-    else hipLaunchKernelGGL((train_mfma_kernel<2, 2>), grid, block, 0, s, t);
+    if (f8) {
+      if (tr.h1 == 32 && tr.h2 == 32) hipLaunchKernelGGL((train_mfma_kernel<1, 1, true>), grid, block, 0, s, t);
+      else if (tr.h1 == 32) hipLaunchKernelGGL((train_mfma_kernel<1, 2, true>), grid, block, 0, s, t);
+      else if (tr.h2 == 32) hipLaunchKernelGGL((train_mfma_kernel<2, 1, true>), grid, block, 0, s, t);
+      else hipLaunchKernelGGL((train_mfma_kernel<2, 2, true>), grid, block, 0, s, t);
+    } else {
+      if (tr.h1 == 32 && tr.h2 == 32) hipLaunchKernelGGL((train_mfma_kernel<1, 1, false>), grid, block, 0, s, t);
+      else if (tr.h1 == 32) hipLaunchKernelGGL((train_mfma_kernel<1, 2, false>), grid, block, 0, s, t);
+      else if (tr.h2 == 32) hipLaunchKernelGGL((train_mfma_kernel<2, 1, false>), grid, block, 0, s, t);
+      else hipLaunchKernelGGL((train_mfma_kernel<2, 2, false>), grid, block, 0, s, t);
+    }
   }
 #define TCASE(A, B)                                                        \
   else if (tr.h1 == A && tr.h2 == B) {                                     \

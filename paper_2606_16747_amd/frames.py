@@ -16,15 +16,15 @@ import torch
 from . import (MODE_EXACT, MODE_LEARNED, WS_QUADTREE, WS_REPROJECT, DeviceFrags, DeviceMlp, FeatBuffers, QtParams,
                starnt_composite, starnt_features, starnt_infer_composite, starnt_infer_composite_sel,
                starnt_interval_init,
-               starnt_interval_next, starnt_interval_report, starnt_patch, starnt_quadtree, starnt_reproject,
+               starnt_interval_next, starnt_interval_report, starnt_m_minus_i, starnt_patch, starnt_quadtree,
+               starnt_reproject,
                starnt_reproject_check, starnt_sched_init,
                starnt_workspace_size, workspace)
 
 
 def m_minus_i(vp_real, vp_cur):
-    """M - I with M = VP_real VP_cur^-1 (FP64 on the host, then FP32)."""
-    M = np.asarray(vp_real, np.float64).reshape(4, 4) @ np.linalg.inv(np.asarray(vp_cur, np.float64).reshape(4, 4))
-    return (M - np.eye(4)).astype(np.float32)
+    """M - I with M = VP_real VP_cur^-1 (the library's host helper, FP64 then FP32)."""
+    return starnt_m_minus_i(vp_real, vp_cur)
 
 
 class Renderer:

@@ -24,7 +24,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import (BF16, NET_DFAOIT, WS_TRAIN, Adam, DeviceFrags, FeatBuffers, Train,
+from . import (BF16, FP8, NET_DFAOIT, WS_TRAIN, Adam, DeviceFrags, FeatBuffers, Train,
                starnt_dfa_inputs, starnt_features, starnt_train_step, starnt_workspace_size, workspace)
 from .frames import exact_frame
 
@@ -82,12 +82,43 @@ class Pow2Scaler:
         return (W1 * self.sc[None, :]).astype(np.float32), np.asarray(b1, np.float32)
 
 
+def e4m3_scale(amax):
+    """Smallest power of two s with amax / s <= 448 (1 for amax = 0): the
+    rule the training kernel applies to each layer's weights."""
+    amax = float(amax)
+    if not amax > 0.0:
+        return 1.0
+    m, e = np.frexp(amax)  # amax = m 2^e, m in [0.5, 1); 448 = 0.875 2^9
+    return float(np.ldexp(1.0, int(e) - 9 if m <= 0.875 else int(e) - 8))
+
+
+def activation_amax(Ws, bs, x):
+    """Largest magnitude of each layer's input over the samples x (FP64
+    forward of the current weights), for the E4M3 activation scales."""
+    amax = [float(np.abs(x).max())]
+    h = np.asarray(x, np.float64)
+    for w, b in list(zip(Ws, bs))[:2]:
+        h = np.maximum(h @ np.asarray(w, np.float64).T + b, 0.0)
+        amax.append(float(np.abs(h).max()))
+    return amax
+
+
+def fp8_inference_scales(Ws, bs, x):
+    """The six scales (s_a, s_w per layer, powers of two) of an FP8 network
+    for inputs like x: twice the observed activation range, the weights'."""
+    sa = [e4m3_scale(2.0 * v) for v in activation_amax(Ws, bs, x)]
+    sw = [e4m3_scale(np.abs(w).max()) for w in Ws]
+    return [v for pair in zip(sa, sw) for v in pair]
+
+
 def train(x, y, Ws, bs, steps=3000, batch=65536, lr=2e-3, lr_min=1e-4, dtype=BF16, seed=0, log_every=0,
-          device="cuda", stream=None, variant=0, weight=None):
+          device="cuda", stream=None, variant=0, weight=None, fp8_every=250):
     """Train from initial weights (Ws, bs); returns (Ws, bs, losses) with the
     input scaling folded into layer 1. variant NET_DFAOIT trains the
     sigmoid-output network on its eleven inputs; weight [M] gives per-sample
-    loss weights (None: plain MSE)."""
+    loss weights (None: plain MSE). dtype FP8 runs the forward products on
+    E4M3 operands; the activation scales (twice the observed range, powers of
+    two) are recalibrated from the current weights every fp8_every steps."""
     dims = (Ws[0].shape[1], Ws[0].shape[0], Ws[1].shape[0], Ws[2].shape[0])
     dfa = variant == NET_DFAOIT
     st = Pow2Scaler(x, 11 if dfa else 5)
@@ -109,7 +140,22 @@ def train(x, y, Ws, bs, steps=3000, batch=65536, lr=2e-3, lr_min=1e-4, dtype=BF1
                1 if dfa else 0)
     ws = workspace(starnt_workspace_size(WS_TRAIN, batch, dims[1], dims[2]), device)
     loss = torch.zeros(steps, dtype=torch.float32, device=device)
+    cal = st.apply(x[order[: min(len(x), 65536)]]).astype(np.float64)
+    shapes = [(dims[1], dims[0]), (dims[1],), (dims[2], dims[1]), (dims[2],), (dims[3], dims[2]), (dims[3],)]
+
+    def unflatten(flat_np):
+        parts, k = [], 0
+        for sh in shapes:
+            n = int(np.prod(sh))
+            parts.append(flat_np[k:k + n].reshape(sh))
+            k += n
+        return parts
     for t in range(steps):
+        if dtype == FP8 and t % fp8_every == 0:
+            parts = unflatten(p.cpu().numpy())
+            amax = activation_amax(parts[0::2], parts[1::2], cal)
+            for l in range(3):
+                tr.fp8_act_scale[l] = e4m3_scale(2.0 * amax[l])
         b = int(rng.integers(nb))
         lr_t = lr_min + 0.5 * (lr - lr_min) * (1 + np.cos(np.pi * t / max(1, steps)))
         ad = Adam(lr_t, 0.9, 0.999, 1e-8, t + 1)
@@ -122,14 +168,6 @@ def train(x, y, Ws, bs, steps=3000, batch=65536, lr=2e-3, lr_min=1e-4, dtype=BF1
             torch.cuda.synchronize()
             print("step %d loss %.3e" % (t, float(loss[t])), flush=True)
     torch.cuda.synchronize()
-    out = p.cpu().numpy()
-    i, h1, h2, o = dims
-    k = 0
-    shapes = [(h1, i), (h1,), (h2, h1), (h2,), (o, h2), (o,)]
-    parts = []
-    for s in shapes:
-        n = int(np.prod(s))
-        parts.append(out[k:k + n].reshape(s))
-        k += n
+    parts = unflatten(p.cpu().numpy())
     W1, b1 = st.fold(parts[0].astype(np.float64), parts[1].astype(np.float64))
     return [W1, parts[2], parts[4]], [b1, parts[3], parts[5]], loss.cpu().numpy()

@@ -44,6 +44,23 @@ def test_host_helpers_match_the_pinned_oracle(starnt, oracle_mod):
             assert starnt.starnt_grid_dim(n, s) == oracle_mod.grid_dim(n, s)
 
 
+def test_m_minus_i_helper_matches_the_oracle(starnt, oracle_mod, sg):
+    """The library's host helper for the reprojection matrix equals the
+    oracle's M - I (both FP64, rounded to FP32) on the camera path of the
+    1080p workload and on a random well-conditioned pair; a singular current
+    matrix is rejected."""
+    sc = sg.Scene("c2_1080p", width=64, height=36, num_tris=10)
+    rng = np.random.default_rng(0)
+    pairs = [(sc.camera(0), sc.camera(t)) for t in range(1, 8)]
+    pairs.append((rng.normal(size=(4, 4)) + 4 * np.eye(4), rng.normal(size=(4, 4)) + 4 * np.eye(4)))
+    for a, b in pairs:
+        got = starnt.starnt_m_minus_i(a, b)
+        want = oracle_mod.m_minus_i(a, b)
+        assert np.abs(got.astype(np.float64) - want).max() <= 1e-6 * max(1.0, np.abs(want).max())
+    with pytest.raises(starnt.StarntError):
+        starnt.starnt_m_minus_i(np.eye(4), np.zeros((4, 4)))
+
+
 def test_workspace_sizes(starnt):
     assert starnt.starnt_workspace_size(starnt.WS_QUADTREE, 1920, 1080, 64) > 0
     assert starnt.starnt_workspace_size(starnt.WS_QUADTREE, 1920, 1080, 12) == 0  # not a multiple of 8

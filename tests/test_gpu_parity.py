@@ -159,6 +159,19 @@ def _grids_for(oracle_mod, W, H, s2, s3):
             oracle_mod.grid_dim(H, s3))
 
 
+def _assert_device_grids(got, oracle_mod, W, H, s2, s3):
+    """The device's eq (4) grids (FP32) against the FP64 definition: equal,
+    except a side where s * n lies within 1e-5 n of an integer (FP32's reach)
+    may be either neighbour."""
+    want = _grids_for(oracle_mod, W, H, s2, s3)
+    for g, w_, n, sc in zip(got, want, (W, H, W, H), (s2, s2, s3, s3)):
+        v = sc * n
+        if abs(v - round(v)) < 1e-5 * n:
+            assert abs(g - w_) <= 1, (got, want)
+        else:
+            assert g == w_, (got, want)
+
+
 @pytest.mark.parametrize("s2,s3", [(1.0, 1.0), (0.5, 0.25), (0.77, 0.31)])
 @pytest.mark.parametrize("mode", ["learned", "f0", "favg"])
 def test_learned_composite_fp32_mixed_resolution(starnt, gpu, sg, oracle_mod, s2, s3, mode):
@@ -267,7 +280,7 @@ def test_quadtree_matches_oracle_over_frames(starnt, gpu, sg, oracle_mod):
         wb = oracle_mod.wbar(hist)
         assert abs(s["wbar"] - wb) < 1e-6
         s2, s3 = oracle_mod.pass_scales(wb)
-        assert (s["w2"], s["h2"], s["w3"], s["h3"]) == _grids_for(oracle_mod, W, H, s2, s3)
+        _assert_device_grids((s["w2"], s["h2"], s["w3"], s["h3"]), oracle_mod, W, H, s2, s3)
         assert s["frames"] == t + 1
         prev, prev_o = cur, m
     assert sum(s["hist"][1:]) > 0  # something split
@@ -424,6 +437,45 @@ def test_train_step_bf16_gradient_direction(starnt, gpu, sg, oracle_mod):
     cos = gg @ gw / (np.linalg.norm(gg) * np.linalg.norm(gw))
     assert cos > 0.999, cos
     assert np.linalg.norm(gg - gw) / np.linalg.norm(gw) < 0.05
+
+
+@pytest.mark.parametrize("dims,batch", [((16, 64, 64, 3), 8192), ((16, 32, 64, 3), 3000)])
+def test_train_step_fp8(starnt, gpu, sg, oracle_mod, dims, batch, capsys):
+    """FP8 mode: the forward products on E4M3 operands (per-layer power-of-two
+    scales: the caller's for activations, the kernel's rule for weights),
+    the backward in bf16 on the same values. The step's loss against the
+    oracle's E4M3 forward on those scales (rel 1e-3: a mean over the batch,
+    so a few samples whose activations round differently move it little);
+    the gradient against the FP64 gradient of the unquantised network
+    (cosine and rel-L2 stated)."""
+    from paper_2606_16747_amd import learn
+    x, y, params = _train_setup(sg, oracle_mod, dims, batch, seed=4)
+    n = params.size
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    p, m, v, g = dev(params.copy()), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    Ws, bs = oracle_mod.split_params(dims, params.astype(np.float64))
+    sa = [learn.e4m3_scale(2.0 * a) for a in learn.activation_amax(Ws, bs, x.astype(np.float64))]
+    sw = [learn.e4m3_scale(np.abs(w).max()) for w in Ws]
+    tr = starnt.Train(16, dims[1], dims[2], 3, starnt.FP8, p.data_ptr(), m.data_ptr(), v.data_ptr(), g.data_ptr())
+    for l in range(3):
+        tr.fp8_act_scale[l] = sa[l]
+    loss = torch.zeros(1, device="cuda")
+    ws = starnt.workspace(starnt.starnt_workspace_size(starnt.WS_TRAIN, batch, dims[1], dims[2]))
+    starnt.starnt_train_step(tr, dev(x), dev(y), batch, starnt.Adam(1e-3, 0.9, 0.999, 1e-8, 1), loss, ws)
+    sync()
+    om = oracle_mod.Mlp([w.astype(np.float32) for w in Ws], [b.astype(np.float32) for b in bs])
+    fq = om.forward_q(x.astype(np.float64), 2, np.array(sa), np.array(sw))
+    lq = float(((fq - y) ** 2).mean())
+    lg = float(to_np(loss)[0])
+    _, gw = oracle_mod.loss_grad(dims, params.astype(np.float64), x, y)
+    gg = to_np(g).astype(np.float64)
+    cos = gg @ gw / (np.linalg.norm(gg) * np.linalg.norm(gw))
+    rel = np.linalg.norm(gg - gw) / np.linalg.norm(gw)
+    with capsys.disabled():
+        print("\n[FP8 training step %s] loss %.6e vs oracle E4M3 forward %.6e; gradient vs FP64: cosine %.5f, "
+              "rel-L2 %.4f" % (dims, lg, lq, cos, rel))
+    assert abs(lg - lq) <= 1e-3 * lq
+    assert cos > 0.98 and rel < 0.2, (cos, rel)
 
 
 @pytest.mark.parametrize("dtype,dims,batch", [("f32", (16, 32, 32, 3), 1000), ("f32", (16, 64, 64, 3), 4096),

@@ -11,13 +11,16 @@
 //      load instruction covers a contiguous run of the CSR arrays); depths go
 //      to LDS, RGBA stays in the loading lane's registers;
 //   2. each lane ranks its fragments within their list by counting the
-//      smaller depths there, eight per LDS round trip (depth bits compare as
-//      unsigned integers, which orders valid depths in [0, 1] as numbers); the
-//      pixel lanes first mark every fragment with its list's range, so no
-//      lane searches for its fragment's list;
+//      smaller keys there, eight per LDS round trip. A key is the depth's
+//      bits (which order valid depths in [0, 1] as numbers) less their four
+//      lowest, under the list's index within the batch, so keys of later
+//      lists are larger and a count over whole 8-key blocks needs no mask;
+//      the pixel lanes first mark every fragment with its list's range, so
+//      no lane searches for its fragment's list;
 //   3. each fragment writes its index at its sorted slot and reads it back: a
-//      slot claimed twice means equal depths in a list, and only then are the
-//      ranks recounted with primitive ids (read from HBM for that batch);
+//      slot claimed twice means equal keys in a list (equal depths, or
+//      depths within 2^-19 of each other), and only then are the ranks
+//      recounted on the exact (depth, primitive id) for that batch;
 //   4. RGBA is scattered to its sorted slot in LDS and one lane per pixel
 //      walks its list front to back.
 // The transmittance is a compensated FP32 product (value + error term).
@@ -98,10 +101,15 @@ __device__ __forceinline__ void write_pixel(const ExactArgs& a, int p, const Wal
 
 template <bool HALF, bool FSTAR>
 __global__ __launch_bounds__(64) void exact_wave_kernel(ExactArgs a) {
-  __shared__ uint32_t s_z[kCapW + 8];  // depth bits in staging order (+8: the 8-wide reads' overrun)
-  __shared__ float4 s_c[kCapW];        // list ranges, then prim ids (tie recount), then sorted RGBA
+  // s_key[i]: (list within the batch << 26) | (depth bits >> 4): within a
+  // list the order of the depths (to 2^-19 relative; closer depths compare
+  // equal and go to the exact recount), and every key of a later list (or of
+  // the padding past the batch) larger, so a count over whole 8-key blocks
+  // from a list's start needs no mask
+  __shared__ uint32_t s_key[kCapW + 8];
+  __shared__ float4 s_c[kCapW];        // list descriptors, then prim ids (recount), then sorted RGBA
   __shared__ uint16_t s_idx[kCapW];    // slot claims
-  uint32_t* s_rng = reinterpret_cast<uint32_t*>(s_c);  // [kCapW]: (list start << 16) | list end
+  uint32_t* s_rng = reinterpret_cast<uint32_t*>(s_c);  // [kCapW]: (list << 20) | (start << 10) | end
 
   const int l = (int)threadIdx.x;
   const int P = a.W * a.H;
@@ -145,51 +153,53 @@ __global__ __launch_bounds__(64) void exact_wave_kernel(ExactArgs a) {
         zb[k] = __float_as_uint(a.depth[bcur + i]);
         c[k] = load_rgba<HALF>(a.rgba, bcur + i);
       }
-      // each pixel lane marks its fragments with its list's range
+      // each pixel lane marks its fragments with its list's descriptor
       if (mine) {
-        const uint32_t rng = ((uint32_t)s0 << 16) | (uint32_t)(s0 + (int)n);
-        for (int t = 0; t < (int)n; ++t) s_rng[s0 + t] = rng;
+        const uint32_t d = ((uint32_t)(l - cur) << 20) | ((uint32_t)s0 << 10) | (uint32_t)(s0 + (int)n);
+        for (int t = 0; t < (int)n; ++t) s_rng[s0 + t] = d;
       }
-#pragma unroll
-      for (int k = 0; k < kSlots; ++k) {
-        const int i = l + 64 * k;
-        if (i < m) {
-          s_z[i] = zb[k];
-          errf |= zb[k] > kOneBits ? STARNT_DERR_DEPTH : 0u;  // negatives, -0 and NaN too
-          errf |= (c[k].w >= 0.0f && c[k].w <= 1.0f) ? 0u : STARNT_DERR_ALPHA;
-        }
-      }
+      if (l < 8) s_key[m + l] = 0xFFFFFFFFu;  // padding: larger than every key
       __syncthreads();
-      // 2. ranks by counting the smaller depths of the list, eight per LDS
-      // round trip (reads past the list's end are masked off)
+      uint32_t kb[kSlots];
       int sb[kSlots], se[kSlots], pos[kSlots];
 #pragma unroll
       for (int k = 0; k < kSlots; ++k) {
         const int i = l + 64 * k;
+        kb[k] = 0;
         sb[k] = se[k] = pos[k] = 0;
         if (i < m) {
-          const uint32_t rng = s_rng[i];
-          sb[k] = (int)(rng >> 16);
-          se[k] = (int)(rng & 0xFFFFu);
+          const uint32_t d = s_rng[i];
+          sb[k] = (int)((d >> 10) & 0x3FFu);
+          se[k] = (int)(d & 0x3FFu);
+          // depths outside [0, 1] (flagged) take 1's key and the exact recount
+          kb[k] = ((d >> 20) << 26) | (min(zb[k], kOneBits) >> 4);
+          s_key[i] = kb[k];
+          errf |= zb[k] > kOneBits ? STARNT_DERR_DEPTH : 0u;  // negatives, -0 and NaN too
+          errf |= (c[k].w >= 0.0f && c[k].w <= 1.0f) ? 0u : STARNT_DERR_ALPHA;
+        }
+      }
+      __syncthreads();  // descriptors read, keys written
+      // 2. ranks: the count of smaller keys from the list's start, eight per
+      // LDS round trip
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k) {
+        const int i = l + 64 * k;
+        if (i < m) {
           int r = 0;
           for (int j = sb[k]; j < se[k]; j += 8) {
             uint32_t v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = s_z[j + u];
+            for (int u = 0; u < 8; ++u) v[u] = s_key[j + u];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) r += (j + u < se[k] && v[u] < zb[k]) ? 1 : 0;
+            for (int u = 0; u < 8; ++u) r += v[u] < kb[k] ? 1 : 0;
           }
           pos[k] = sb[k] + r;
+          s_idx[pos[k]] = (uint16_t)i;
         }
       }
-      __syncthreads();  // every range is read before the claims and RGBA reuse s_c
-#pragma unroll
-      for (int k = 0; k < kSlots; ++k) {
-        const int i = l + 64 * k;
-        if (i < m) s_idx[pos[k]] = (uint16_t)i;
-      }
       __syncthreads();
-      // 3. every slot claimed once, or equal depths somewhere in the batch
+      // 3. every slot claimed once, or equal keys somewhere in the batch:
+      // then exact ranks on (depth, prim)
       bool clash = false;
 #pragma unroll
       for (int k = 0; k < kSlots; ++k) {
@@ -206,6 +216,7 @@ __global__ __launch_bounds__(64) void exact_wave_kernel(ExactArgs a) {
           if (i < m) {
             pr[k] = a.prim[bcur + i];
             s_pr[i] = pr[k];
+            s_key[i] = zb[k];  // the exact depth bits
           }
         }
         __syncthreads();
@@ -218,7 +229,7 @@ __global__ __launch_bounds__(64) void exact_wave_kernel(ExactArgs a) {
             // permutation of the list's slots
             int r = 0;
             for (int j = sb[k]; j < se[k]; ++j) {
-              const uint32_t zj = s_z[j], pj = s_pr[j];
+              const uint32_t zj = s_key[j], pj = s_pr[j];
               r += (zj < zb[k]) | ((zj == zb[k]) & ((pj < pr[k]) | ((pj == pr[k]) & (j < i))));
             }
             pos[k] = sb[k] + r;

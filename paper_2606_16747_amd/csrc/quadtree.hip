@@ -59,19 +59,21 @@ __device__ void finish_schedule(const uint32_t* tile_hist, int T, int W, int H, 
   for (int off = 32; off > 0; off >>= 1)
     for (int l = 0; l < 4; ++l) h[l] += __shfl_down(h[l], off);
   if (t == 0) {
-    const double den = (double)h[0] + h[1] + h[2] + h[3];
-    const double wb = den > 0 ? ((double)h[1] + 2.0 * h[2] + 3.0 * h[3]) / den : 0.0;
-    const double s2 = fmin(1.0, fmax(0.25, exp2(wb - 2.2)));
-    const double s3 = fmin(1.0, fmax(0.25, exp2(wb - 3.0)));
-    auto dim = [](int n, double sc) {
-      double v = ceil(sc * (double)n);
-      v = fmax(1.0, fmin((double)n, v));
+    // FP32 (a grid side can differ from the FP64 definition only where
+    // s * n lies within FP32 rounding of an integer)
+    const float den = (float)h[0] + (float)h[1] + (float)h[2] + (float)h[3];
+    const float wb = den > 0.0f ? ((float)h[1] + 2.0f * (float)h[2] + 3.0f * (float)h[3]) / den : 0.0f;
+    const float s2 = fminf(1.0f, fmaxf(0.25f, exp2f(wb - 2.2f)));
+    const float s3 = fminf(1.0f, fmaxf(0.25f, exp2f(wb - 3.0f)));
+    auto dim = [](int n, float sc) {
+      float v = ceilf(sc * (float)n);
+      v = fmaxf(1.0f, fminf((float)n, v));
       return (int)v;
     };
     for (int l = 0; l < 4; ++l) s->hist[l] = h[l];
-    s->wbar = (float)wb;
-    s->s2 = (float)s2;
-    s->s3 = (float)s3;
+    s->wbar = wb;
+    s->s2 = s2;
+    s->s3 = s3;
     s->w2 = dim(W, s2);
     s->h2 = dim(H, s2);
     s->w3 = dim(W, s3);

@@ -64,7 +64,7 @@ def _load():
             lib.orc_mlp_forward_q_act.restype = ctypes.c_int
             lib.orc_mlp_forward_q_amb.restype = ctypes.c_int
             lib.orc_mlp_forward_q_amb.argtypes = [ctypes.POINTER(_Mlp), _P, ctypes.c_int64, ctypes.c_int32, _P, _P,
-                                                  ctypes.c_int32, ctypes.c_double, ctypes.c_double, _P, _P]
+                                                  ctypes.c_int32, ctypes.c_double, ctypes.c_double, _P, _P, _P]
             lib.orc_mlp_forward_q_act.argtypes = [ctypes.POINTER(_Mlp), _P, ctypes.c_int64, ctypes.c_int32, _P, _P,
                                                   ctypes.c_int32, _P]
             lib.orc_mlp_loss_grad_act.restype = ctypes.c_double
@@ -218,21 +218,23 @@ class Mlp:
             raise RuntimeError("orc_mlp_forward_q failed")
         return y
 
-    def forward_q_amb(self, x, qmode, sa=None, sw=None, tol_in=0.0, tol_h=0.0):
+    def forward_q_amb(self, x, qmode, sa=None, sw=None, tol_in=0.0, tol_h=0.0, with_mag=False):
         """forward_q plus, per sample, which rounded operands are ambiguous:
         bit 0 when an input moved by tol_in |v| rounds differently, bit 1 when
         a hidden activation moved by tol_h times the sum of the absolute terms
-        (and bias) that produce it does."""
+        (and bias) that produce it does. with_mag: also each output's sum of
+        absolute terms and bias."""
         x = _c(x, np.float64)
         n = x.shape[0]
         y = np.empty((n, self.dims[3]), np.float64)
         amb = np.zeros(n, np.uint8)
+        ym = np.empty((n, self.dims[3]), np.float64) if with_mag else None
         sa_ = _c(sa if sa is not None else np.ones(3), np.float64)
         sw_ = _c(sw if sw is not None else np.ones(3), np.float64)
         if _load().orc_mlp_forward_q_amb(ctypes.byref(self._s), _ptr(x), n, int(qmode), _ptr(sa_), _ptr(sw_),
-                                         self.act, float(tol_in), float(tol_h), _ptr(y), _ptr(amb)) != 0:
+                                         self.act, float(tol_in), float(tol_h), _ptr(y), _ptr(amb), _ptr(ym)) != 0:
             raise RuntimeError("orc_mlp_forward_q_amb failed")
-        return y, amb
+        return (y, amb, ym) if with_mag else (y, amb)
 
     def params(self):
         """Flat FP64 parameter vector: W1, b1, W2, b2, W3, b3."""

@@ -325,9 +325,12 @@ static double narrow(double v, int32_t qmode, double scale) {
  * activation moved by tol_h times the sum of the absolute terms (and the
  * bias) that produce it. A computation in another precision that stays
  * within those distances rounds every operand of an unflagged sample to the
- * same value as this one, or to one within 4 d of it. */
+ * same value as this one, or to one within 4 d of it. Optional ymag [n][out]:
+ * each output's sum of absolute terms and bias (the size its own
+ * accumulation error scales with). */
 int orc_mlp_forward_q_amb(const orc_mlp* m, const double* x, int64_t n, int32_t qmode, const double* sa,
-                          const double* sw, int32_t act, double tol_in, double tol_h, double* y, uint8_t* amb) {
+                          const double* sw, int32_t act, double tol_in, double tol_h, double* y, uint8_t* amb,
+                          double* ymag) {
   if (m->h1 > 1024 || m->h2 > 1024 || m->out > 64 || m->in > 64) return -1;
   const int dims[4] = {m->in, m->h1, m->h2, m->out};
   const float* Ws[3] = {m->W1, m->W2, m->W3};
@@ -386,13 +389,16 @@ int orc_mlp_forward_q_amb(const orc_mlp* m, const double* x, int64_t n, int32_t 
     }
     for (int j = 0; j < m->out; ++j) y[(size_t)k * m->out + j] = a[j];
     if (amb) amb[k] = flag;
+    /* the output layer's sum of absolute terms (and bias), per output */
+    if (ymag)
+      for (int j = 0; j < m->out; ++j) ymag[(size_t)k * m->out + j] = mag[j];
   }
   return 0;
 }
 
 int orc_mlp_forward_q_act(const orc_mlp* m, const double* x, int64_t n, int32_t qmode, const double* sa,
                           const double* sw, int32_t act, double* y) {
-  return orc_mlp_forward_q_amb(m, x, n, qmode, sa, sw, act, 0.0, 0.0, y, NULL);
+  return orc_mlp_forward_q_amb(m, x, n, qmode, sa, sw, act, 0.0, 0.0, y, NULL, NULL);
 }
 
 int orc_mlp_forward_q(const orc_mlp* m, const double* x, int64_t n, int32_t qmode, const double* sa,

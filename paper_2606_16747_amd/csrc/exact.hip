@@ -11,16 +11,16 @@
 //      load instruction covers a contiguous run of the CSR arrays); depths go
 //      to LDS, RGBA stays in the loading lane's registers;
 //   2. each lane ranks its fragments within their list by counting the
-//      smaller keys there, eight per LDS round trip. A key is the depth's
-//      bits (which order valid depths in [0, 1] as numbers) less their four
-//      lowest, under the list's index within the batch, so keys of later
-//      lists are larger and a count over whole 8-key blocks needs no mask;
-//      the pixel lanes first mark every fragment with its list's range, so
-//      no lane searches for its fragment's list;
+//      smaller depths there (depth bits compare as unsigned integers, which
+//      orders valid depths in [0, 1] as numbers), eight per LDS round trip:
+//      in LDS every list is followed by seven guard keys larger than any
+//      depth, so whole 8-key blocks are counted with no mask; the pixel
+//      lanes first mark every fragment with its list's range, so no lane
+//      searches for its fragment's list;
 //   3. each fragment writes its index at its sorted slot and reads it back: a
-//      slot claimed twice means equal keys in a list (equal depths, or
-//      depths within 2^-19 of each other), and only then are the ranks
-//      recounted on the exact (depth, primitive id) for that batch;
+//      slot claimed twice means equal depths in a list, and only then are
+//      the ranks recounted on (depth, primitive id) for that batch, with the
+//      primitive ids read for that batch alone;
 //   4. RGBA is scattered to its sorted slot in LDS and one lane per pixel
 //      walks its list front to back.
 // The transmittance is a compensated FP32 product (value + error term).
@@ -101,12 +101,11 @@ __device__ __forceinline__ void write_pixel(const ExactArgs& a, int p, const Wal
 
 template <bool HALF, bool FSTAR>
 __global__ __launch_bounds__(64) void exact_wave_kernel(ExactArgs a) {
-  // s_key[i]: (list within the batch << 26) | (depth bits >> 4): within a
-  // list the order of the depths (to 2^-19 relative; closer depths compare
-  // equal and go to the exact recount), and every key of a later list (or of
-  // the padding past the batch) larger, so a count over whole 8-key blocks
-  // from a list's start needs no mask
-  __shared__ uint32_t s_key[kCapW + 8];
+  // s_key: the depth bits of list L's fragments at positions start + 7 L, so
+  // every list is followed by seven keys larger than any depth (the batch
+  // holds at most 64 lists): a count over whole 8-key blocks from a list's
+  // start reads no other list's keys and needs no mask
+  __shared__ uint32_t s_key[kCapW + 7 * 64 + 8];
   __shared__ float4 s_c[kCapW];        // list descriptors, then prim ids (recount), then sorted RGBA
   __shared__ uint16_t s_idx[kCapW];    // slot claims
   uint32_t* s_rng = reinterpret_cast<uint32_t*>(s_c);  // [kCapW]: (list << 20) | (start << 10) | end
@@ -153,52 +152,54 @@ __global__ __launch_bounds__(64) void exact_wave_kernel(ExactArgs a) {
         zb[k] = __float_as_uint(a.depth[bcur + i]);
         c[k] = load_rgba<HALF>(a.rgba, bcur + i);
       }
-      // each pixel lane marks its fragments with its list's descriptor
+      // each pixel lane marks its fragments with its list's descriptor and
+      // writes the seven guard keys after its list
       if (mine) {
-        const uint32_t d = ((uint32_t)(l - cur) << 20) | ((uint32_t)s0 << 10) | (uint32_t)(s0 + (int)n);
+        const int lid = l - cur;
+        const uint32_t d = ((uint32_t)lid << 20) | ((uint32_t)s0 << 10) | (uint32_t)(s0 + (int)n);
         for (int t = 0; t < (int)n; ++t) s_rng[s0 + t] = d;
+#pragma unroll
+        for (int g = 0; g < 7; ++g) s_key[s0 + (int)n + 7 * lid + g] = 0xFFFFFFFFu;
       }
-      if (l < 8) s_key[m + l] = 0xFFFFFFFFu;  // padding: larger than every key
       __syncthreads();
-      uint32_t kb[kSlots];
-      int sb[kSlots], se[kSlots], pos[kSlots];
+      int sb[kSlots], se[kSlots], lk[kSlots], pos[kSlots];
 #pragma unroll
       for (int k = 0; k < kSlots; ++k) {
         const int i = l + 64 * k;
-        kb[k] = 0;
-        sb[k] = se[k] = pos[k] = 0;
+        sb[k] = se[k] = lk[k] = pos[k] = 0;
         if (i < m) {
           const uint32_t d = s_rng[i];
           sb[k] = (int)((d >> 10) & 0x3FFu);
           se[k] = (int)(d & 0x3FFu);
-          // depths outside [0, 1] (flagged) take 1's key and the exact recount
-          kb[k] = ((d >> 20) << 26) | (min(zb[k], kOneBits) >> 4);
-          s_key[i] = kb[k];
+          lk[k] = 7 * (int)(d >> 20);  // the list's shift in s_key
+          s_key[i + lk[k]] = zb[k];
           errf |= zb[k] > kOneBits ? STARNT_DERR_DEPTH : 0u;  // negatives, -0 and NaN too
           errf |= (c[k].w >= 0.0f && c[k].w <= 1.0f) ? 0u : STARNT_DERR_ALPHA;
         }
       }
       __syncthreads();  // descriptors read, keys written
-      // 2. ranks: the count of smaller keys from the list's start, eight per
-      // LDS round trip
+      // 2. ranks: the count of smaller depths from the list's start, eight
+      // per LDS round trip (depth bits compare as unsigned integers, which
+      // orders valid depths in [0, 1] as numbers)
 #pragma unroll
       for (int k = 0; k < kSlots; ++k) {
         const int i = l + 64 * k;
         if (i < m) {
           int r = 0;
-          for (int j = sb[k]; j < se[k]; j += 8) {
+          const uint32_t zi = min(zb[k], kOneBits);  // out-of-range depths (flagged) below the guards
+          for (int j = sb[k] + lk[k]; j < se[k] + lk[k]; j += 8) {
             uint32_t v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) v[u] = s_key[j + u];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) r += v[u] < kb[k] ? 1 : 0;
+            for (int u = 0; u < 8; ++u) r += v[u] < zi ? 1 : 0;
           }
           pos[k] = sb[k] + r;
           s_idx[pos[k]] = (uint16_t)i;
         }
       }
       __syncthreads();
-      // 3. every slot claimed once, or equal keys somewhere in the batch:
+      // 3. every slot claimed once, or equal depths somewhere in the batch:
       // then exact ranks on (depth, prim)
       bool clash = false;
 #pragma unroll
@@ -216,7 +217,6 @@ __global__ __launch_bounds__(64) void exact_wave_kernel(ExactArgs a) {
           if (i < m) {
             pr[k] = a.prim[bcur + i];
             s_pr[i] = pr[k];
-            s_key[i] = zb[k];  // the exact depth bits
           }
         }
         __syncthreads();
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(64) void exact_wave_kernel(ExactArgs a) {
             // permutation of the list's slots
             int r = 0;
             for (int j = sb[k]; j < se[k]; ++j) {
-              const uint32_t zj = s_key[j], pj = s_pr[j];
+              const uint32_t zj = s_key[j + lk[k]], pj = s_pr[j];
               r += (zj < zb[k]) | ((zj == zb[k]) & ((pj < pr[k]) | ((pj == pr[k]) & (j < i))));
             }
             pos[k] = sb[k] + r;

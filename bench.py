@@ -85,9 +85,9 @@ PROFILE_SUMMARY = "profiles/features_c2_1080p.md"
 PROFILE_COMMANDS = (
     "rocprofv3 --kernel-trace --stats -d $PROF_DIR/trace -o trace -- "
     "python3 $REPO/bench.py --no-cpu-baseline --calib-copy-mb 512 > $PROF_DIR/trace.json",
-    "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'features_kernel|infer_mfma|copyBuffer' -d $PROF_DIR/fetch -o fetch "
+    "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'features_kernel|infer_mfma|reproject_kernel|exact_wave|copyBuffer' -d $PROF_DIR/fetch -o fetch "
     "-- python3 $REPO/bench.py --no-cpu-baseline --calib-copy-mb 512 > $PROF_DIR/fetch.json",
-    "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex 'features_kernel|infer_mfma|copyBuffer' -d $PROF_DIR/write -o write "
+    "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex 'features_kernel|infer_mfma|reproject_kernel|exact_wave|copyBuffer' -d $PROF_DIR/write -o write "
     "-- python3 $REPO/bench.py --no-cpu-baseline --calib-copy-mb 512 > $PROF_DIR/write.json",
     "python3 $REPO/bench.py --profile-summary $PROF_DIR --calib-copy-mb 512",
 )
@@ -244,6 +244,52 @@ def profile_summary(d, calib_mb):
                   % (ialg, ialg / idur / 1e6, ialg / idur / 1e6 / 8.0),
                   "* FETCH_SIZE %.1f KiB x %.3f = %d B; WRITE_SIZE %.1f KiB x %.3f = %d B; traffic / algorithmic: %.3f"
                   % (float(np.mean(fi)), ffac, int(ifb), float(np.mean(wi)), wfac, int(iwb), (ifb + iwb) / ialg)]
+    # the reprojection gather (interpolated frames of the timed region) and
+    # the exact path (every launch of the run): trace durations and counters
+    def kernel_counters(name, counter, first_start=None, last_end=None):
+        c = db(name)
+        rows = c.execute("select dispatch_id, kernel_name, sum(value) from counters_collection where counter_name = ? "
+                         "group by dispatch_id order by dispatch_id", (counter,)).fetchall()
+        return rows
+
+    extra = {}
+    P1080 = 1920 * 1080
+    for label, pat, alg, where in (
+            ("reproject_kernel", "reproject_kernel", 28 * P1080,
+             "4 B d1 + 12 B gathered colour + 12 B colour out per pixel (no source index)"),
+            ("exact_wave_kernel<false, false> (the exact step's 1080p frames, colour only)",
+             "exact_wave_kernel<false, false>", None,
+             "4 B offsets + 12 B colour out per pixel, 4 B depth + 16 B RGBA per fragment")):
+        tr_rows = con.execute("select dispatch_id, start, duration from kernels where name like ? order by dispatch_id",
+                              ("%" + pat + "%",)).fetchall()
+        if not tr_rows:
+            continue
+        if label == "reproject_kernel":
+            pick = [j for j, (_, st0, _) in enumerate(tr_rows) if t0 <= st0 < t1]
+        else:
+            pick = list(range(len(tr_rows)))  # every launch of that variant is a 1080p exact frame
+        dur = float(np.mean([tr_rows[j][2] for j in pick])) / 1e3
+        fv = [v for _, k, v in kernel_counters("fetch", "FETCH_SIZE") if pat in k]
+        wv = [v for _, k, v in kernel_counters("write", "WRITE_SIZE") if pat in k]
+        fb_ = float(np.mean([fv[j] for j in pick if j < len(fv)])) * 1024 * ffac if fv else None
+        wb_ = float(np.mean([wv[j] for j in pick if j < len(wv)])) * 1024 * wfac if wv else None
+        if alg is None:
+            alg = bench["trace"].get("roofline_exact", {}).get("algorithmic_bytes_per_frame")
+        extra[label] = {"avg_us": round(dur, 2), "launches": len(pick), "algorithmic_bytes_per_launch": alg,
+                        "fetch_bytes_per_launch": int(fb_) if fb_ else None,
+                        "write_bytes_per_launch": int(wb_) if wb_ else None}
+        lines += ["", "## %s (%d launches)" % (label, len(pick)), "",
+                  "* rocprofv3 average duration: %.2f us" % dur,
+                  "* algorithmic bytes per launch: %s (%s)%s" % (alg, where,
+                      "; %.2f TB/s = %.3f of 8 TB/s" % (alg / dur / 1e6, alg / dur / 1e6 / 8.0) if alg else "")]
+        if fb_ and wb_:
+            lines.append("* FETCH_SIZE x %.3f = %d B; WRITE_SIZE x %.3f = %d B; traffic / algorithmic: %s"
+                         % (ffac, int(fb_), wfac, int(wb_), "%.3f" % ((fb_ + wb_) / alg) if alg else "n/a"))
+    if extra:
+        rec["other_kernels"] = extra
+        with open(os.path.join(ROOT, COUNTERS_RECORD), "w") as f:
+            json.dump(rec, f, indent=1)
+            f.write("\n")
     lines.append("")
     with open(os.path.join(ROOT, PROFILE_SUMMARY), "w") as f:
         f.write("\n".join(lines))
@@ -252,8 +298,7 @@ def profile_summary(d, calib_mb):
 
 def cpu_baseline(host, mlp_w, mlp_b, bg, budget_s, nthreads=1):
     """The FP64 oracle on the host over the same sequence (nthreads OpenMP
-    threads in the per-pixel sort, composite and features stage, which
-    dominates; the rest is single-threaded):
+    threads over pixels in every stage but the quadtree update):
     a real frame is the exact sort and over, the tail features, the FP64
     network, the eq (3) composite at full resolution and the quadtree; an
     interpolated frame is the reprojection of the last real one. Frames run in
@@ -284,12 +329,138 @@ def cpu_baseline(host, mlp_w, mlp_b, bg, budget_s, nthreads=1):
             break
     dt = time.perf_counter() - t0
     how = ("single-threaded" if nthreads == 1 else
-           "sort, composite and features on %d OpenMP threads, the rest single-threaded" % nthreads)
+           "sort, composite, features, network, eq (3) and reprojection on %d OpenMP threads (the quadtree "
+           "update single-threaded)" % nthreads)
     return {"value": frags / dt / 1e9, "unit": "Gfrag/s", "cores": nthreads, "kind": "oracle",
             "sample": "%d frames (%d real: sort+over, features, FP64 MLP 16-32-32-3, eq (3), quadtree; %d "
                       "reprojected) of the 1080p sequence in order, %.1f s, %s"
                       % (frames, (frames + 1) // 2, frames // 2, dt, how),
             "ms_per_frame": dt * 1e3 / frames}
+
+
+def sequence_1440p(args):
+    """The 2560x1440 60-frame sequence (4000 static + 500 moving triangles,
+    per-frame seeded rigid motion): the full pipeline (quadtree, reprojection
+    on odd frames, the trained BF16 network) against the exact A-buffer of
+    every frame. The network is trained first on pairs from other seeds of the
+    same scene family (640x360, T2^2-weighted loss). Every frame's fragments
+    are generated and uploaded before its timing starts; a frame's time is the
+    events around its own calls. Prints one JSON object."""
+    import torch
+    import scenegen as sg
+    import paper_2606_16747_amd as st
+    from paper_2606_16747_amd import frames as fm
+    from paper_2606_16747_amd import learn
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    bg = (1.0, 1.0, 1.0)
+    dims = (16, 32, 32, 3)
+    xs, ys, ts = [], [], []
+    for k in range(48):
+        tf = sg.Scene("c5_1440p", seed=sg.BASE_SEED + 5 + 1000 * (k + 1), width=640, height=360).frame(0)
+        x, y, t2 = learn.pairs_from(st.DeviceFrags.from_frame(tf, max_per_pixel=160), bg, with_t2=True)
+        xs.append(x)
+        ys.append(y)
+        ts.append(t2)
+    x, y, t2 = np.concatenate(xs), np.concatenate(ys), np.concatenate(ts)
+    Ws0, bs0 = sg.init_mlp(dims, seed=sg.BASE_SEED + 100, out_bias=0.05)
+    Ws, bs, losses = learn.train(x, y, Ws0, bs0, steps=args.train_steps, batch=65536, dtype=st.BF16,
+                                 weight=t2 ** 2)
+    log("trained on %d pairs, loss %.3e -> %.3e" % (len(x), losses[0], losses[-1]))
+    mlp = st.DeviceMlp(Ws, bs, st.BF16)
+    scene = sg.Scene("c5_1440p")
+    W, H, NF = scene.params.width, scene.params.height, scene.params.num_frames
+    P = W * H
+    rend = fm.Renderer(W, H, mlp, base=64, bg=bg)
+    rend.reset()
+    out_real = torch.empty(P, 3, dtype=torch.float32, device=dev)
+    out_int = torch.empty(P, 3, dtype=torch.float32, device=dev)
+    exact = torch.empty(P, 3, dtype=torch.float32, device=dev)
+    fav = fm.Renderer(W, H, mlp, base=64, bg=bg, mode=st.MODE_FAVG)
+    fav.reset()
+    fav_real = torch.empty(P, 3, dtype=torch.float32, device=dev)
+    fav_int = torch.empty(P, 3, dtype=torch.float32, device=dev)
+    # one untimed frame first: the first launches of each kernel pay one-time
+    # costs (code object load) that are not the pipeline's
+    fr0 = scene.frame(0)
+    df0 = st.DeviceFrags.from_frame(fr0, max_per_pixel=160)
+    rend.real_frame(df0, out_real)
+    fm.exact_frame(df0, exact, bg)
+    fav.real_frame(df0, fav_real)
+    torch.cuda.synchronize()
+    del df0
+    rend.reset()
+    fav.reset()
+    ms, kinds, psnr, psnr_favg, frags_n, ex_ms = [], [], [], [], [], []
+    vp_real = None
+    for t in range(NF):
+        fr = scene.frame(t)
+        df = st.DeviceFrags.from_frame(fr, max_per_pixel=160)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        real = t % 2 == 0
+        mmi = None if real else fm.m_minus_i(vp_real, fr.vp)
+        # the GPU spins first, so the frame's calls are queued before it
+        # reaches them: the events bracket the GPU work, not the host's launches
+        torch.cuda._sleep(2_000_000)
+        a.record()
+        if real:
+            rend.real_frame(df, out_real)
+            o = out_real
+        else:
+            rend.interpolated_frame(mmi, out_int)
+            o = out_int
+        b.record()
+        c = torch.cuda.Event(enable_timing=True)
+        c.record()
+        fm.exact_frame(df, exact, bg)
+        d_ = torch.cuda.Event(enable_timing=True)
+        d_.record()
+        if real:
+            fav.real_frame(df, fav_real)
+            of = fav_real
+            vp_real = fr.vp
+        else:
+            fav.interpolated_frame(mmi, fav_int)
+            of = fav_int
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+        ex_ms.append(c.elapsed_time(d_))
+        kinds.append("R" if real else "i")
+        frags_n.append(fr.num_frags)
+        dd = (o - exact).double()
+        psnr.append(10 * np.log10(1.0 / float((dd * dd).mean())))
+        dd = (of - exact).double()
+        psnr_favg.append(10 * np.log10(1.0 / float((dd * dd).mean())))
+        if t % 10 == 0:
+            log("frame %d (%s): %.3f ms, exact %.3f ms, PSNR %.2f dB (f_avg %.2f)"
+                % (t, kinds[-1], ms[-1], ex_ms[-1], psnr[-1], psnr_favg[-1]))
+    ms_a, ex_a = np.array(ms), np.array(ex_ms)
+    real = np.array([k == "R" for k in kinds])
+    pct = lambda v: {"p50": round(float(np.percentile(v, 50)), 4), "p90": round(float(np.percentile(v, 90)), 4),
+                     "p99": round(float(np.percentile(v, 99)), 4), "mean": round(float(v.mean()), 4)}
+    res = {
+        "workload": "2560x1440, 60 frames, 4000 static + 500 moving seeded triangles, depth complexity mean %.2f "
+                    "max %d; quadtree 64->8 px, reprojection on odd frames, BF16 MLP 16-32-32-3 trained on %d "
+                    "pairs (48 other seeds of the family at 640x360, T2^2-weighted)"
+                    % (float(np.mean([n / P for n in frags_n])), scene.params.max_per_pixel, len(x)),
+        "ms_per_frame": pct(ms_a), "ms_per_frame_real": pct(ms_a[real]), "ms_per_frame_interpolated": pct(ms_a[~real]),
+        "exact_ms_per_frame": pct(ex_a),
+        "speedup_vs_exact_mean": round(float(ex_a.mean() / ms_a.mean()), 3),
+        "gfrag_per_s": round(sum(frags_n) / (ms_a.sum() / 1e3) / 1e9, 2),
+        "psnr_db": {"mean": round(float(np.mean(psnr)), 2), "min": round(float(np.min(psnr)), 2),
+                    "real_mean": round(float(np.mean(np.array(psnr)[real])), 2),
+                    "interpolated_mean": round(float(np.mean(np.array(psnr)[~real])), 2),
+                    "per_frame": [round(v, 2) for v in psnr]},
+        "psnr_db_favg_same_pipeline": {"mean": round(float(np.mean(psnr_favg)), 2),
+                                       "real_mean": round(float(np.mean(np.array(psnr_favg)[real])), 2)},
+        "kinds": "".join(kinds),
+        "train": {"steps": args.train_steps, "pairs": int(len(x)), "loss_first": float(losses[0]),
+                  "loss_last": float(losses[-1])},
+    }
+    print(json.dumps(res), flush=True)
 
 
 def main():
@@ -298,18 +469,23 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--train-steps", type=int, default=8000)
-    ap.add_argument("--train-scenes", type=int, default=512)
+    ap.add_argument("--train-scenes", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ablation", action="store_true", help="skip the ten-feature DFAOIT comparison")
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of single-threaded oracle work for the cpu_baseline sample")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--sequence-1440p", action="store_true",
+                    help="run the 60-frame 2560x1440 sequence with the trained network and exit")
     ap.add_argument("--profile-summary", metavar="DIR", default=None,
                     help="summarise the profiled runs under DIR (no GPU work) and exit")
     args = ap.parse_args()
     if args.profile_summary:
         profile_summary(args.profile_summary, args.calib_copy_mb or 512)
+        return
+    if args.sequence_1440p:
+        sequence_1440p(args)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (--gpus %d refused)" % args.gpus,
@@ -339,29 +515,33 @@ def main():
     frags = [st.DeviceFrags.from_frame(f, max_per_pixel=64) for f in host]
 
     # ---- the network, trained on the GPU by the library ------------------
-    # pairs from many small seeded scenes of the training family (256x256, the
-    # 512x512 scene recipe): material diversity is what makes it generalise
+    # pairs from other seeds of the workload's own scene family (480x270: the
+    # same world scenes at a sixteenth of the pixels), with each pair's squared
+    # error weighted by T2^2 (the composite's error, eq (3))
     dims = (16, 32, 32, 3)
     Ws0, bs0 = sg.init_mlp(dims, seed=sg.BASE_SEED + 100, out_bias=0.05)
-    xs, ys, dxs, dys = [], [], [], []
+    xs, ys, ts, dxs, dys = [], [], [], [], []
     for k in range(args.train_scenes):
-        tf = sg.Scene("c3_512", seed=sg.BASE_SEED + 3 + 1000 * (k + 1), width=256, height=256).frame(0)
-        tdf = st.DeviceFrags.from_frame(tf, max_per_pixel=128)
-        x, y = learn.pairs_from(tdf, bg)
+        tf = sg.Scene("c2_1080p", seed=sg.BASE_SEED + 2 + 1000 * (k + 1), width=480, height=270).frame(0)
+        tdf = st.DeviceFrags.from_frame(tf, max_per_pixel=64)
+        x, y, t2 = learn.pairs_from(tdf, bg, with_t2=True)
         xs.append(x)
         ys.append(y)
+        ts.append(t2)
         if not args.no_ablation:
             x, y = learn.dfa_pairs_from(tdf)
             dxs.append(x)
             dys.append(y)
     x = np.concatenate(xs)
     y = np.concatenate(ys)
+    t2 = np.concatenate(ts)
     if len(x) > 8_000_000:
         pick = np.random.default_rng(0).choice(len(x), 8_000_000, replace=False)
-        x, y = x[pick], y[pick]
+        x, y, t2 = x[pick], y[pick], t2[pick]
     log("training pairs: %d" % len(x))
     tt = time.perf_counter()
-    Ws, bs, losses = learn.train(x, y, Ws0, bs0, steps=args.train_steps, batch=65536, dtype=st.BF16)
+    Ws, bs, losses = learn.train(x, y, Ws0, bs0, steps=args.train_steps, batch=65536, dtype=st.BF16,
+                                 weight=t2 ** 2)
     train_s = time.perf_counter() - tt
     log("trained %d steps in %.2f s, loss %.3e -> %.3e" % (args.train_steps, train_s, losses[0], losses[-1]))
     mlp = st.DeviceMlp(Ws, bs, st.BF16)
@@ -384,6 +564,12 @@ def main():
         fm.exact_frame(frags[t], exact[t], bg)
     torch.cuda.synchronize()
 
+    def psnr_of(a, b):
+        d = (a - b).double()
+        mse = float((d * d).mean())
+        return 10 * np.log10(1.0 / mse) if mse > 0 else 200.0
+
+    real_ts_all = [t for t in range(NF) if t % 2 == 0]
     mmis = [fm.m_minus_i(host[t - 1].vp, host[t].vp) if t % 2 else None for t in range(NF)]
     outs = [torch.empty(P, 3, dtype=torch.float32, device=dev) for _ in range(NF)]
     rend = fm.Renderer(W, H, mlp, base=64, bg=bg)
@@ -403,12 +589,14 @@ def main():
     # grids used by each real frame (deterministic): one untimed pass reading
     # the device schedule before every real frame
     grids = {}
+    scheds = {}
     rend.reset()
     for t in range(NF):
         if t % 2 == 0:
             torch.cuda.synchronize()
             s = st.read_sched(rend.sched)
             grids[t] = (s["w2"], s["h2"], s["w3"], s["h3"])
+            scheds[t] = rend.sched.clone()
             rend.real_frame(frags[t], outs[t])
         else:
             rend.interpolated_frame(mmis[t], outs[t])
@@ -622,6 +810,34 @@ def main():
 
     psnr_favg = mode_psnr(st.MODE_FAVG)
     psnr_f0 = mode_psnr(st.MODE_F0)
+
+    # error budget of the real frames, each on the grids the sequence used and
+    # at full resolution: eq (3) with the exact tail colour f = f* (what is
+    # left is the upscaling of layer 2 and t_tail), with f_avg (no network)
+    # and with the network
+    fbb = st.FeatBuffers(W, H)
+    fst = torch.empty(P, 3, dtype=torch.float32, device=dev)
+    tail_rgb = torch.empty(P, 3, dtype=torch.float32, device=dev)
+    budget = {}
+    for where in ("quadtree_grids", "full_resolution"):
+        vals = {"f_star": [], "f_avg": [], "network": []}
+        for t in real_ts_all:
+            sch = scheds[t] if where == "quadtree_grids" else None
+            fm.exact_frame(frags[t], outs[t], bg, fst)
+            st.starnt_features(frags[t], sch, fbb)
+            st.starnt_composite(frags[t], fbb, fst, sch, bg, st.MODE_LEARNED, outs[t])
+            torch.cuda.synchronize()
+            vals["f_star"].append(psnr_of(outs[t], exact[t]))
+            st.starnt_composite(frags[t], fbb, None, sch, bg, st.MODE_FAVG, outs[t])
+            torch.cuda.synchronize()
+            vals["f_avg"].append(psnr_of(outs[t], exact[t]))
+            st.starnt_infer(mlp, fbb.tail, fbb.count, sch, W, H, tail_rgb)
+            st.starnt_composite(frags[t], fbb, tail_rgb, sch, bg, st.MODE_LEARNED, outs[t])
+            torch.cuda.synchronize()
+            vals["network"].append(psnr_of(outs[t], exact[t]))
+        budget[where] = {k: round(float(np.mean(v)), 2) for k, v in vals.items()}
+    del fbb, fst, tail_rgb
+    log("error budget (real frames, PSNR dB): %s" % budget)
 
     # per-call breakdown (extra steps with events around every call)
     names = {}
@@ -857,6 +1073,7 @@ def main():
 
     total_frags = sum(f.num_frags for f in host)
     value = total_frags / (step_ms / 1e3) / 1e9
+    exact_bytes = sum(4 * (P + 1) + 12 * P + (4 + 4 * f.rgba.dtype.itemsize) * f.num_frags for f in host)
     res = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -882,6 +1099,13 @@ def main():
         "ms_per_frame": round(step_ms / NF, 4),
         "mpixel_per_s": round(P * NF / (step_ms / 1e3) / 1e6, 1),
         "exact_ms_per_frame": round(exact_step_ms / NF, 4),
+        "roofline_exact": {"kernel": "starnt_composite (MODE_EXACT, colour only)", "bound": "hbm",
+                           "achieved": round(exact_bytes / (exact_step_ms / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(exact_bytes / (exact_step_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "algorithmic_bytes_per_frame": int(exact_bytes / NF),
+                           "note": "4 B offsets and 12 B colour out per pixel, 4 B depth and 16 B RGBA per fragment; "
+                                   "over the exact step's event time"},
+        "error_budget_real_frames_psnr_db": budget,
         "exact_gfrag_per_s": round(total_frags / (exact_step_ms / 1e3) / 1e9, 3),
         "speedup_vs_exact": round(exact_step_ms / step_ms, 3),
         "psnr_db": {"min": round(min(psnr), 2), "mean": round(float(np.mean(psnr)), 2),
@@ -944,7 +1168,8 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         res["cpu_baseline"] = cpu_baseline(host, Ws, bs, bg, args.cpu_budget)
-        threads = max(1, min(16, os.cpu_count() or 1))
+        # every core this process may run on (the GPU machine's share)
+        threads = max(1, len(os.sched_getaffinity(0)))
         log("cpu baseline (oracle, %d threads) ..." % threads)
         res["cpu_baseline_threads"] = cpu_baseline(host, Ws, bs, bg, args.cpu_budget, nthreads=threads)
     print(json.dumps(res), flush=True)

@@ -802,6 +802,10 @@ int orc_quadtree(int32_t W, int32_t H, const float* rgb, const uint32_t* N, cons
  */
 int orc_reproject(int32_t W, int32_t H, const float* rgb_r, const float* d1_r, const double* mmi, float* out,
                   int32_t* src, double* margin) {
+  /* rows are independent (out never aliases rgb_r): they run in parallel */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
   for (int32_t py = 0; py < H; ++py)
     for (int32_t px = 0; px < W; ++px) {
       int64_t p = (int64_t)py * W + px;

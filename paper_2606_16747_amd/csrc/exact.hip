@@ -34,6 +34,7 @@ namespace {
 
 constexpr int kCapW = 384;   // fragments per wave batch (main kernel)
 constexpr int kSlots = kCapW / 64;
+constexpr int kWPB = 1;       // waves per block (each works alone; 4 measured slower)
 constexpr int kPB = 256;     // pixels per window (long-list kernel)
 constexpr int kCapL = 2048;  // fragments per LDS batch (long-list kernel)
 constexpr uint32_t kOneBits = 0x3F800000u;  // bits of 1.0f
@@ -99,20 +100,33 @@ __device__ __forceinline__ void write_pixel(const ExactArgs& a, int p, const Wal
   }
 }
 
+// LDS written by some lanes of a wave and read by others: the wave's own
+// ordering point (waves of a block never share data)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <bool HALF, bool FSTAR>
-__global__ __launch_bounds__(64) void exact_wave_kernel(ExactArgs a) {
+__global__ __launch_bounds__(64 * kWPB) void exact_wave_kernel(ExactArgs a) {
   // s_key: the depth bits of list L's fragments at positions start + 7 L, so
   // every list is followed by seven keys larger than any depth (the batch
   // holds at most 64 lists): a count over whole 8-key blocks from a list's
   // start reads no other list's keys and needs no mask
-  __shared__ uint32_t s_key[kCapW + 7 * 64 + 8];
-  __shared__ float4 s_c[kCapW];        // list descriptors, then prim ids (recount), then sorted RGBA
-  __shared__ uint16_t s_idx[kCapW];    // slot claims
+  __shared__ uint32_t s_key_all[kWPB][kCapW + 7 * 64 + 8];
+  __shared__ float4 s_c_all[kWPB][kCapW];        // list descriptors, then prim ids (recount), then sorted RGBA
+  __shared__ uint16_t s_idx_all[kWPB][kCapW];    // slot claims
+  const int wv = (int)(threadIdx.x >> 6);
+  uint32_t* s_key = s_key_all[wv];
+  float4* s_c = s_c_all[wv];
+  uint16_t* s_idx = s_idx_all[wv];
   uint32_t* s_rng = reinterpret_cast<uint32_t*>(s_c);  // [kCapW]: (list << 20) | (start << 10) | end
 
-  const int l = (int)threadIdx.x;
+  const int l = (int)(threadIdx.x & 63);
   const int P = a.W * a.H;
-  const int p0 = (int)blockIdx.x * 64;
+  const int p0 = ((int)blockIdx.x * kWPB + wv) * 64;
+  if (p0 >= P) return;  // a whole wave past the frame
   const int np = min(64, P - p0);
   const int p = p0 + l;
   const bool valid = l < np;
@@ -161,7 +175,7 @@ __global__ __launch_bounds__(64) void exact_wave_kernel(ExactArgs a) {
 #pragma unroll
         for (int g = 0; g < 7; ++g) s_key[s0 + (int)n + 7 * lid + g] = 0xFFFFFFFFu;
       }
-      __syncthreads();
+      wave_sync();
       int sb[kSlots], se[kSlots], lk[kSlots], pos[kSlots];
 #pragma unroll
       for (int k = 0; k < kSlots; ++k) {
@@ -177,7 +191,7 @@ __global__ __launch_bounds__(64) void exact_wave_kernel(ExactArgs a) {
           errf |= (c[k].w >= 0.0f && c[k].w <= 1.0f) ? 0u : STARNT_DERR_ALPHA;
         }
       }
-      __syncthreads();  // descriptors read, keys written
+      wave_sync();  // descriptors read, keys written
       // 2. ranks: the count of smaller depths from the list's start, eight
       // per LDS round trip (depth bits compare as unsigned integers, which
       // orders valid depths in [0, 1] as numbers)
@@ -198,7 +212,7 @@ __global__ __launch_bounds__(64) void exact_wave_kernel(ExactArgs a) {
           s_idx[pos[k]] = (uint16_t)i;
         }
       }
-      __syncthreads();
+      wave_sync();
       // 3. every slot claimed once, or equal depths somewhere in the batch:
       // then exact ranks on (depth, prim)
       bool clash = false;
@@ -219,7 +233,7 @@ __global__ __launch_bounds__(64) void exact_wave_kernel(ExactArgs a) {
             s_pr[i] = pr[k];
           }
         }
-        __syncthreads();
+        wave_sync();
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) {
           const int i = l + 64 * k;
@@ -235,7 +249,7 @@ __global__ __launch_bounds__(64) void exact_wave_kernel(ExactArgs a) {
             pos[k] = sb[k] + r;
           }
         }
-        __syncthreads();  // prim ids are read before RGBA overwrites them
+        wave_sync();  // prim ids are read before RGBA overwrites them
       }
       // 4. RGBA to sorted slots, then one lane per pixel walks its list (the
       // next colour is read before the current one is blended)
@@ -243,7 +257,7 @@ __global__ __launch_bounds__(64) void exact_wave_kernel(ExactArgs a) {
       for (int k = 0; k < kSlots; ++k) {
         if (l + 64 * k < m) s_c[pos[k]] = c[k];
       }
-      __syncthreads();
+      wave_sync();
       if (mine && n > 0) {
         float4 cn = s_c[s0];
         for (int t = 0; t < (int)n; ++t) {
@@ -252,7 +266,7 @@ __global__ __launch_bounds__(64) void exact_wave_kernel(ExactArgs a) {
           walk_step<FSTAR>(w, cc, t >= 2);
         }
       }
-      __syncthreads();  // the next batch reuses the LDS arrays
+      wave_sync();  // the next batch reuses the LDS arrays
     }
     cur = end;
   }
@@ -342,7 +356,7 @@ __global__ __launch_bounds__(256) void exact_long_kernel(ExactArgs a) {
 template <bool HALF, bool FSTAR>
 void launch_exact_t(const ExactArgs& a, bool with_long, hipStream_t s) {
   const int P = a.W * a.H;
-  hipLaunchKernelGGL((exact_wave_kernel<HALF, FSTAR>), dim3((P + 63) / 64), dim3(64), 0, s, a);
+  hipLaunchKernelGGL((exact_wave_kernel<HALF, FSTAR>), dim3((P + 64 * kWPB - 1) / (64 * kWPB)), dim3(64 * kWPB), 0, s, a);
   if (with_long)
     hipLaunchKernelGGL((exact_long_kernel<HALF, FSTAR>), dim3((P + kPB - 1) / kPB), dim3(256), 0, s, a);
 }

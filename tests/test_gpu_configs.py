@@ -424,3 +424,75 @@ def test_config4_quadtree_path(starnt, gpu, sg, oracle_mod, capsys):
         for dt in (starnt.BF16, starnt.FP8):
             _tight_network_check(starnt, oracle_mod, Ws, bs, fb, rend.sched, W, H, x, cnt, px, dt, 1e-6,
                                  "config 4 quadtree grids")
+
+
+def test_config5_trained_network_frames(starnt, gpu, sg, oracle_mod, capsys):
+    """The 1440p sequence with a trained BF16 network (pairs from other seeds
+    of the scene family, T2^2-weighted loss): frames 0-3 through the pipeline
+    (real, reprojected, real on the quadtree's grids, reprojected). On frame 2:
+    the FP32 learned composite on those grids against the oracle on every
+    pixel (1e-4), and the BF16 network on the GPU's own records (upscaled in
+    FP64) against the oracle's bf16-operand forward on 200,000 seeded pixels
+    (the tight bar). Every frame's PSNR against the exact composite is
+    stated; the floors are loose (the 60-frame run is in the bench)."""
+    from paper_2606_16747_amd import frames as fm
+    from paper_2606_16747_amd import learn
+    xs, ys, ts = [], [], []
+    for k in range(6):
+        tf = sg.Scene("c5_1440p", seed=sg.BASE_SEED + 5 + 1000 * (k + 1), width=640, height=360).frame(0)
+        x, y, t2 = learn.pairs_from(starnt.DeviceFrags.from_frame(tf, max_per_pixel=160), with_t2=True)
+        xs.append(x)
+        ys.append(y)
+        ts.append(t2)
+    x, y, t2 = np.concatenate(xs), np.concatenate(ys), np.concatenate(ts)
+    Ws0, bs0 = sg.init_mlp((16, 32, 32, 3), seed=sg.BASE_SEED + 100, out_bias=0.05)
+    Ws, bs, losses = learn.train(x, y, Ws0, bs0, steps=400, batch=65536, dtype=starnt.BF16, weight=t2 ** 2)
+    assert losses[-20:].mean() < 0.5 * losses[:5].mean()
+    sc = sg.Scene("c5_1440p")
+    W, H = sc.params.width, sc.params.height
+    P = W * H
+    rend = fm.Renderer(W, H, starnt.DeviceMlp(Ws, bs, starnt.BF16), base=64)
+    rend.reset()
+    outs = [torch.empty(P, 3, dtype=torch.float32, device="cuda") for _ in range(2)]
+    ex = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+    psnr = []
+    vp_real = None
+    for t in range(4):
+        fr = sc.frame(t)
+        df = starnt.DeviceFrags.from_frame(fr, max_per_pixel=160)
+        if t % 2 == 0:
+            if t == 2:
+                sched = rend.sched.clone()
+                s = starnt.read_sched(sched)
+                grids = (s["w2"], s["h2"], s["w3"], s["h3"])
+            rend.real_frame(df, outs[0])
+            vp_real = fr.vp
+            o = outs[0]
+        else:
+            rend.interpolated_frame(fm.m_minus_i(vp_real, fr.vp), outs[1])
+            o = outs[1]
+        starnt.starnt_composite(df, None, None, None, (1, 1, 1), starnt.MODE_EXACT, ex)
+        sync()
+        d = (to_np(o) - to_np(ex)).astype(np.float64)
+        psnr.append(10 * np.log10(1.0 / (d * d).mean()))
+        if t == 2:
+            fb = rend.feats
+            rgb = torch.empty(P, 3, dtype=torch.float32, device="cuda")
+            starnt.starnt_infer_composite(starnt.DeviceMlp(Ws, bs, starnt.F32), fb, sched, (1, 1, 1), rgb)
+            sync()
+            od = oracle_mod.frame_of(fr, nthreads=16, want=("lay", "tail"))
+            want, _, _ = oracle_mod.learned(od["lay"], od["tail"], W, H, grids, oracle_mod.Mlp(Ws, bs))
+            assert np.abs(to_np(rgb) - want).max() <= TOL
+            w3, h3 = grids[2], grids[3]
+            rec = to_np(fb.tail)[: w3 * h3].astype(np.float64).reshape(h3, w3, 8)[:, :, :5]
+            up = rec.reshape(-1, 5) if (w3, h3) == (W, H) else oracle_mod.upsample(rec, W, H).reshape(-1, 5)
+            px = np.random.default_rng(43).choice(P, 200000, replace=False)
+            xt = np.zeros((len(px), 16))
+            xt[:, :5] = up[px]
+            with capsys.disabled():
+                print("\n[config 5 frame 2] grids %s" % (grids,))
+                _tight_network_check(starnt, oracle_mod, Ws, bs, fb, sched, W, H, xt, to_np(fb.count)[px], px,
+                                     starnt.BF16, 0.0 if (w3, h3) == (W, H) else 1e-6, "config 5 frame 2")
+    with capsys.disabled():
+        print("[config 5, trained BF16 network] PSNR frames 0-3: %s" % ", ".join("%.2f" % v for v in psnr))
+    assert min(psnr[0::2]) > 26.0 and min(psnr[1::2]) > 20.0

@@ -83,34 +83,32 @@ def test_fp8_training_held_out(starnt, gpu, sg, capsys):
 
 def test_config3_training_gain_over_no_network(starnt, gpu, sg, capsys):
     """32 training scenes (512x512, mean depth ~12), 16-64-64-3 in BF16 with
-    FP32 masters, batch 65536. On 8 held-out scenes the trained network is far
-    better than dropping the tail (f = 0) and close to the order-free
-    weighted-average tail f_avg (which needs no network)."""
+    FP32 masters, batch 65536, the T2^2-weighted loss. On 8 held-out scenes
+    the trained network is far better than dropping the tail (f = 0) and than
+    its untrained start, and within 1.5 dB of the order-free weighted-average
+    tail f_avg: the five features carry no order, and f_avg is close to the
+    mean tail colour given them, which bounds what any network on these
+    features can reach (both numbers stated)."""
     from paper_2606_16747_amd import learn
-    xs, ys = [], []
-    for k in range(32):
-        fr = sg.Scene("c3_512", seed=sg.BASE_SEED + 3 + 1000 * (k + 1)).frame(0)
-        x, y = learn.pairs_from(starnt.DeviceFrags.from_frame(fr, max_per_pixel=256))
-        xs.append(x)
-        ys.append(y)
-    x, y = np.concatenate(xs), np.concatenate(ys)
-    pick = np.random.default_rng(0).choice(len(x), min(len(x), 4_000_000), replace=False)
-    x, y = x[pick], y[pick]
+    x, y, t2 = _c3_pairs(starnt, sg)
     Ws0, bs0 = sg.init_mlp((16, 64, 64, 3), seed=sg.BASE_SEED + 100, out_bias=0.05)
-    Ws, bs, losses = learn.train(x, y, Ws0, bs0, steps=1500, lr=2e-3, batch=65536, dtype=starnt.BF16)
+    Ws, bs, losses = learn.train(x, y, Ws0, bs0, steps=1500, lr=2e-3, batch=65536, dtype=starnt.BF16,
+                                 weight=t2 ** 2)
     assert losses[-20:].mean() < 0.25 * losses[:5].mean()
     held = [sg.BASE_SEED + 3 + 77777 * (k + 1) for k in range(8)]
     p_learn, e_learn = _held_out_psnr(starnt, sg, Ws, bs, held, "learned", starnt.BF16)
+    p_f32, _ = _held_out_psnr(starnt, sg, Ws, bs, held, "learned", starnt.F32)
     p_f0, _ = _held_out_psnr(starnt, sg, Ws, bs, held, "f0")
     p_favg, _ = _held_out_psnr(starnt, sg, Ws, bs, held, "favg")
     p_init, _ = _held_out_psnr(starnt, sg, Ws0, bs0, held, "learned", starnt.BF16)
     with capsys.disabled():
-        print("\n[config-3 training] held-out PSNR: learned %.2f dB (max err %.3f), f=0 %.2f, f_avg %.2f, "
-              "untrained %.2f; loss %.3e -> %.3e" % (p_learn, e_learn, p_f0, p_favg, p_init, losses[:5].mean(),
-                                                    losses[-20:].mean()))
+        print("\n[config-3 training] held-out PSNR: learned BF16 %.2f dB (FP32 network %.2f; max err %.3f), "
+              "f=0 %.2f, f_avg %.2f, untrained %.2f; loss %.3e -> %.3e"
+              % (p_learn, p_f32, e_learn, p_f0, p_favg, p_init, losses[:5].mean(), losses[-20:].mean()))
     assert p_learn > p_f0 + 10.0
     assert p_learn > p_init + 5.0
-    assert p_learn > p_favg - 1.5
+    assert abs(p_learn - p_favg) < 1.5
+    assert abs(p_learn - p_f32) < 0.5  # bf16 products against the same network in FP32
 
 
 def test_training_resume_from_checkpoint_is_bitwise(starnt, gpu, sg, oracle_mod):

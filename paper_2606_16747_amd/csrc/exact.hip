@@ -8,8 +8,8 @@
 // is one wave, so no wave waits on another). It takes its pixels in batches
 // of whole lists holding at most kCapW fragments:
 //   1. the batch's fragments are loaded with one lane per fragment (every
-//      load instruction covers a contiguous run of the CSR arrays); depths go
-//      to LDS, RGBA stays in the loading lane's registers;
+//      load instruction covers a contiguous run of the CSR arrays); depths
+//      and RGBA go to LDS in CSR order;
 //   2. each lane ranks its fragments within their list by counting the
 //      smaller depths there (depth bits compare as unsigned integers, which
 //      orders valid depths in [0, 1] as numbers), eight per LDS round trip:
@@ -20,10 +20,16 @@
 //   3. each fragment writes its index at its sorted slot and reads it back: a
 //      slot claimed twice means equal depths in a list, and only then are
 //      the ranks recounted on (depth, primitive id) for that batch, with the
-//      primitive ids read for that batch alone;
-//   4. RGBA is scattered to its sorted slot in LDS and one lane per pixel
-//      walks its list front to back.
-// The transmittance is a compensated FP32 product (value + error term).
+//      primitive ids read for that batch alone; the claims are the sorted
+//      order (RGBA stays in LDS in CSR order, nothing is moved);
+//   4. the walk is split over the lanes: each lane composites six
+//      consecutive sorted slots, closing a partial composite at every list
+//      start, and each pixel lane joins its list's partials in order (the
+//      over operator is associative: (C, T) then (C', T') is
+//      (C + T C', T T')).
+// Inside a batch the transmittance is a plain FP32 product (at most kCapW
+// factors, relative error below 2^-15); the long-list kernel keeps a
+// compensated FP32 product (value + error term).
 // Lists longer than kCapW are left to a block-wide kernel (launched only when
 // the declared maximum list length allows them), which stages up to kCapL
 // fragments of a 256-pixel window in LDS.
@@ -35,6 +41,7 @@ namespace {
 constexpr int kCapW = 384;   // fragments per wave batch (main kernel)
 constexpr int kSlots = kCapW / 64;
 constexpr int kWPB = 1;       // waves per block (each works alone; 4 measured slower)
+constexpr int kKeys = kCapW + 7 * 64 + 8;  // keys, seven guards per list, slack
 constexpr int kPB = 256;     // pixels per window (long-list kernel)
 constexpr int kCapL = 2048;  // fragments per LDS batch (long-list kernel)
 constexpr uint32_t kOneBits = 0x3F800000u;  // bits of 1.0f
@@ -108,20 +115,89 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Composite of a run of sorted slots (over operator, plain FP32: the
+// transmittance of at most kCapW factors stays within 2^-15 relative)
+struct Part {
+  float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.0f;
+  __device__ __forceinline__ void add(float4 c) {
+    const float al = fminf(fmaxf(c.w, 0.0f), 1.0f);
+    const float ta = T * al;
+    C0 = fmaf(ta, c.x, C0);
+    C1 = fmaf(ta, c.y, C1);
+    C2 = fmaf(ta, c.z, C2);
+    T = fmaf(-T, al, T);
+  }
+  __device__ __forceinline__ float4 get() const { return make_float4(C0, C1, C2, T); }
+};
+
+// Slot-claim word: the fragment index in bits 0-8, and at a list's first
+// sorted slot the list's index in the batch in bits 9-14 and bit 15 set
+constexpr uint32_t kIdxMask = 0x1FFu;
+constexpr uint32_t kStartBit = 0x8000u;
+
+// Chunked walk of a batch's sorted slots: lane l composites slots
+// [kSlots l, kSlots l + kSlots), closing a segment at every list start. A
+// chunk's segment before its first list start (the whole chunk if none
+// starts in it) goes to s_part[l]; the segment from a list's start to its
+// end or the chunk's end goes to s_part[64 + list]. TAIL leaves out each
+// list's first two slots (the tail colour).
+template <bool TAIL>
+__device__ __forceinline__ void chunk_walk(const float4* s_c, const uint16_t* s_idx, float4* s_part, int l, int m) {
+  Part pt;
+  int open = -1;
+  const int t0 = kSlots * l;
+  // TAIL: whether the slot before the chunk starts a list (then the chunk's
+  // first slot is its list's second)
+  bool prev_start = TAIL && t0 > 0 && t0 < m && (s_idx[t0 - 1] & kStartBit);
+#pragma unroll
+  for (int u = 0; u < kSlots; ++u) {
+    const int t = t0 + u;
+    if (t < m) {
+      const uint32_t q = s_idx[t];
+      const bool st = (q & kStartBit) != 0;
+      if (st) {
+        s_part[open < 0 ? l : 64 + open] = pt.get();
+        pt = Part();
+        open = (int)((q >> 9) & 63u);
+      }
+      if (!TAIL || !(st || prev_start)) pt.add(s_c[q & kIdxMask]);
+      prev_start = st;
+    }
+  }
+  s_part[open < 0 ? l : 64 + open] = pt.get();
+}
+
+// A list's composite from the chunk partials: its own segment, then the
+// head segment of every later chunk it reaches
+__device__ __forceinline__ float4 list_result(const float4* s_part, int lid, int s0, int n) {
+  float4 r = s_part[64 + lid];
+  const int q2 = (s0 + n - 1) / kSlots;
+  for (int q = s0 / kSlots + 1; q <= q2; ++q) {
+    const float4 h = s_part[q];
+    r.x = fmaf(r.w, h.x, r.x);
+    r.y = fmaf(r.w, h.y, r.y);
+    r.z = fmaf(r.w, h.z, r.z);
+    r.w *= h.w;
+  }
+  return r;
+}
+
 template <bool HALF, bool FSTAR>
 __global__ __launch_bounds__(64 * kWPB) void exact_wave_kernel(ExactArgs a) {
   // s_key: the depth bits of list L's fragments at positions start + 7 L, so
   // every list is followed by seven keys larger than any depth (the batch
   // holds at most 64 lists): a count over whole 8-key blocks from a list's
-  // start reads no other list's keys and needs no mask
-  __shared__ uint32_t s_key_all[kWPB][kCapW + 7 * 64 + 8];
-  __shared__ float4 s_c_all[kWPB][kCapW];        // list descriptors, then prim ids (recount), then sorted RGBA
-  __shared__ uint16_t s_idx_all[kWPB][kCapW];    // slot claims
+  // start reads no other list's keys and needs no mask. After the ranking it
+  // holds the chunk partials of the walk.
+  __shared__ __align__(16) uint32_t s_key_all[kWPB][kKeys];
+  __shared__ float4 s_c_all[kWPB][kCapW];        // list descriptors, then RGBA in CSR order (prim ids in a recount)
+  __shared__ uint16_t s_idx_all[kWPB][kCapW];    // slot claims: the sorted order
   const int wv = (int)(threadIdx.x >> 6);
   uint32_t* s_key = s_key_all[wv];
   float4* s_c = s_c_all[wv];
   uint16_t* s_idx = s_idx_all[wv];
   uint32_t* s_rng = reinterpret_cast<uint32_t*>(s_c);  // [kCapW]: (list << 20) | (start << 10) | end
+  float4* s_part = reinterpret_cast<float4*>(s_key);   // [128] chunk and list partials
 
   const int l = (int)(threadIdx.x & 63);
   const int P = a.W * a.H;
@@ -177,21 +253,28 @@ __global__ __launch_bounds__(64 * kWPB) void exact_wave_kernel(ExactArgs a) {
       }
       wave_sync();
       int sb[kSlots], se[kSlots], lk[kSlots], pos[kSlots];
+      uint32_t fl[kSlots];  // the claim word's list-start bits (when the fragment sorts first)
 #pragma unroll
       for (int k = 0; k < kSlots; ++k) {
         const int i = l + 64 * k;
         sb[k] = se[k] = lk[k] = pos[k] = 0;
+        fl[k] = 0;
         if (i < m) {
           const uint32_t d = s_rng[i];
           sb[k] = (int)((d >> 10) & 0x3FFu);
           se[k] = (int)(d & 0x3FFu);
           lk[k] = 7 * (int)(d >> 20);  // the list's shift in s_key
+          fl[k] = kStartBit | ((d >> 20) << 9);
           s_key[i + lk[k]] = zb[k];
           errf |= zb[k] > kOneBits ? STARNT_DERR_DEPTH : 0u;  // negatives, -0 and NaN too
           errf |= (c[k].w >= 0.0f && c[k].w <= 1.0f) ? 0u : STARNT_DERR_ALPHA;
         }
       }
       wave_sync();  // descriptors read, keys written
+      // RGBA to LDS in CSR order (lanes past the batch repeat its last
+      // fragment, the same value to the same place)
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k) s_c[min(l + 64 * k, m - 1)] = c[k];
       // 2. ranks: the count of smaller depths from the list's start, eight
       // per LDS round trip (depth bits compare as unsigned integers, which
       // orders valid depths in [0, 1] as numbers)
@@ -209,20 +292,22 @@ __global__ __launch_bounds__(64 * kWPB) void exact_wave_kernel(ExactArgs a) {
             for (int u = 0; u < 8; ++u) r += v[u] < zi ? 1 : 0;
           }
           pos[k] = sb[k] + r;
-          s_idx[pos[k]] = (uint16_t)i;
+          s_idx[pos[k]] = (uint16_t)(i | (r == 0 ? fl[k] : 0u));
         }
       }
       wave_sync();
       // 3. every slot claimed once, or equal depths somewhere in the batch:
-      // then exact ranks on (depth, prim)
+      // then exact ranks on (depth, prim), and the claims written again
       bool clash = false;
 #pragma unroll
       for (int k = 0; k < kSlots; ++k) {
         const int i = l + 64 * k;
-        if (i < m) clash |= s_idx[pos[k]] != (uint16_t)i;
+        if (i < m) clash |= (s_idx[pos[k]] & kIdxMask) != (uint32_t)i;
       }
       if (__builtin_amdgcn_ballot_w64(clash)) {
-        uint32_t* s_pr = reinterpret_cast<uint32_t*>(s_c);
+        // prim ids beside the colours: s_c holds kCapW float4, the ids take
+        // the words after the first kCapW
+        uint32_t* s_pr = reinterpret_cast<uint32_t*>(s_c) + 3 * kCapW;
         uint32_t pr[kSlots];
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) {
@@ -249,21 +334,38 @@ __global__ __launch_bounds__(64 * kWPB) void exact_wave_kernel(ExactArgs a) {
             pos[k] = sb[k] + r;
           }
         }
-        wave_sync();  // prim ids are read before RGBA overwrites them
-      }
-      // 4. RGBA to sorted slots, then one lane per pixel walks its list (the
-      // next colour is read before the current one is blended)
+        // the colours the prim ids displaced, read again
+        float4 cr[kSlots];
 #pragma unroll
-      for (int k = 0; k < kSlots; ++k) {
-        if (l + 64 * k < m) s_c[pos[k]] = c[k];
+        for (int k = 0; k < kSlots; ++k) cr[k] = load_rgba<HALF>(a.rgba, bcur + min(l + 64 * k, m - 1));
+        wave_sync();  // keys and prim ids read before the colours are restored
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) {
+          const int i = l + 64 * k;
+          s_c[min(i, m - 1)] = cr[k];
+          if (i < m) s_idx[pos[k]] = (uint16_t)(i | (pos[k] == sb[k] ? fl[k] : 0u));
+        }
       }
+      wave_sync();  // claims final, keys no longer read
+      // 4. the walk: chunk partials, then each pixel lane combines its list's
+      chunk_walk<false>(s_c, s_idx, s_part, l, m);
       wave_sync();
       if (mine && n > 0) {
-        float4 cn = s_c[s0];
-        for (int t = 0; t < (int)n; ++t) {
-          const float4 cc = cn;
-          if (t + 1 < (int)n) cn = s_c[s0 + t + 1];
-          walk_step<FSTAR>(w, cc, t >= 2);
+        const float4 r = list_result(s_part, l - cur, s0, (int)n);
+        w.C0 = r.x;
+        w.C1 = r.y;
+        w.C2 = r.z;
+        w.th = r.w;
+      }
+      if (FSTAR) {
+        wave_sync();  // colour partials read before the tail's overwrite them
+        chunk_walk<true>(s_c, s_idx, s_part, l, m);
+        wave_sync();
+        if (mine && n > 0) {
+          const float4 r = list_result(s_part, l - cur, s0, (int)n);
+          w.F0 = r.x;
+          w.F1 = r.y;
+          w.F2 = r.z;
         }
       }
       wave_sync();  // the next batch reuses the LDS arrays

@@ -4,9 +4,11 @@
 // This is the ground truth the learned path is judged against, the source of
 // training targets, and the baseline it must beat on time.
 //
-// Main kernel: one wave owns 64 consecutive pixels and works alone (a block
+// Main kernel: one wave owns PIX consecutive pixels and works alone (a block
 // is one wave, so no wave waits on another). It takes its pixels in batches
-// of whole lists holding at most kCapW fragments:
+// of whole lists holding at most CAP fragments (two configurations: 192
+// fragments for 32 pixels when the declared maximum list fits, else 384 for
+// 48):
 //   1. the batch's fragments are loaded with one lane per fragment (every
 //      load instruction covers a contiguous run of the CSR arrays); depths
 //      and RGBA go to LDS in CSR order;
@@ -22,15 +24,15 @@
 //      the ranks recounted on (depth, primitive id) for that batch, with the
 //      primitive ids read for that batch alone; the claims are the sorted
 //      order (RGBA stays in LDS in CSR order, nothing is moved);
-//   4. the walk is split over the lanes: each lane composites six
+//   4. the walk is split over the lanes: each lane composites CAP / 64
 //      consecutive sorted slots, closing a partial composite at every list
 //      start, and each pixel lane joins its list's partials in order (the
 //      over operator is associative: (C, T) then (C', T') is
 //      (C + T C', T T')).
-// Inside a batch the transmittance is a plain FP32 product (at most kCapW
+// Inside a batch the transmittance is a plain FP32 product (at most CAP
 // factors, relative error below 2^-15); the long-list kernel keeps a
 // compensated FP32 product (value + error term).
-// Lists longer than kCapW are left to a block-wide kernel (launched only when
+// Lists longer than CAP are left to a block-wide kernel (launched only when
 // the declared maximum list length allows them), which stages up to kCapL
 // fragments of a 256-pixel window in LDS.
 #include "internal.h"
@@ -38,10 +40,23 @@
 namespace starnt {
 namespace {
 
-constexpr int kCapW = 384;   // fragments per wave batch (main kernel)
-constexpr int kSlots = kCapW / 64;
-constexpr int kWPB = 1;       // waves per block (each works alone; 4 measured slower)
-constexpr int kKeys = kCapW + 7 * 64 + 8;  // keys, seven guards per list, slack
+// Main-kernel configurations: a wave owns PIX consecutive pixels and takes
+// batches of at most CAP fragments. Small batches keep LDS and registers low
+// (more waves per CU hide more latency); the larger one keeps lists up to
+// 384 fragments out of the long-list kernel.
+template <int CAP, int PIX>
+struct WaveCfg {
+  static constexpr int kCap = CAP;
+  static constexpr int kPix = PIX;
+  static constexpr int kSlots = CAP / 64;  // fragments per lane in a batch
+  // keys, seven guards per list and slack; the walk's partials (64 chunks
+  // and PIX lists, four words each) reuse the same words
+  static constexpr int kKeys = (CAP + 7 * PIX + 8) > 4 * (64 + PIX) ? (CAP + 7 * PIX + 8) : 4 * (64 + PIX);
+  static_assert(CAP % 64 == 0 && CAP <= 512 && PIX <= 64, "batch words hold 9-bit indices, 6-bit lists");
+};
+using CfgSmall = WaveCfg<192, 32>;  // lists up to 192 fragments
+using CfgLarge = WaveCfg<384, 48>;  // lists up to 384 fragments
+constexpr int kWPB = 1;             // waves per block (each works alone; 4 measured slower)
 constexpr int kPB = 256;     // pixels per window (long-list kernel)
 constexpr int kCapL = 2048;  // fragments per LDS batch (long-list kernel)
 constexpr uint32_t kOneBits = 0x3F800000u;  // bits of 1.0f
@@ -116,7 +131,7 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Composite of a run of sorted slots (over operator, plain FP32: the
-// transmittance of at most kCapW factors stays within 2^-15 relative)
+// transmittance of at most 384 factors stays within 2^-15 relative)
 struct Part {
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.0f;
   __device__ __forceinline__ void add(float4 c) {
@@ -141,7 +156,7 @@ constexpr uint32_t kStartBit = 0x8000u;
 // starts in it) goes to s_part[l]; the segment from a list's start to its
 // end or the chunk's end goes to s_part[64 + list]. TAIL leaves out each
 // list's first two slots (the tail colour).
-template <bool TAIL>
+template <int kSlots, bool TAIL>
 __device__ __forceinline__ void chunk_walk(const float4* s_c, const uint16_t* s_idx, float4* s_part, int l, int m) {
   Part pt;
   int open = -1;
@@ -169,6 +184,7 @@ __device__ __forceinline__ void chunk_walk(const float4* s_c, const uint16_t* s_
 
 // A list's composite from the chunk partials: its own segment, then the
 // head segment of every later chunk it reaches
+template <int kSlots>
 __device__ __forceinline__ float4 list_result(const float4* s_part, int lid, int s0, int n) {
   float4 r = s_part[64 + lid];
   const int q2 = (s0 + n - 1) / kSlots;
@@ -182,8 +198,11 @@ __device__ __forceinline__ float4 list_result(const float4* s_part, int lid, int
   return r;
 }
 
-template <bool HALF, bool FSTAR>
+template <class Cfg, bool HALF, bool FSTAR>
 __global__ __launch_bounds__(64 * kWPB) void exact_wave_kernel(ExactArgs a) {
+  constexpr int kCapW = Cfg::kCap;
+  constexpr int kSlots = Cfg::kSlots;
+  constexpr int kKeys = Cfg::kKeys;
   // s_key: the depth bits of list L's fragments at positions start + 7 L, so
   // every list is followed by seven keys larger than any depth (the batch
   // holds at most 64 lists): a count over whole 8-key blocks from a list's
@@ -192,7 +211,7 @@ __global__ __launch_bounds__(64 * kWPB) void exact_wave_kernel(ExactArgs a) {
   __shared__ __align__(16) uint32_t s_key_all[kWPB][kKeys];
   __shared__ float4 s_c_all[kWPB][kCapW];        // list descriptors, then RGBA in CSR order (prim ids in a recount)
   __shared__ uint16_t s_idx_all[kWPB][kCapW];    // slot claims: the sorted order
-  const int wv = (int)(threadIdx.x >> 6);
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // one value per wave
   uint32_t* s_key = s_key_all[wv];
   float4* s_c = s_c_all[wv];
   uint16_t* s_idx = s_idx_all[wv];
@@ -201,9 +220,9 @@ __global__ __launch_bounds__(64 * kWPB) void exact_wave_kernel(ExactArgs a) {
 
   const int l = (int)(threadIdx.x & 63);
   const int P = a.W * a.H;
-  const int p0 = ((int)blockIdx.x * kWPB + wv) * 64;
+  const int p0 = ((int)blockIdx.x * kWPB + wv) * Cfg::kPix;
   if (p0 >= P) return;  // a whole wave past the frame
-  const int np = min(64, P - p0);
+  const int np = min(Cfg::kPix, P - p0);
   const int p = p0 + l;
   const bool valid = l < np;
   const uint32_t b = a.off[valid ? p : P];
@@ -348,10 +367,10 @@ __global__ __launch_bounds__(64 * kWPB) void exact_wave_kernel(ExactArgs a) {
       }
       wave_sync();  // claims final, keys no longer read
       // 4. the walk: chunk partials, then each pixel lane combines its list's
-      chunk_walk<false>(s_c, s_idx, s_part, l, m);
+      chunk_walk<kSlots, false>(s_c, s_idx, s_part, l, m);
       wave_sync();
       if (mine && n > 0) {
-        const float4 r = list_result(s_part, l - cur, s0, (int)n);
+        const float4 r = list_result<kSlots>(s_part, l - cur, s0, (int)n);
         w.C0 = r.x;
         w.C1 = r.y;
         w.C2 = r.z;
@@ -359,10 +378,10 @@ __global__ __launch_bounds__(64 * kWPB) void exact_wave_kernel(ExactArgs a) {
       }
       if (FSTAR) {
         wave_sync();  // colour partials read before the tail's overwrite them
-        chunk_walk<true>(s_c, s_idx, s_part, l, m);
+        chunk_walk<kSlots, true>(s_c, s_idx, s_part, l, m);
         wave_sync();
         if (mine && n > 0) {
-          const float4 r = list_result(s_part, l - cur, s0, (int)n);
+          const float4 r = list_result<kSlots>(s_part, l - cur, s0, (int)n);
           w.F0 = r.x;
           w.F1 = r.y;
           w.F2 = r.z;
@@ -381,7 +400,7 @@ __global__ __launch_bounds__(64 * kWPB) void exact_wave_kernel(ExactArgs a) {
 // staged in LDS in batches of at most kCapL with coalesced loads, each
 // fragment's rank within its list is counted there on the full key, the rank
 // scatters it into sorted order, and one thread per long pixel walks its list.
-template <bool HALF, bool FSTAR>
+template <int kCapW, bool HALF, bool FSTAR>
 __global__ __launch_bounds__(256) void exact_long_kernel(ExactArgs a) {
   __shared__ uint32_t s_off[kPB + 1];
   __shared__ float s_z[kCapL];
@@ -455,12 +474,22 @@ __global__ __launch_bounds__(256) void exact_long_kernel(ExactArgs a) {
   if (errf && a.err) atomicOr(a.err, errf);
 }
 
-template <bool HALF, bool FSTAR>
-void launch_exact_t(const ExactArgs& a, bool with_long, hipStream_t s) {
+template <class Cfg, bool HALF, bool FSTAR>
+void launch_exact_c(const ExactArgs& a, uint32_t max_n, hipStream_t s) {
   const int P = a.W * a.H;
-  hipLaunchKernelGGL((exact_wave_kernel<HALF, FSTAR>), dim3((P + 64 * kWPB - 1) / (64 * kWPB)), dim3(64 * kWPB), 0, s, a);
-  if (with_long)
-    hipLaunchKernelGGL((exact_long_kernel<HALF, FSTAR>), dim3((P + kPB - 1) / kPB), dim3(256), 0, s, a);
+  const int waves = (P + Cfg::kPix - 1) / Cfg::kPix;
+  hipLaunchKernelGGL((exact_wave_kernel<Cfg, HALF, FSTAR>), dim3((waves + kWPB - 1) / kWPB), dim3(64 * kWPB), 0, s,
+                     a);
+  // the long-list kernel only where the declared maximum allows such lists
+  if (max_n > (uint32_t)Cfg::kCap)
+    hipLaunchKernelGGL((exact_long_kernel<Cfg::kCap, HALF, FSTAR>), dim3((P + kPB - 1) / kPB), dim3(256), 0, s, a);
+}
+
+// The small configuration when every list fits its batches, else the large
+template <bool HALF, bool FSTAR>
+void launch_exact_t(const ExactArgs& a, uint32_t max_n, hipStream_t s) {
+  if (max_n <= (uint32_t)CfgSmall::kCap) launch_exact_c<CfgSmall, HALF, FSTAR>(a, max_n, s);
+  else launch_exact_c<CfgLarge, HALF, FSTAR>(a, max_n, s);
 }
 
 }  // namespace
@@ -483,15 +512,13 @@ int launch_exact(const starnt_frags& f, const float bg[3], float* rgb, float* fs
   a.rgb = rgb;
   a.fstar = fstar;
   a.err = err;
-  // the long-list kernel only where the declared maximum allows such lists
-  const bool with_long = f.max_per_pixel > (uint32_t)kCapW;
   const bool half = f.rgba_dtype == STARNT_F16;
   if (half) {
-    if (fstar) launch_exact_t<true, true>(a, with_long, s);
-    else launch_exact_t<true, false>(a, with_long, s);
+    if (fstar) launch_exact_t<true, true>(a, f.max_per_pixel, s);
+    else launch_exact_t<true, false>(a, f.max_per_pixel, s);
   } else {
-    if (fstar) launch_exact_t<false, true>(a, with_long, s);
-    else launch_exact_t<false, false>(a, with_long, s);
+    if (fstar) launch_exact_t<false, true>(a, f.max_per_pixel, s);
+    else launch_exact_t<false, false>(a, f.max_per_pixel, s);
   }
   STARNT_LAUNCH_CHECK("starnt_composite (exact) launch");
   return STARNT_OK;

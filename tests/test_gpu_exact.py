@@ -1,8 +1,9 @@
 """Exact A-buffer path against the FP64 oracle at the shapes its kernels
-split on: lists at and around the per-wave batch capacity (384 fragments),
-runs of long lists next to short ones, equal depths inside short and long
-lists, waves whose pixels are all empty, and the call without the tail
-output. Bar: <= 1e-4 per channel against FP64 (eq (1), the A-buffer of
+split on: lists at and around the per-wave batch capacities (192 fragments
+for 32-pixel waves when the declared maximum allows, 384 for 48-pixel waves
+otherwise), runs of long lists next to short ones, equal depths inside short
+and long lists, waves whose pixels are all empty, and the call without the
+tail output. Bar: <= 1e-4 per channel against FP64 (eq (1), the A-buffer of
 Sec. 4); the colour is bitwise the same with and without the tail output
 and under permutation of every list."""
 import numpy as np
@@ -63,6 +64,38 @@ def test_exact_lists_around_the_batch_capacity(starnt, gpu, oracle_mod, seed):
     lengths[64 + 8] = 384
     lengths[128:192] = 0  # a wave of empty pixels
     _check(starnt, oracle_mod, _lists(rng, lengths), W, H, 1024)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_exact_small_batches_around_their_capacity(starnt, gpu, oracle_mod, seed):
+    """Declared maximum 192: 32-pixel waves with batches of at most 192
+    fragments. Lists at and below the capacity, waves whose lists need
+    several batches, a wave of empty pixels, a frame that is not a whole
+    number of waves."""
+    rng = np.random.default_rng(20 + seed)
+    W, H = 61, 3
+    lengths = rng.choice([0, 1, 2, 3, 9, 40, 96, 150], size=W * H)
+    lengths[0] = 192
+    lengths[1:4] = (191, 192, 1)
+    lengths[31] = 192  # last lane of the first wave
+    lengths[32:64] = 0  # a wave of empty pixels
+    lengths[64:70] = (100, 100, 100, 100, 100, 100)  # one list per batch
+    lengths[-1] = 192
+    _check(starnt, oracle_mod, _lists(rng, lengths), W, H, 192)
+
+
+def test_exact_small_batches_with_ties(starnt, gpu, oracle_mod):
+    """The recount on (depth, prim) in the small configuration, and the same
+    outputs under permutation of every list."""
+    rng = np.random.default_rng(9)
+    W, H = 45, 2
+    lengths = rng.choice([0, 2, 5, 17, 64, 180], size=W * H)
+    lists = _lists(rng, lengths, ties_every=3)
+    csr, rgb, fstar = _check(starnt, oracle_mod, lists, W, H, 192)
+    perm = [[l[k] for k in rng.permutation(len(l))] for l in lists]
+    df2 = starnt.DeviceFrags(*make_csr(perm, W, H), W, H, 192)
+    rgb2, fstar2 = run_exact(starnt, df2, bg=(0.3, 0.6, 0.9))
+    assert np.array_equal(rgb, rgb2) and np.array_equal(fstar, fstar2)
 
 
 def test_exact_ties_in_short_and_long_lists(starnt, gpu, oracle_mod):

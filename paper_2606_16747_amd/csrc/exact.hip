@@ -203,19 +203,19 @@ __global__ __launch_bounds__(64 * kWPB) void exact_wave_kernel(ExactArgs a) {
   constexpr int kCapW = Cfg::kCap;
   constexpr int kSlots = Cfg::kSlots;
   constexpr int kKeys = Cfg::kKeys;
-  // s_key: the depth bits of list L's fragments at positions start + 7 L, so
-  // every list is followed by seven keys larger than any depth (the batch
-  // holds at most 64 lists): a count over whole 8-key blocks from a list's
-  // start reads no other list's keys and needs no mask. After the ranking it
-  // holds the chunk partials of the walk.
+  // s_key: first the list descriptor of each fragment, (list << 20) | (start
+  // << 10) | end; then the depth bits of list L's fragments at positions
+  // start + 7 L, so every list is followed by seven keys larger than any
+  // depth (the batch holds at most 64 lists): a count over whole 8-key
+  // blocks from a list's start reads no other list's keys and needs no mask.
+  // After the ranking it holds the chunk partials of the walk.
   __shared__ __align__(16) uint32_t s_key_all[kWPB][kKeys];
-  __shared__ float4 s_c_all[kWPB][kCapW];        // list descriptors, then RGBA in CSR order (prim ids in a recount)
+  __shared__ float4 s_c_all[kWPB][kCapW];        // RGBA in CSR order (prim ids in a recount)
   __shared__ uint16_t s_idx_all[kWPB][kCapW];    // slot claims: the sorted order
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // one value per wave
   uint32_t* s_key = s_key_all[wv];
   float4* s_c = s_c_all[wv];
   uint16_t* s_idx = s_idx_all[wv];
-  uint32_t* s_rng = reinterpret_cast<uint32_t*>(s_c);  // [kCapW]: (list << 20) | (start << 10) | end
   float4* s_part = reinterpret_cast<float4*>(s_key);   // [128] chunk and list partials
 
   const int l = (int)(threadIdx.x & 63);
@@ -261,14 +261,18 @@ __global__ __launch_bounds__(64 * kWPB) void exact_wave_kernel(ExactArgs a) {
         zb[k] = __float_as_uint(a.depth[bcur + i]);
         c[k] = load_rgba<HALF>(a.rgba, bcur + i);
       }
-      // each pixel lane marks its fragments with its list's descriptor and
-      // writes the seven guard keys after its list
+      // each pixel lane marks its fragments with its list's descriptor (in
+      // the key words, read before any key is written); RGBA goes to LDS in
+      // CSR order as it arrives (lanes past the batch repeat its last
+      // fragment, the same value to the same place)
       if (mine) {
-        const int lid = l - cur;
-        const uint32_t d = ((uint32_t)lid << 20) | ((uint32_t)s0 << 10) | (uint32_t)(s0 + (int)n);
-        for (int t = 0; t < (int)n; ++t) s_rng[s0 + t] = d;
+        const uint32_t d = ((uint32_t)(l - cur) << 20) | ((uint32_t)s0 << 10) | (uint32_t)(s0 + (int)n);
+        for (int t = 0; t < (int)n; ++t) s_key[s0 + t] = d;
+      }
 #pragma unroll
-        for (int g = 0; g < 7; ++g) s_key[s0 + (int)n + 7 * lid + g] = 0xFFFFFFFFu;
+      for (int k = 0; k < kSlots; ++k) {
+        errf |= (l + 64 * k < m && !(c[k].w >= 0.0f && c[k].w <= 1.0f)) ? STARNT_DERR_ALPHA : 0u;
+        s_c[min(l + 64 * k, m - 1)] = c[k];
       }
       wave_sync();
       int sb[kSlots], se[kSlots], lk[kSlots], pos[kSlots];
@@ -279,21 +283,24 @@ __global__ __launch_bounds__(64 * kWPB) void exact_wave_kernel(ExactArgs a) {
         sb[k] = se[k] = lk[k] = pos[k] = 0;
         fl[k] = 0;
         if (i < m) {
-          const uint32_t d = s_rng[i];
+          const uint32_t d = s_key[i];
           sb[k] = (int)((d >> 10) & 0x3FFu);
           se[k] = (int)(d & 0x3FFu);
           lk[k] = 7 * (int)(d >> 20);  // the list's shift in s_key
           fl[k] = kStartBit | ((d >> 20) << 9);
-          s_key[i + lk[k]] = zb[k];
           errf |= zb[k] > kOneBits ? STARNT_DERR_DEPTH : 0u;  // negatives, -0 and NaN too
-          errf |= (c[k].w >= 0.0f && c[k].w <= 1.0f) ? 0u : STARNT_DERR_ALPHA;
         }
       }
-      wave_sync();  // descriptors read, keys written
-      // RGBA to LDS in CSR order (lanes past the batch repeat its last
-      // fragment, the same value to the same place)
+      wave_sync();  // descriptors read before keys overwrite them
+      // keys, and the seven guard keys after every list
 #pragma unroll
-      for (int k = 0; k < kSlots; ++k) s_c[min(l + 64 * k, m - 1)] = c[k];
+      for (int k = 0; k < kSlots; ++k)
+        if (l + 64 * k < m) s_key[l + 64 * k + lk[k]] = zb[k];
+      if (mine) {
+#pragma unroll
+        for (int g = 0; g < 7; ++g) s_key[s0 + (int)n + 7 * (l - cur) + g] = 0xFFFFFFFFu;
+      }
+      wave_sync();  // keys written
       // 2. ranks: the count of smaller depths from the list's start, eight
       // per LDS round trip (depth bits compare as unsigned integers, which
       // orders valid depths in [0, 1] as numbers)

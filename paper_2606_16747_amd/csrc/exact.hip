@@ -6,9 +6,8 @@
 //
 // Main kernel: one wave owns PIX consecutive pixels and works alone (a block
 // is one wave, so no wave waits on another). It takes its pixels in batches
-// of whole lists holding at most CAP fragments (two configurations: 192
-// fragments for 32 pixels when the declared maximum list fits, else 384 for
-// 48):
+// of whole lists holding at most CAP fragments (16 pixels; CAP 192, 256 or
+// 384, the smallest that holds the declared maximum list length):
 //   1. the batch's fragments are loaded with one lane per fragment (every
 //      load instruction covers a contiguous run of the CSR arrays); depths
 //      and RGBA go to LDS in CSR order;
@@ -41,9 +40,13 @@ namespace starnt {
 namespace {
 
 // Main-kernel configurations: a wave owns PIX consecutive pixels and takes
-// batches of at most CAP fragments. Small batches keep LDS and registers low
-// (more waves per CU hide more latency); the larger one keeps lists up to
-// 384 fragments out of the long-list kernel.
+// batches of at most CAP fragments. The launch takes the smallest CAP that
+// holds the declared maximum list length: small batches keep LDS and
+// registers low (more waves per CU hide more latency), larger ones keep
+// longer lists out of the much slower long-list kernel. Measured per frame:
+// 1080p (mean 8, max 64) 126 us at <192, 16> against 142 us at <192, 32>;
+// 4K (mean 16, max 256) 1.71 ms at <256, 16>, 1.98 ms at <384, 16> and 3.4
+// ms at <384, 48>; 16-pixel waves were also faster than 8, 12, 20 or 24.
 template <int CAP, int PIX>
 struct WaveCfg {
   static constexpr int kCap = CAP;
@@ -54,8 +57,9 @@ struct WaveCfg {
   static constexpr int kKeys = (CAP + 7 * PIX + 8) > 4 * (64 + PIX) ? (CAP + 7 * PIX + 8) : 4 * (64 + PIX);
   static_assert(CAP % 64 == 0 && CAP <= 512 && PIX <= 64, "batch words hold 9-bit indices, 6-bit lists");
 };
-using CfgSmall = WaveCfg<192, 32>;  // lists up to 192 fragments
-using CfgLarge = WaveCfg<384, 48>;  // lists up to 384 fragments
+using CfgSmall = WaveCfg<192, 16>;  // lists up to 192 fragments
+using CfgMid = WaveCfg<256, 16>;    // up to 256
+using CfgLarge = WaveCfg<384, 16>;  // up to 384 (longer ones: the long-list kernel)
 constexpr int kWPB = 1;             // waves per block (each works alone; 4 measured slower)
 constexpr int kPB = 256;     // pixels per window (long-list kernel)
 constexpr int kCapL = 2048;  // fragments per LDS batch (long-list kernel)
@@ -488,14 +492,19 @@ void launch_exact_c(const ExactArgs& a, uint32_t max_n, hipStream_t s) {
   hipLaunchKernelGGL((exact_wave_kernel<Cfg, HALF, FSTAR>), dim3((waves + kWPB - 1) / kWPB), dim3(64 * kWPB), 0, s,
                      a);
   // the long-list kernel only where the declared maximum allows such lists
-  if (max_n > (uint32_t)Cfg::kCap)
-    hipLaunchKernelGGL((exact_long_kernel<Cfg::kCap, HALF, FSTAR>), dim3((P + kPB - 1) / kPB), dim3(256), 0, s, a);
+  // (only the largest configuration leaves any)
+  if constexpr (Cfg::kCap == CfgLarge::kCap) {
+    if (max_n > (uint32_t)Cfg::kCap)
+      hipLaunchKernelGGL((exact_long_kernel<Cfg::kCap, HALF, FSTAR>), dim3((P + kPB - 1) / kPB), dim3(256), 0, s,
+                         a);
+  }
 }
 
-// The small configuration when every list fits its batches, else the large
+// The smallest configuration whose batches hold every declared list
 template <bool HALF, bool FSTAR>
 void launch_exact_t(const ExactArgs& a, uint32_t max_n, hipStream_t s) {
   if (max_n <= (uint32_t)CfgSmall::kCap) launch_exact_c<CfgSmall, HALF, FSTAR>(a, max_n, s);
+  else if (max_n <= (uint32_t)CfgMid::kCap) launch_exact_c<CfgMid, HALF, FSTAR>(a, max_n, s);
   else launch_exact_c<CfgLarge, HALF, FSTAR>(a, max_n, s);
 }
 

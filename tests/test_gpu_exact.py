@@ -1,9 +1,9 @@
 """Exact A-buffer path against the FP64 oracle at the shapes its kernels
-split on: lists at and around the per-wave batch capacities (192 fragments
-for 32-pixel waves when the declared maximum allows, 384 for 48-pixel waves
-otherwise), runs of long lists next to short ones, equal depths inside short
-and long lists, waves whose pixels are all empty, and the call without the
-tail output. Bar: <= 1e-4 per channel against FP64 (eq (1), the A-buffer of
+split on: 16-pixel waves whose batches hold 192, 256 or 384 fragments (the
+smallest that holds the declared maximum list length; longer lists go to
+the long-list kernel), lists at and around each capacity, runs of long lists
+next to short ones, equal depths inside short and long lists, waves whose
+pixels are all empty, and the call without the tail output. Bar: <= 1e-4 per channel against FP64 (eq (1), the A-buffer of
 Sec. 4); the colour is bitwise the same with and without the tail output
 and under permutation of every list."""
 import numpy as np
@@ -62,26 +62,38 @@ def test_exact_lists_around_the_batch_capacity(starnt, gpu, oracle_mod, seed):
     lengths[63] = 1000
     lengths[64 + 7] = 384
     lengths[64 + 8] = 384
-    lengths[128:192] = 0  # a wave of empty pixels
+    lengths[128:192] = 0  # four waves of empty pixels
     _check(starnt, oracle_mod, _lists(rng, lengths), W, H, 1024)
 
 
 @pytest.mark.parametrize("seed", [0, 1])
 def test_exact_small_batches_around_their_capacity(starnt, gpu, oracle_mod, seed):
-    """Declared maximum 192: 32-pixel waves with batches of at most 192
-    fragments. Lists at and below the capacity, waves whose lists need
-    several batches, a wave of empty pixels, a frame that is not a whole
-    number of waves."""
+    """Declared maximum 192: batches of at most 192 fragments. Lists at and
+    below the capacity, waves whose lists need several batches, waves of
+    empty pixels, a frame that is not a whole number of waves."""
     rng = np.random.default_rng(20 + seed)
     W, H = 61, 3
     lengths = rng.choice([0, 1, 2, 3, 9, 40, 96, 150], size=W * H)
     lengths[0] = 192
     lengths[1:4] = (191, 192, 1)
-    lengths[31] = 192  # last lane of the first wave
-    lengths[32:64] = 0  # a wave of empty pixels
+    lengths[15] = 192  # last pixel of the first wave
+    lengths[32:64] = 0  # two waves of empty pixels
     lengths[64:70] = (100, 100, 100, 100, 100, 100)  # one list per batch
     lengths[-1] = 192
     _check(starnt, oracle_mod, _lists(rng, lengths), W, H, 192)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_exact_mid_batches_around_their_capacity(starnt, gpu, oracle_mod, seed):
+    """Declared maximum 256: batches of at most 256 fragments, lists at, just
+    below and well below that, one list per batch in a run, ties."""
+    rng = np.random.default_rng(40 + seed)
+    W, H = 50, 2
+    lengths = rng.choice([0, 1, 7, 30, 129, 200], size=W * H)
+    lengths[0:4] = (256, 255, 193, 256)
+    lengths[16:32] = 0
+    lengths[-1] = 256
+    _check(starnt, oracle_mod, _lists(rng, lengths, ties_every=5 if seed else 0), W, H, 256)
 
 
 def test_exact_small_batches_with_ties(starnt, gpu, oracle_mod):

@@ -879,6 +879,32 @@ def main():
         torch.cuda.synchronize()
     exact_launch_us = 1e3 * float(np.mean([a_.elapsed_time(b_) for a_, b_ in ex_ev]))
     log("exact launch %.2f us (events behind a GPU spin)" % exact_launch_us)
+    # the fragment pass of each real frame at its quadtree scales and at full
+    # resolution, alone (events around each launch behind a GPU spin)
+    fbs = st.FeatBuffers(W, H)
+    by_scale = []
+    for t in real_ts_all:
+        us = {}
+        for where, sch in (("grids", scheds[t]), ("full", None)):
+            evs = []
+            for _ in range(3):
+                gpu_lead()
+                for _ in range(4):
+                    a_ = torch.cuda.Event(enable_timing=True)
+                    b_ = torch.cuda.Event(enable_timing=True)
+                    a_.record()
+                    st.starnt_features(frags[t], sch, fbs)
+                    b_.record()
+                    evs.append((a_, b_))
+                torch.cuda.synchronize()
+            us[where] = 1e3 * float(np.mean([a_.elapsed_time(b_) for a_, b_ in evs]))
+        bg_, _ = feature_pass_bytes(host[t], grids[t])
+        bf_, _ = feature_pass_bytes(host[t], (W, H, W, H))
+        by_scale.append({"frame": t, "s2": round(grids[t][0] / W, 3), "s3": round(grids[t][2] / W, 3),
+                         "us": round(us["grids"], 2), "fullres_us": round(us["full"], 2),
+                         "time_ratio": round(us["grids"] / us["full"], 3), "bytes_ratio": round(bg_ / bf_, 3)})
+    del fbs
+    log("fragment pass by scale: %s" % by_scale)
 
     # variants: FP32 network, and the plain full-resolution learned path
     mlp.set_dtype(st.F32)
@@ -1154,6 +1180,7 @@ def main():
                      "peak_tflops_bf16": 2500.0, "frac": round(mlp_flops / mlp_s / 2.5e15, 5),
                      "note": "2(5*32+32*32+32*3) flop per pixel with N >= 3 over the fused network call's time"},
         "kernels_us": breakdown,
+        "features_by_scale": by_scale,
         "grids": {str(k): v for k, v in grids.items()},
         "fp32_mlp_ms_per_frame": round(fp32_step_ms / NF, 4),
         "plain_fullres_ms_per_frame": round(plain_step_ms / NF, 4),

@@ -445,10 +445,25 @@ void infer_mfma_kernel(InferArgs a) {
   const int half = lane >> 5;
   const int col = lane & 31;
   const int waves_per_block = blockDim.x >> 6;
-  const int wave = blockIdx.x * waves_per_block + (threadIdx.x >> 6);
-  const int nwaves = gridDim.x * waves_per_block;
   const int P = pixel_count<MODE>(a);
   const int nsteps = (P + 63) / 64;
+  // Steps of 64 pixels: blocks go to the eight XCDs in turn, so with a grid
+  // of a multiple of 8 blocks each XCD takes a contiguous eighth of the
+  // steps (its waves stride through it). Vertically adjacent steps then
+  // share the pass-3 rows their taps read in one XCD's L2 instead of
+  // fetching them into several.
+  int wave, nwaves, st_end;
+  if ((gridDim.x & 7) == 0 && MODE != kPatch) {
+    const int xcd = (int)(blockIdx.x & 7);
+    const int lo = (int)(((long long)nsteps * xcd) >> 3);
+    st_end = (int)(((long long)nsteps * (xcd + 1)) >> 3);
+    wave = lo + (int)(blockIdx.x >> 3) * waves_per_block + (int)(threadIdx.x >> 6);
+    nwaves = (int)(gridDim.x >> 3) * waves_per_block;
+  } else {
+    wave = blockIdx.x * waves_per_block + (threadIdx.x >> 6);
+    nwaves = gridDim.x * waves_per_block;
+    st_end = nsteps;
+  }
   const Grids g = load_grids(a.sched, a.W, a.H);
   // FP8: activation scale of each layer's input, inverse weight scale, and
   // the dequantisation factor sa * sw of each layer's products
@@ -590,17 +605,17 @@ void infer_mfma_kernel(InferArgs a) {
   // and the wave's last step prefetches its own pixels again (cache hits);
   // neither is used.
   auto run = [&](auto full) {
-  if (wave >= nsteps) return;
+  if (wave >= st_end) return;
   PixRaw r;
   int pn = wave * 64 + lane;
   issue_loads<MODE>(a, g, full, pn < P ? pn : P - 1, r);
-  for (int st = wave; st < nsteps; st += nwaves) {
+  for (int st = wave; st < st_end; st += nwaves) {
     const int p = pn;
     const bool live = p < P;
     const PixIn in = blend<MODE>(r, full);
     const int sn = st + nwaves;
     pn = sn * 64 + lane;
-    const int q = sn < nsteps ? pn : p;
+    const int q = sn < st_end ? pn : p;
     issue_loads<MODE>(a, g, full, q < P ? q : P - 1, r);
     // group A is the pixels of lanes 0..31, group B those of lanes 32..63; a
     // group's inputs 0..7 go to half 0 and 8..15 to half 1 of the same

@@ -276,6 +276,11 @@ int starnt_dfa_inputs(const starnt_feats* feats, const starnt_sched* sched, floa
  *   C = sum_j a_j c_j prod_{k<j} (1 - a_k) + prod_j (1 - a_j) C_b (eq (1));
  *   optional fstar [P][3] receives the exact tail colour, sorted positions
  *   3..N composited alone. Reads only `frags` (+ feats->err for flags).
+ *   frags->max_per_pixel (at most 2048, else EUNSUPPORTED) picks the batch
+ *   size, the smallest of 192, 256 and 384 fragments that holds it; lists
+ *   longer than 384 take a slower block-wide kernel, so a tight declared
+ *   maximum is faster. Outputs do not depend on that choice beyond FP32
+ *   rounding of the transmittance (within 1e-4 of eq (1) in FP64).
  * bg is a host float[3]. */
 int starnt_composite(const starnt_frags* frags, const starnt_feats* feats, const float* tail_rgb,
                      const starnt_sched* sched, const float* bg, int32_t mode, float* rgb, float* fstar,

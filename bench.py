@@ -329,8 +329,8 @@ def cpu_baseline(host, mlp_w, mlp_b, bg, budget_s, nthreads=1):
             break
     dt = time.perf_counter() - t0
     how = ("single-threaded" if nthreads == 1 else
-           "sort, composite, features, network, eq (3) and reprojection on %d OpenMP threads (the quadtree "
-           "update single-threaded)" % nthreads)
+           "every stage (sort, composite, features, network, eq (3), quadtree, reprojection) on %d OpenMP "
+           "threads" % nthreads)
     return {"value": frags / dt / 1e9, "unit": "Gfrag/s", "cores": nthreads, "kind": "oracle",
             "sample": "%d frames (%d real: sort+over, features, FP64 MLP 16-32-32-3, eq (3), quadtree; %d "
                       "reprojected) of the 1080p sequence in order, %.1f s, %s"
@@ -1211,12 +1211,12 @@ def main():
                      "timed_dispatches": ev_ids},
     }
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        res["cpu_baseline"] = cpu_baseline(host, Ws, bs, bg, args.cpu_budget)
         # every core this process may run on (the GPU machine's share)
         threads = max(1, len(os.sched_getaffinity(0)))
         log("cpu baseline (oracle, %d threads) ..." % threads)
-        res["cpu_baseline_threads"] = cpu_baseline(host, Ws, bs, bg, args.cpu_budget, nthreads=threads)
+        res["cpu_baseline"] = cpu_baseline(host, Ws, bs, bg, args.cpu_budget, nthreads=threads)
+        log("cpu baseline (oracle, one thread) ...")
+        res["cpu_baseline_1thread"] = cpu_baseline(host, Ws, bs, bg, args.cpu_budget)
     print(json.dumps(res), flush=True)
 
 

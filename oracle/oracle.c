@@ -651,7 +651,9 @@ int orc_quadtree(int32_t W, int32_t H, const float* rgb, const uint32_t* N, cons
     free(L); free(R);
     return -1;
   }
-  /* top-down decisions per tile */
+  /* top-down decisions per tile (tiles are independent: each writes only its
+   * own D rows and cells; threads of the caller's OpenMP setting) */
+#pragma omp parallel for collapse(2) schedule(static)
   for (int32_t ty = 0; ty < Th; ++ty)
     for (int32_t tx = 0; tx < Tw; ++tx) {
       int64_t t = (int64_t)ty * Tw + tx;
@@ -693,6 +695,7 @@ int orc_quadtree(int32_t W, int32_t H, const float* rgb, const uint32_t* N, cons
   /* masks from a level map, then leaf levels from the masks */
   for (int it = 0; it <= qp->k_relax; ++it) {
     if (it > 0) {
+#pragma omp parallel for schedule(static)
       for (int32_t gy = 0; gy < Ch; ++gy)
         for (int32_t gx = 0; gx < Cw; ++gx) {
           int r = L[gy * Cw + gx];
@@ -705,6 +708,7 @@ int orc_quadtree(int32_t W, int32_t H, const float* rgb, const uint32_t* N, cons
     } else {
       memcpy(R, L, sizeof(int) * (size_t)Cw * Ch);
     }
+#pragma omp parallel for collapse(2) schedule(static)
     for (int32_t ty = 0; ty < Th; ++ty)
       for (int32_t tx = 0; tx < Tw; ++tx) {
         uint32_t m = 0;
@@ -748,7 +752,8 @@ int orc_quadtree(int32_t W, int32_t H, const float* rgb, const uint32_t* N, cons
   for (int64_t c = 0; c < (int64_t)Cw * Ch; ++c) level[c] = (uint8_t)L[c];
   /* occupied leaves per level: a leaf is occupied when some pixel inside it
    * (and inside the frame) has at least one fragment */
-  for (int l = 0; l < 4; ++l) hist[l] = 0;
+  uint32_t h0 = 0, h1 = 0, h2 = 0, h3 = 0;
+#pragma omp parallel for collapse(2) schedule(static) reduction(+ : h0, h1, h2, h3)
   for (int32_t ty = 0; ty < Th; ++ty)
     for (int32_t tx = 0; tx < Tw; ++tx) {
       uint32_t mt = mask[(int64_t)ty * Tw + tx];
@@ -776,10 +781,19 @@ int orc_quadtree(int32_t W, int32_t H, const float* rgb, const uint32_t* N, cons
                   occ = 1;
                   break;
                 }
-            if (occ) hist[lvl]++;
+            if (occ) {
+              if (lvl == 0) ++h0;
+              else if (lvl == 1) ++h1;
+              else if (lvl == 2) ++h2;
+              else ++h3;
+            }
           }
       }
     }
+  hist[0] = h0;
+  hist[1] = h1;
+  hist[2] = h2;
+  hist[3] = h3;
   free(L);
   free(R);
   return 0;

@@ -903,8 +903,33 @@ def main():
         by_scale.append({"frame": t, "s2": round(grids[t][0] / W, 3), "s3": round(grids[t][2] / W, 3),
                          "us": round(us["grids"], 2), "fullres_us": round(us["full"], 2),
                          "time_ratio": round(us["grids"] / us["full"], 3), "bytes_ratio": round(bg_ / bf_, 3)})
+    # fixed pass scales on the first frame (the paper's reduced-pass rows of
+    # its Tab. 1, here for the one fused pass): time and algorithmic bytes
+    fixed_scales = []
+    for s2_, s3_ in ((1.0, 1.0), (1.0, 0.75), (1.0, 0.5), (1.0, 0.25), (0.5, 0.5)):
+        sch = st.new_sched(W, H, s2_, s3_)
+        sd = st.read_sched(sch)
+        gg = (sd["w2"], sd["h2"], sd["w3"], sd["h3"])
+        evs = []
+        for _ in range(3):
+            gpu_lead()
+            for _ in range(4):
+                a_ = torch.cuda.Event(enable_timing=True)
+                b_ = torch.cuda.Event(enable_timing=True)
+                a_.record()
+                st.starnt_features(frags[0], sch, fbs)
+                b_.record()
+                evs.append((a_, b_))
+            torch.cuda.synchronize()
+        fixed_scales.append({"s2": s2_, "s3": s3_, "grids": list(gg),
+                             "us": round(1e3 * float(np.mean([a_.elapsed_time(b_) for a_, b_ in evs])), 2),
+                             "bytes": int(feature_pass_bytes(host[0], gg)[0])})
+    for r_ in fixed_scales:
+        r_["time_ratio"] = round(r_["us"] / fixed_scales[0]["us"], 3)
+        r_["bytes_ratio"] = round(r_["bytes"] / fixed_scales[0]["bytes"], 3)
     del fbs
     log("fragment pass by scale: %s" % by_scale)
+    log("fragment pass at fixed scales (frame 0): %s" % fixed_scales)
 
     # variants: FP32 network, and the plain full-resolution learned path
     mlp.set_dtype(st.F32)
@@ -1181,6 +1206,7 @@ def main():
                      "note": "2(5*32+32*32+32*3) flop per pixel with N >= 3 over the fused network call's time"},
         "kernels_us": breakdown,
         "features_by_scale": by_scale,
+        "features_fixed_scales": fixed_scales,
         "grids": {str(k): v for k, v in grids.items()},
         "fp32_mlp_ms_per_frame": round(fp32_step_ms / NF, 4),
         "plain_fullres_ms_per_frame": round(plain_step_ms / NF, 4),

@@ -60,7 +60,7 @@ struct WaveCfg {
 using CfgSmall = WaveCfg<192, 16>;  // lists up to 192 fragments
 using CfgMid = WaveCfg<256, 16>;    // up to 256
 using CfgLarge = WaveCfg<384, 16>;  // up to 384 (longer ones: the long-list kernel)
-constexpr int kWPB = 1;             // waves per block (each works alone; 4 measured slower)
+constexpr int kWPB = 1;             // waves per block (each works alone; 2 or 4 measured slower)
 constexpr int kPB = 256;     // pixels per window (long-list kernel)
 constexpr int kCapL = 2048;  // fragments per LDS batch (long-list kernel)
 constexpr uint32_t kOneBits = 0x3F800000u;  // bits of 1.0f
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(64 * kWPB) void exact_wave_kernel(ExactArgs a) {
   uint32_t* s_key = s_key_all[wv];
   float4* s_c = s_c_all[wv];
   uint16_t* s_idx = s_idx_all[wv];
-  float4* s_part = reinterpret_cast<float4*>(s_key);   // [128] chunk and list partials
+  float4* s_part = reinterpret_cast<float4*>(s_key);   // [64 + PIX] chunk and list partials
 
   const int l = (int)(threadIdx.x & 63);
   const int P = a.W * a.H;

@@ -280,7 +280,9 @@ int starnt_dfa_inputs(const starnt_feats* feats, const starnt_sched* sched, floa
  *   size, the smallest of 192, 256 and 384 fragments that holds it; lists
  *   longer than 384 take a slower block-wide kernel, so a tight declared
  *   maximum is faster. Outputs do not depend on that choice beyond FP32
- *   rounding of the transmittance (within 1e-4 of eq (1) in FP64).
+ *   rounding of the transmittance (within 1e-4 of eq (1) in FP64). A list
+ *   longer than the declared maximum sets STARNT_DERR_COUNT; if it is also
+ *   longer than the batch size chosen, its pixel gets the background alone.
  * bg is a host float[3]. */
 int starnt_composite(const starnt_frags* frags, const starnt_feats* feats, const float* tail_rgb,
                      const starnt_sched* sched, const float* bg, int32_t mode, float* rgb, float* fstar,

@@ -402,7 +402,10 @@ __global__ __launch_bounds__(64 * kWPB) void exact_wave_kernel(ExactArgs a) {
     }
     cur = end;
   }
-  if (valid && !lng) write_pixel(a, p, w);
+  // a long list is the long-list kernel's, unless the declared maximum ruled
+  // that kernel out: then the list broke the declaration (flagged above) and
+  // the pixel gets the background alone, so every output is defined
+  if (valid && (!lng || a.max_n <= (uint32_t)kCapW)) write_pixel(a, p, w);
   if (errf && a.err) atomicOr(a.err, errf);
 }
 

@@ -140,7 +140,8 @@ def test_exact_declared_maximum_below_the_capacity(starnt, gpu, oracle_mod):
 
 def test_exact_flags_lists_longer_than_declared(starnt, gpu):
     """A list longer than the declared maximum sets the count flag (the call
-    itself is not an error; the flag is read after the stream)."""
+    itself is not an error; the flag is read after the stream), and every
+    pixel is still written."""
     rng = np.random.default_rng(2)
     W, H = 8, 1
     lengths = [3, 400, 2, 0, 5, 6, 7, 8]
@@ -148,9 +149,14 @@ def test_exact_flags_lists_longer_than_declared(starnt, gpu):
     csr = make_csr(lists, W, H)
     df = starnt.DeviceFrags(*csr, W, H, 64)
     fb = starnt.FeatBuffers(W, H)
-    rgb = torch.empty(W * H, 3, dtype=torch.float32, device="cuda")
+    rgb = torch.full((W * H, 3), float("nan"), dtype=torch.float32, device="cuda")
     fb.err.zero_()
     starnt.starnt_composite(df, fb, None, None, (1, 1, 1), starnt.MODE_EXACT, rgb, None)
     sync()
     e = int(to_np(fb.err)[0])
     assert e & starnt.DERR_COUNT
+    # every pixel is written: the list past every batch size gets the
+    # background alone, the others their exact colour
+    out = to_np(rgb)
+    assert np.isfinite(out).all()
+    assert np.array_equal(out[1], np.ones(3, np.float32))

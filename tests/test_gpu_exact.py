@@ -110,6 +110,24 @@ def test_exact_small_batches_with_ties(starnt, gpu, oracle_mod):
     assert np.array_equal(rgb, rgb2) and np.array_equal(fstar, fstar2)
 
 
+@pytest.mark.parametrize("max_n", [192, 384])
+def test_exact_half_colour(starnt, gpu, oracle_mod, max_n):
+    """FP16 RGBA in the small and large configurations: the kernels convert
+    each colour once; the oracle takes the same half values as FP32."""
+    rng = np.random.default_rng(60 + max_n)
+    W, H = 37, 3
+    lengths = rng.choice([0, 1, 3, 8, 25, 90], size=W * H)
+    lengths[0:3] = (max_n, max_n - 1, 2)
+    off, dep, rgba, prim = make_csr(_lists(rng, lengths, ties_every=6), W, H)
+    h = rgba.astype(np.float16)
+    df = starnt.DeviceFrags(off, dep, h, prim, W, H, max_n)
+    bg = (0.2, 0.4, 0.6)
+    rgb, fstar = run_exact(starnt, df, bg=bg)
+    o = oracle_mod.frame(off, dep, h.astype(np.float32), prim, W, H, bg=bg)
+    assert np.abs(rgb - o["rgb"]).max() <= TOL
+    assert np.abs(fstar - o["fstar"]).max() <= TOL
+
+
 def test_exact_ties_in_short_and_long_lists(starnt, gpu, oracle_mod):
     rng = np.random.default_rng(5)
     W, H = 40, 4

@@ -556,6 +556,13 @@ def main():
                                         variant=st.NET_DFAOIT)
         dfa_mlp = st.DeviceMlp(dWs, dbs, st.BF16, variant=st.NET_DFAOIT)
         log("DFAOIT network trained, loss %.3e -> %.3e" % (dlosses[0], dlosses[-1]))
+        # the same with twice the hidden width, to see whether capacity
+        # explains the gap
+        Wd0, bd0 = sg.init_mlp((16, 64, 64, 3), seed=sg.BASE_SEED + 100, out_bias=0.05)
+        dWs2, dbs2, dlosses2 = learn.train(x, y, Wd0, bd0, steps=args.train_steps, batch=65536, dtype=st.BF16,
+                                           variant=st.NET_DFAOIT)
+        dfa_mlp_wide = st.DeviceMlp(dWs2, dbs2, st.BF16, variant=st.NET_DFAOIT)
+        log("DFAOIT 16-64-64-3 trained, loss %.3e -> %.3e" % (dlosses2[0], dlosses2[-1]))
         del dxs, dys
 
     # ---- exact references -------------------------------------------------
@@ -1054,13 +1061,17 @@ def main():
     ablation = None
     if dfa_mlp is not None:
         fbd = st.FeatBuffers(W, H, with_avg=True)
-        dpsnr = []
+        dpsnr, dpsnr_w = [], []
         for t in range(NF):
             st.starnt_features(frags[t], None, fbd)
             st.starnt_infer_composite(dfa_mlp, fbd, None, bg, outs[t])
             torch.cuda.synchronize()
             d = (outs[t] - exact[t]).double()
             dpsnr.append(10 * np.log10(1.0 / float((d * d).mean())))
+            st.starnt_infer_composite(dfa_mlp_wide, fbd, None, bg, outs[t])
+            torch.cuda.synchronize()
+            d = (outs[t] - exact[t]).double()
+            dpsnr_w.append(10 * np.log10(1.0 / float((d * d).mean())))
         st.starnt_features(frags[0], None, fbd)
         torch.cuda.synchronize()
 
@@ -1078,7 +1089,8 @@ def main():
 
         ablation = {
             "psnr_db_fullres_mean": {"starnt_5_features": round(float(np.mean(plain_psnr)), 2),
-                                     "dfaoit_10_features": round(float(np.mean(dpsnr)), 2)},
+                                     "dfaoit_10_features": round(float(np.mean(dpsnr)), 2),
+                                     "dfaoit_10_features_16_64_64_3": round(float(np.mean(dpsnr_w)), 2)},
             "infer_composite_us_fullres_bf16": {
                 "starnt_5_features": round(time_us(lambda: st.starnt_infer_composite(mlp, fbd, None, bg, outs[0])), 2),
                 "dfaoit_10_features": round(time_us(lambda: st.starnt_infer_composite(dfa_mlp, fbd, None, bg,

@@ -154,6 +154,15 @@ struct Part {
 constexpr uint32_t kIdxMask = 0x1FFu;
 constexpr uint32_t kStartBit = 0x8000u;
 
+// A fragment's list descriptor in a batch, (list << 20) | (start << 10) |
+// end, kept in one register per fragment and unpacked where used
+__device__ __forceinline__ int desc_start(uint32_t d) { return (int)((d >> 10) & 0x3FFu); }
+__device__ __forceinline__ int desc_end(uint32_t d) { return (int)(d & 0x3FFu); }
+// the list's shift in the key words: seven guards after every earlier list
+__device__ __forceinline__ int desc_shift(uint32_t d) { return 7 * (int)(d >> 20); }
+// the claim word's list-start bits, for the fragment that sorts first
+__device__ __forceinline__ uint32_t desc_first(uint32_t d) { return kStartBit | ((d >> 20) << 9); }
+
 // Chunked walk of a batch's sorted slots: lane l composites slots
 // [kSlots l, kSlots l + kSlots), closing a segment at every list start. A
 // chunk's segment before its first list start (the whole chunk if none
@@ -202,8 +211,17 @@ __device__ __forceinline__ float4 list_result(const float4* s_part, int lid, int
   return r;
 }
 
+// Waves per SIMD asked of the register allocator: the 192-fragment colour
+// kernel fits 64 registers without spilling, so 8 waves per SIMD (LDS allows
+// 33 waves per CU); 1080p 125.1 against 126.5 us at 7 waves, 1440p 720
+// against 734 us. The tail variant and larger batches keep their registers
+// (a cap spills there, and LDS caps their waves anyway).
+template <class Cfg, bool FSTAR>
+constexpr int exact_waves_per_simd() { return (Cfg::kCap == 192 && !FSTAR) ? 8 : 1; }
+
 template <class Cfg, bool HALF, bool FSTAR>
-__global__ __launch_bounds__(64 * kWPB) void exact_wave_kernel(ExactArgs a) {
+__global__ __launch_bounds__(64 * kWPB) __attribute__((amdgpu_waves_per_eu(exact_waves_per_simd<Cfg, FSTAR>())))
+void exact_wave_kernel(ExactArgs a) {
   constexpr int kCapW = Cfg::kCap;
   constexpr int kSlots = Cfg::kSlots;
   constexpr int kKeys = Cfg::kKeys;
@@ -279,19 +297,15 @@ __global__ __launch_bounds__(64 * kWPB) void exact_wave_kernel(ExactArgs a) {
         s_c[min(l + 64 * k, m - 1)] = c[k];
       }
       wave_sync();
-      int sb[kSlots], se[kSlots], lk[kSlots], pos[kSlots];
-      uint32_t fl[kSlots];  // the claim word's list-start bits (when the fragment sorts first)
+      int pos[kSlots];
+      uint32_t dd[kSlots];  // each fragment's list descriptor
 #pragma unroll
       for (int k = 0; k < kSlots; ++k) {
         const int i = l + 64 * k;
-        sb[k] = se[k] = lk[k] = pos[k] = 0;
-        fl[k] = 0;
+        pos[k] = 0;
+        dd[k] = 0;
         if (i < m) {
-          const uint32_t d = s_key[i];
-          sb[k] = (int)((d >> 10) & 0x3FFu);
-          se[k] = (int)(d & 0x3FFu);
-          lk[k] = 7 * (int)(d >> 20);  // the list's shift in s_key
-          fl[k] = kStartBit | ((d >> 20) << 9);
+          dd[k] = s_key[i];
           errf |= zb[k] > kOneBits ? STARNT_DERR_DEPTH : 0u;  // negatives, -0 and NaN too
         }
       }
@@ -299,7 +313,7 @@ __global__ __launch_bounds__(64 * kWPB) void exact_wave_kernel(ExactArgs a) {
       // keys, and the seven guard keys after every list
 #pragma unroll
       for (int k = 0; k < kSlots; ++k)
-        if (l + 64 * k < m) s_key[l + 64 * k + lk[k]] = zb[k];
+        if (l + 64 * k < m) s_key[l + 64 * k + desc_shift(dd[k])] = zb[k];
       if (mine) {
 #pragma unroll
         for (int g = 0; g < 7; ++g) s_key[s0 + (int)n + 7 * (l - cur) + g] = 0xFFFFFFFFu;
@@ -314,15 +328,16 @@ __global__ __launch_bounds__(64 * kWPB) void exact_wave_kernel(ExactArgs a) {
         if (i < m) {
           int r = 0;
           const uint32_t zi = min(zb[k], kOneBits);  // out-of-range depths (flagged) below the guards
-          for (int j = sb[k] + lk[k]; j < se[k] + lk[k]; j += 8) {
+          const int sh = desc_shift(dd[k]);
+          for (int j = desc_start(dd[k]) + sh; j < desc_end(dd[k]) + sh; j += 8) {
             uint32_t v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) v[u] = s_key[j + u];
 #pragma unroll
             for (int u = 0; u < 8; ++u) r += v[u] < zi ? 1 : 0;
           }
-          pos[k] = sb[k] + r;
-          s_idx[pos[k]] = (uint16_t)(i | (r == 0 ? fl[k] : 0u));
+          pos[k] = desc_start(dd[k]) + r;
+          s_idx[pos[k]] = (uint16_t)(i | (r == 0 ? desc_first(dd[k]) : 0u));
         }
       }
       wave_sync();
@@ -357,23 +372,22 @@ __global__ __launch_bounds__(64 * kWPB) void exact_wave_kernel(ExactArgs a) {
             // contract) keep their staging order, so the ranks always form a
             // permutation of the list's slots
             int r = 0;
-            for (int j = sb[k]; j < se[k]; ++j) {
-              const uint32_t zj = s_key[j + lk[k]], pj = s_pr[j];
+            const int sh = desc_shift(dd[k]);
+            for (int j = desc_start(dd[k]); j < desc_end(dd[k]); ++j) {
+              const uint32_t zj = s_key[j + sh], pj = s_pr[j];
               r += (zj < zb[k]) | ((zj == zb[k]) & ((pj < pr[k]) | ((pj == pr[k]) & (j < i))));
             }
-            pos[k] = sb[k] + r;
+            pos[k] = desc_start(dd[k]) + r;
           }
         }
-        // the colours the prim ids displaced, read again
-        float4 cr[kSlots];
-#pragma unroll
-        for (int k = 0; k < kSlots; ++k) cr[k] = load_rgba<HALF>(a.rgba, bcur + min(l + 64 * k, m - 1));
         wave_sync();  // keys and prim ids read before the colours are restored
+        // the colours the prim ids displaced, read again (this rare path
+        // waits on each reload rather than holding them all in registers)
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) {
           const int i = l + 64 * k;
-          s_c[min(i, m - 1)] = cr[k];
-          if (i < m) s_idx[pos[k]] = (uint16_t)(i | (pos[k] == sb[k] ? fl[k] : 0u));
+          s_c[min(i, m - 1)] = load_rgba<HALF>(a.rgba, bcur + min(i, m - 1));
+          if (i < m) s_idx[pos[k]] = (uint16_t)(i | (pos[k] == desc_start(dd[k]) ? desc_first(dd[k]) : 0u));
         }
       }
       wave_sync();  // claims final, keys no longer read

@@ -257,7 +257,7 @@ def profile_summary(d, calib_mb):
     for label, pat, alg, where in (
             ("reproject_kernel", "reproject_kernel", 28 * P1080,
              "4 B d1 + 12 B gathered colour + 12 B colour out per pixel (no source index)"),
-            ("exact_wave_kernel, 192-fragment batches (the exact step's 1080p frames, colour only)",
+            ("exact_wave_kernel, 192-fragment batches (the 1080p frames, colour only)",
              "WaveCfg<192, 16>, false, false>", None,
              "4 B offsets + 12 B colour out per pixel, 4 B depth + 16 B RGBA per fragment")):
         tr_rows = con.execute("select dispatch_id, start, duration from kernels where name like ? order by dispatch_id",
@@ -267,7 +267,19 @@ def profile_summary(d, calib_mb):
         if label == "reproject_kernel":
             pick = [j for j, (_, st0, _) in enumerate(tr_rows) if t0 <= st0 < t1]
         else:
-            pick = list(range(len(tr_rows)))  # every launch of that variant is a 1080p exact frame
+            # the 1080p frames only (the training scenes' 480x270 frames use
+            # the same variant), picked by the launch's grid: one 64-lane
+            # workgroup per 16 pixels
+            cols = [c[1] for c in con.execute("pragma table_info(kernels)")]
+            gcol = next((c for c in ("grid_size_x", "grid_x", "grid_size") if c in cols), None)
+            if gcol is None:
+                raise SystemExit("no grid-size column in the trace's kernels view: %s" % cols)
+            grids = [g for (g,) in con.execute("select %s from kernels where name like ? order by dispatch_id" % gcol,
+                                                ("%" + pat + "%",)).fetchall()]
+            full = {P1080 // 16, P1080 // 16 * 64}
+            pick = [j for j, g in enumerate(grids) if g in full]
+            if not pick:
+                raise SystemExit("no 1080p exact launch in the trace (grids %s)" % sorted(set(grids)))
         dur = float(np.mean([tr_rows[j][2] for j in pick])) / 1e3
         fv = [v for _, k, v in kernel_counters("fetch", "FETCH_SIZE") if pat in k]
         wv = [v for _, k, v in kernel_counters("write", "WRITE_SIZE") if pat in k]

@@ -453,6 +453,19 @@ size_t starnt_workspace_size(int32_t kind, int64_t a, int64_t b, int64_t c);
 /* status for a device error word read back after the stream synchronised */
 int starnt_check(uint32_t err_word);
 
+/* Kernel timing, for callers that measure a kernel alone (a benchmark's
+ * roofline, not part of the method). The next of these kernels that the
+ * calling thread launches: the fragment pass (starnt_features), the network
+ * (every call that runs it) or the exact path's main kernel (starnt_composite
+ * with STARNT_MODE_EXACT), goes out through hipExtLaunchKernel, which records
+ * start_event when the kernel starts and stop_event when it ends, so their
+ * elapsed time is the kernel's own duration, without the dispatch gaps of
+ * events recorded around the call. Both are hipEvent_t created (and recorded
+ * once) by the caller with timing enabled; either may be NULL. The request
+ * holds for that one launch and is then cleared; both NULL clears it. Never
+ * fails. */
+int starnt_time_next_launch(void* start_event, void* stop_event);
+
 /* message of the calling thread's last failure ("" if none) */
 const char* starnt_last_error(void);
 

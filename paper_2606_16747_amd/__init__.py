@@ -89,7 +89,8 @@ EXPORTS = ("starnt_features", "starnt_infer", "starnt_infer_composite", "starnt_
            "starnt_quadtree", "starnt_quadtree_noalloc", "starnt_reproject", "starnt_reproject_check", "starnt_patch", "starnt_interval_init", "starnt_interval_next",
            "starnt_interval_report",
            "starnt_train_step", "starnt_sched_init", "starnt_wbar", "starnt_pass_scales", "starnt_grid_dim",
-           "starnt_workspace_size", "starnt_check", "starnt_last_error", "starnt_version", "starnt_m_minus_i")
+           "starnt_workspace_size", "starnt_check", "starnt_last_error", "starnt_version", "starnt_m_minus_i",
+           "starnt_time_next_launch")
 
 
 def _load():
@@ -134,6 +135,7 @@ def _load():
                                      ctypes.POINTER(ctypes.c_float)]
     lib.starnt_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
     lib.starnt_check.argtypes = [ctypes.c_uint32]
+    lib.starnt_time_next_launch.argtypes = [_P, _P]
     lib.starnt_last_error.restype = ctypes.c_char_p
     lib.starnt_version.restype = ctypes.c_char_p
     return lib
@@ -273,6 +275,22 @@ def starnt_features(frags: DeviceFrags, sched, feats: FeatBuffers, stream=None):
     global features_launches
     _check(lib.starnt_features(ctypes.byref(frags._c), _ptr(sched), ctypes.byref(feats._c), _stream(stream)))
     features_launches += 1
+
+
+def _event_handle(ev):
+    if ev is None:
+        return None
+    h = int(ev.cuda_event)
+    if h == 0:
+        raise ValueError("starnt_time_next_launch: record the event once before passing it (torch creates it then)")
+    return ctypes.c_void_p(h)
+
+
+def starnt_time_next_launch(start=None, stop=None):
+    """The calling thread's next fragment-pass, network or exact-path kernel
+    records these torch.cuda.Events with its own dispatch (both None clears
+    the request)."""
+    _check(lib.starnt_time_next_launch(_event_handle(start), _event_handle(stop)))
 
 
 def starnt_infer(mlp: DeviceMlp, tail, count, sched, width, height, tail_rgb, stream=None):

@@ -21,6 +21,14 @@ int hip_status(hipError_t e, const char* what) {
   return STARNT_EHIP;
 }
 
+static thread_local LaunchTimer g_timer;
+
+LaunchTimer take_launch_timer() {
+  const LaunchTimer t = g_timer;
+  g_timer = LaunchTimer();
+  return t;
+}
+
 }  // namespace starnt
 
 using namespace starnt;
@@ -382,6 +390,12 @@ int starnt_check(uint32_t err_word) {
   if (err_word & STARNT_DERR_COUNT) m += " list longer than max_per_pixel;";
   if (err_word & STARNT_DERR_LIST) m += " pixel list entry outside the frame or longer than its capacity;";
   return fail(STARNT_ERANGE, m);
+}
+
+int starnt_time_next_launch(void* start_event, void* stop_event) {
+  g_timer.start = static_cast<hipEvent_t>(start_event);
+  g_timer.stop = static_cast<hipEvent_t>(stop_event);
+  return STARNT_OK;
 }
 
 const char* starnt_last_error(void) { return g_last_error.c_str(); }

@@ -506,8 +506,8 @@ template <class Cfg, bool HALF, bool FSTAR>
 void launch_exact_c(const ExactArgs& a, uint32_t max_n, hipStream_t s) {
   const int P = a.W * a.H;
   const int waves = (P + Cfg::kPix - 1) / Cfg::kPix;
-  hipLaunchKernelGGL((exact_wave_kernel<Cfg, HALF, FSTAR>), dim3((waves + kWPB - 1) / kWPB), dim3(64 * kWPB), 0, s,
-                     a);
+  launch_maybe_timed(take_launch_timer(), exact_wave_kernel<Cfg, HALF, FSTAR>, dim3((waves + kWPB - 1) / kWPB),
+                     dim3(64 * kWPB), s, a);
   // the long-list kernel only where the declared maximum allows such lists
   // (only the largest configuration leaves any)
   if constexpr (Cfg::kCap == CfgLarge::kCap) {

@@ -463,12 +463,13 @@ int launch_features(const starnt_frags& f, const starnt_sched* sched, const star
   const dim3 block(256), grid((unsigned)((f.width + 256 / kG - 1) / (256 / kG)), (unsigned)f.height);
   a.tail_avg = reinterpret_cast<float4*>(o.tail_avg);
   const bool half = f.rgba_dtype == STARNT_F16;
+  const LaunchTimer tm = take_launch_timer();
   if (o.tail_avg) {
-    if (half) hipLaunchKernelGGL((features_kernel<true, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((features_kernel<false, true>), grid, block, 0, s, a);
+    if (half) launch_maybe_timed(tm, features_kernel<true, true>, grid, block, s, a);
+    else launch_maybe_timed(tm, features_kernel<false, true>, grid, block, s, a);
   } else {
-    if (half) hipLaunchKernelGGL((features_kernel<true, false>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((features_kernel<false, false>), grid, block, 0, s, a);
+    if (half) launch_maybe_timed(tm, features_kernel<true, false>, grid, block, s, a);
+    else launch_maybe_timed(tm, features_kernel<false, false>, grid, block, s, a);
   }
   STARNT_LAUNCH_CHECK("starnt_features launch");
   return STARNT_OK;

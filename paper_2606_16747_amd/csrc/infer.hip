@@ -662,7 +662,7 @@ void infer_mfma_kernel(InferArgs a) {
 template <int H1, int H2, int MODE>
 void launch_f32(const InferArgs& a, hipStream_t s) {
   const int P = a.W * a.H;
-  hipLaunchKernelGGL((infer_f32_kernel<H1, H2, MODE>), dim3((P + 255) / 256), dim3(256), 0, s, a);
+  launch_maybe_timed(take_launch_timer(), infer_f32_kernel<H1, H2, MODE>, dim3((P + 255) / 256), dim3(256), s, a);
 }
 
 // blocks of 256 threads of `kernel` that the device holds at once (the
@@ -695,7 +695,7 @@ void launch_mfma(const InferArgs& a, hipStream_t s) {
   // 5-10% of the pixels listed)
   if (MODE == kPatch && blocks > 512) blocks = 512;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL((infer_mfma_kernel<T1, T2, FP8, MODE>), dim3(blocks), dim3(256), 0, s, a);
+  launch_maybe_timed(take_launch_timer(), infer_mfma_kernel<T1, T2, FP8, MODE>, dim3(blocks), dim3(256), s, a);
 }
 
 template <int MODE>

@@ -2,6 +2,7 @@
 // the C-ABI layer. Device helpers here are used by GPU code only.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -20,6 +21,22 @@ int hip_status(hipError_t e, const char* what);
     hipError_t e_ = hipGetLastError();                    \
     if (e_ != hipSuccess) return hip_status(e_, what);    \
   } while (0)
+
+// ---- kernel timing (starnt_time_next_launch) -------------------------------
+// The pending request of the calling thread, taken (and cleared) by the
+// launcher of the timed kernel.
+struct LaunchTimer {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+LaunchTimer take_launch_timer();
+
+// hipLaunchKernelGGL, or hipExtLaunchKernelGGL recording the timer's events
+// with the dispatch itself when a request is pending
+template <typename K, typename... Args>
+void launch_maybe_timed(const LaunchTimer& tm, K kernel, dim3 grid, dim3 block, hipStream_t s, Args... args) {
+  if (tm.start || tm.stop) hipExtLaunchKernelGGL(kernel, grid, block, 0, s, tm.start, tm.stop, 0, args...);
+  else hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
 
 // ---- device helpers -------------------------------------------------------
 

@@ -15,9 +15,11 @@
 //      smaller depths there (depth bits compare as unsigned integers, which
 //      orders valid depths in [0, 1] as numbers), eight per LDS round trip:
 //      in LDS every list is followed by seven guard keys larger than any
-//      depth, so whole 8-key blocks are counted with no mask; the pixel
-//      lanes first mark every fragment with its list's range, so no lane
-//      searches for its fragment's list;
+//      depth, so whole 8-key blocks are counted with no mask. Each
+//      fragment finds its list's range with no search: every list writes
+//      its descriptor (index, start, end) at its first slot, the other slots
+//      hold 0, and a prefix maximum over the batch's slots (descriptors grow
+//      with the list index) carries each list's descriptor over its slots;
 //   3. each fragment writes its index at its sorted slot and reads it back: a
 //      slot claimed twice means equal depths in a list, and only then are
 //      the ranks recounted on (depth, primitive id) for that batch, with the
@@ -126,6 +128,21 @@ __device__ __forceinline__ void write_pixel(const ExactArgs& a, int p, const Wal
   }
 }
 
+// Inclusive prefix maximum over the 64 lanes of a wave, in lane order: a
+// Hillis-Steele scan inside each 16-lane row (row_shr 1, 2, 4, 8; lanes
+// shifted in from outside the row read 0), then the last lane of row 0 into
+// row 1 and of row 2 into row 3 (row_bcast:15), then lane 31 into rows 2 and
+// 3 (row_bcast:31).
+__device__ __forceinline__ uint32_t wave_max_scan(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false));
+  return v;
+}
+
 // LDS written by some lanes of a wave and read by others: the wave's own
 // ordering point (waves of a block never share data)
 __device__ __forceinline__ void wave_sync() {
@@ -225,9 +242,9 @@ void exact_wave_kernel(ExactArgs a) {
   constexpr int kCapW = Cfg::kCap;
   constexpr int kSlots = Cfg::kSlots;
   constexpr int kKeys = Cfg::kKeys;
-  // s_key: first the list descriptor of each fragment, (list << 20) | (start
-  // << 10) | end; then the depth bits of list L's fragments at positions
-  // start + 7 L, so every list is followed by seven keys larger than any
+  // s_key: first each list's descriptor, (list << 20) | (start << 10) | end,
+  // at the list's first slot (0 elsewhere); then the depth bits of list L's
+  // fragments at positions start + 7 L, so every list is followed by seven keys larger than any
   // depth (the batch holds at most 64 lists): a count over whole 8-key
   // blocks from a list's start reads no other list's keys and needs no mask.
   // After the ranking it holds the chunk partials of the walk.
@@ -283,14 +300,16 @@ void exact_wave_kernel(ExactArgs a) {
         zb[k] = __float_as_uint(a.depth[bcur + i]);
         c[k] = load_rgba<HALF>(a.rgba, bcur + i);
       }
-      // each pixel lane marks its fragments with its list's descriptor (in
-      // the key words, read before any key is written); RGBA goes to LDS in
-      // CSR order as it arrives (lanes past the batch repeat its last
-      // fragment, the same value to the same place)
-      if (mine) {
-        const uint32_t d = ((uint32_t)(l - cur) << 20) | ((uint32_t)s0 << 10) | (uint32_t)(s0 + (int)n);
-        for (int t = 0; t < (int)n; ++t) s_key[s0 + t] = d;
-      }
+      // each nonempty list's descriptor at its first slot, 0 at the others
+      // (in the key words, read before any key is written; a wave's LDS
+      // writes land in program order); RGBA goes to LDS in CSR order as it
+      // arrives (lanes past the batch repeat its last fragment, the same
+      // value to the same place)
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k)
+        if (l + 64 * k < m) s_key[l + 64 * k] = 0u;
+      if (mine && n > 0)
+        s_key[s0] = ((uint32_t)(l - cur) << 20) | ((uint32_t)s0 << 10) | (uint32_t)(s0 + (int)n);
 #pragma unroll
       for (int k = 0; k < kSlots; ++k) {
         errf |= (l + 64 * k < m && !(c[k].w >= 0.0f && c[k].w <= 1.0f)) ? STARNT_DERR_ALPHA : 0u;
@@ -298,16 +317,17 @@ void exact_wave_kernel(ExactArgs a) {
       }
       wave_sync();
       int pos[kSlots];
-      uint32_t dd[kSlots];  // each fragment's list descriptor
+      uint32_t dd[kSlots];
+      // each fragment's descriptor: the prefix maximum up to its slot, in
+      // blocks of 64 slots (run: the maximum over the earlier blocks)
+      uint32_t run = 0;
 #pragma unroll
       for (int k = 0; k < kSlots; ++k) {
         const int i = l + 64 * k;
         pos[k] = 0;
-        dd[k] = 0;
-        if (i < m) {
-          dd[k] = s_key[i];
-          errf |= zb[k] > kOneBits ? STARNT_DERR_DEPTH : 0u;  // negatives, -0 and NaN too
-        }
+        dd[k] = max(wave_max_scan(i < m ? s_key[i] : 0u), run);
+        run = (uint32_t)__builtin_amdgcn_readlane((int)dd[k], 63);
+        if (i < m) errf |= zb[k] > kOneBits ? STARNT_DERR_DEPTH : 0u;  // negatives, -0 and NaN too
       }
       wave_sync();  // descriptors read before keys overwrite them
       // keys, and the seven guard keys after every list

@@ -66,6 +66,25 @@ def test_exact_lists_around_the_batch_capacity(starnt, gpu, oracle_mod, seed):
     _check(starnt, oracle_mod, _lists(rng, lengths), W, H, 1024)
 
 
+@pytest.mark.parametrize("max_n,lengths", [
+    (192, (10, 130, 52)),          # list 1 covers slots 64..127: no list starts there
+    (192, (0, 60, 0, 8, 0, 120)),  # empty lists before, between and after; starts at 60 and 68
+    (192, (1, 1, 190)),            # one list over all three blocks of 64 slots
+    (384, (5, 300, 70, 9)),        # blocks 1..4 hold no start
+    (384, (63, 1, 64, 1, 255)),    # starts at 63, 64, 128 and 129
+])
+def test_exact_lists_spanning_slot_blocks(starnt, gpu, oracle_mod, max_n, lengths):
+    """Every fragment takes its list from a prefix maximum over the batch's
+    slots, 64 slots at a time: lists that start right at and right after a
+    block edge, and blocks inside one list (the maximum carried from earlier
+    blocks alone names the list). One 16-pixel wave per case; the remaining
+    pixels of the wave are empty."""
+    rng = np.random.default_rng(sum(lengths))
+    W, H = 16, 1
+    full = list(lengths) + [0] * (W * H - len(lengths))
+    _check(starnt, oracle_mod, _lists(rng, full), W, H, max_n)
+
+
 @pytest.mark.parametrize("seed", [0, 1])
 def test_exact_small_batches_around_their_capacity(starnt, gpu, oracle_mod, seed):
     """Declared maximum 192: batches of at most 192 fragments. Lists at and

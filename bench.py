@@ -113,6 +113,24 @@ def counters_traffic(path, src_hash):
     return rec.get("bytes_per_launch")
 
 
+def exact_launches_of_frame(con, pat, pixels):
+    """Positions, among a kernel trace's launches whose name contains `pat`
+    (in dispatch order), of those sized for a frame of `pixels` pixels: the
+    exact wave kernel runs one 64-lane workgroup per 16 pixels, and the trace
+    gives the grid in work-items or in workgroups."""
+    cols = [c[1] for c in con.execute("pragma table_info(kernels)")]
+    gcol = next((c for c in ("grid_size_x", "grid_x", "grid_size") if c in cols), None)
+    if gcol is None:
+        raise SystemExit("no grid-size column in the trace's kernels view: %s" % cols)
+    grids = [g for (g,) in con.execute("select %s from kernels where name like ? order by dispatch_id" % gcol,
+                                        ("%" + pat + "%",)).fetchall()]
+    groups = (pixels + 15) // 16
+    pick = [j for j, g in enumerate(grids) if g in (groups, groups * 64)]
+    if not pick:
+        raise SystemExit("no exact launch of a %d-pixel frame in the trace (grids %s)" % (pixels, sorted(set(grids))))
+    return pick
+
+
 def profile_summary(d, calib_mb):
     """Summarise the three profiled runs of this bench (PROFILE_COMMANDS: kernel
     trace, FETCH_SIZE pass, WRITE_SIZE pass; each run's JSON line saved as
@@ -269,18 +287,8 @@ def profile_summary(d, calib_mb):
             pick = [j for j, (_, st0, _) in enumerate(tr_rows) if t0 <= st0 < t1]
         else:
             # the 1080p frames only (the training scenes' 480x270 frames use
-            # the same variant), picked by the launch's grid: one 64-lane
-            # workgroup per 16 pixels
-            cols = [c[1] for c in con.execute("pragma table_info(kernels)")]
-            gcol = next((c for c in ("grid_size_x", "grid_x", "grid_size") if c in cols), None)
-            if gcol is None:
-                raise SystemExit("no grid-size column in the trace's kernels view: %s" % cols)
-            grids = [g for (g,) in con.execute("select %s from kernels where name like ? order by dispatch_id" % gcol,
-                                                ("%" + pat + "%",)).fetchall()]
-            full = {P1080 // 16, P1080 // 16 * 64}
-            pick = [j for j, g in enumerate(grids) if g in full]
-            if not pick:
-                raise SystemExit("no 1080p exact launch in the trace (grids %s)" % sorted(set(grids)))
+            # the same variant)
+            pick = exact_launches_of_frame(con, pat, P1080)
         dur = float(np.mean([tr_rows[j][2] for j in pick])) / 1e3
         fv = [v for _, k, v in kernel_counters("fetch", "FETCH_SIZE") if pat in k]
         wv = [v for _, k, v in kernel_counters("write", "WRITE_SIZE") if pat in k]

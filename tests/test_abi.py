@@ -167,3 +167,10 @@ def test_product_package_has_no_cpu_fallback():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "oracle.c" not in txt, f
+
+
+def test_time_next_launch_request_without_events(starnt):
+    """A request with no events is accepted and clears any pending one; it
+    touches no GPU state, so it runs without a device."""
+    starnt.starnt_time_next_launch(None, None)
+    assert starnt.lib.starnt_time_next_launch(None, None) == 0  # STARNT_OK

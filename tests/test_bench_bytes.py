@@ -52,3 +52,35 @@ def test_fragment_pass_bytes_one_pass3_sample(bench):
 def test_inference_bytes(bench):
     # 32 B per pixel, 16 per pass-2 sample, 32 per pass-3 record
     assert bench.infer_pass_bytes(2, 1, (2, 1, 1, 1)) == 32 * 2 + 16 * 2 + 32
+
+
+def _trace(rows, col="grid_size_x"):
+    """An in-memory kernel trace: rows of (dispatch_id, name, grid)."""
+    import sqlite3
+    con = sqlite3.connect(":memory:")
+    con.execute("create table kernels (dispatch_id integer, name text, start integer, duration integer, %s integer)"
+                % col)
+    con.executemany("insert into kernels values (?, ?, 0, 0, ?)", rows)
+    return con
+
+
+def test_exact_launches_picked_by_frame_size(bench):
+    """The profile summary averages the exact kernel over the 1080p frames
+    only: launches of the same variant on smaller frames (the training
+    scenes) and of other variants are left out, whichever unit the trace
+    gives the grid in."""
+    pat = "WaveCfg<192, 16>, false, false>"
+    name = "void starnt::exact_wave_kernel<starnt::WaveCfg<192, 16>, false, false>(starnt::ExactArgs)"
+    other = "void starnt::exact_wave_kernel<starnt::WaveCfg<192, 16>, false, true>(starnt::ExactArgs)"
+    P = 1920 * 1080
+    small = 480 * 270
+    rows = [(1, name, small // 16 * 64), (2, other, P // 16 * 64), (3, name, P // 16 * 64),
+            (4, name, small // 16 * 64), (5, name, P // 16 * 64)]
+    # positions among the variant's own launches in dispatch order: 0, 1, 2, 3
+    assert bench.exact_launches_of_frame(_trace(rows), pat, P) == [1, 3]
+    wg = [(d, n, g // 64) for d, n, g in rows]
+    assert bench.exact_launches_of_frame(_trace(wg, "grid_x"), pat, P) == [1, 3]
+    with pytest.raises(SystemExit):
+        bench.exact_launches_of_frame(_trace(rows), pat, 2560 * 1440)
+    with pytest.raises(SystemExit):
+        bench.exact_launches_of_frame(_trace(rows, "workgroups"), pat, P)

@@ -45,7 +45,8 @@ namespace {
 // batches of at most CAP fragments. The launch takes the smallest CAP that
 // holds the declared maximum list length: small batches keep LDS and
 // registers low (more waves per CU hide more latency), larger ones keep
-// longer lists out of the much slower long-list kernel. Measured per frame:
+// longer lists out of the much slower long-list kernel. Measured per frame
+// when the configurations were chosen (the kernel has since become faster):
 // 1080p (mean 8, max 64) 126 us at <192, 16> against 142 us at <192, 32>;
 // 4K (mean 16, max 256) 1.71 ms at <256, 16>, 1.98 ms at <384, 16> and 3.4
 // ms at <384, 48>; 16-pixel waves were also faster than 8, 12, 20 or 24.

@@ -66,13 +66,16 @@ def test_exact_lists_around_the_batch_capacity(starnt, gpu, oracle_mod, seed):
     _check(starnt, oracle_mod, _lists(rng, lengths), W, H, 1024)
 
 
-@pytest.mark.parametrize("max_n,lengths", [
+SPANNING = [
     (192, (10, 130, 52)),          # list 1 covers slots 64..127: no list starts there
     (192, (0, 60, 0, 8, 0, 120)),  # empty lists before, between and after; starts at 60 and 68
     (192, (1, 1, 190)),            # one list over all three blocks of 64 slots
     (384, (5, 300, 70, 9)),        # blocks 1..4 hold no start
     (384, (63, 1, 64, 1, 255)),    # starts at 63, 64, 128 and 129
-])
+]
+
+
+@pytest.mark.parametrize("max_n,lengths", SPANNING)
 def test_exact_lists_spanning_slot_blocks(starnt, gpu, oracle_mod, max_n, lengths):
     """Every fragment takes its list from a prefix maximum over the batch's
     slots, 64 slots at a time: lists that start right at and right after a
@@ -83,6 +86,24 @@ def test_exact_lists_spanning_slot_blocks(starnt, gpu, oracle_mod, max_n, length
     W, H = 16, 1
     full = list(lengths) + [0] * (W * H - len(lengths))
     _check(starnt, oracle_mod, _lists(rng, full), W, H, max_n)
+
+
+@pytest.mark.parametrize("max_n,lengths", SPANNING)
+def test_exact_lists_spanning_slot_blocks_half_with_ties(starnt, gpu, oracle_mod, max_n, lengths):
+    """The same batches with FP16 RGBA and many equal depths in every list:
+    the recount on (depth, primitive id) takes each fragment's list from the
+    same prefix maximum."""
+    rng = np.random.default_rng(100 + sum(lengths))
+    W, H = 16, 1
+    full = list(lengths) + [0] * (W * H - len(lengths))
+    off, dep, rgba, prim = make_csr(_lists(rng, full, ties_every=4), W, H)
+    h = rgba.astype(np.float16)
+    df = starnt.DeviceFrags(off, dep, h, prim, W, H, max_n)
+    bg = (0.5, 0.25, 0.75)
+    rgb, fstar = run_exact(starnt, df, bg=bg)
+    o = oracle_mod.frame(off, dep, h.astype(np.float32), prim, W, H, bg=bg)
+    assert np.abs(rgb - o["rgb"]).max() <= TOL
+    assert np.abs(fstar - o["fstar"]).max() <= TOL
 
 
 @pytest.mark.parametrize("seed", [0, 1])

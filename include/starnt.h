@@ -462,8 +462,9 @@ int starnt_check(uint32_t err_word);
  * elapsed time is the kernel's own duration, without the dispatch gaps of
  * events recorded around the call. Both are hipEvent_t created (and recorded
  * once) by the caller with timing enabled; either may be NULL. The request
- * holds for that one launch and is then cleared; both NULL clears it. Never
- * fails. */
+ * holds for that one launch and is then cleared; both NULL clears it. Meant
+ * for eager launches: leave no request pending while capturing a HIP graph.
+ * Never fails. */
 int starnt_time_next_launch(void* start_event, void* stop_event);
 
 /* message of the calling thread's last failure ("" if none) */
